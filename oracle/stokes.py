@@ -1,0 +1,115 @@
+"""Stokes LDG saddle-point operator (oracle; test infrastructure).
+
+Section 3.1 ("LDG schemes") and eq:components: unknowns (u_1..u_d, p), and
+
+    [ A_ij        -G_i^T M ]        A_ij = delta_ij (sum_k G_k^T M_mu G_k)
+    [ -M G_j      -E_p     ]               + gamma G_j^T M_mu G_i + delta_ij E
+
+with G the (viscosity-upwinded) discrete gradient of the scalar problem, M the
+plain block-diagonal mass, M_mu the viscosity-weighted mass, E the scalar
+velocity penalty and E_p a pressure-only penalty.  gamma = 0 standard form,
+gamma = 1 stress form.  Velocity Dirichlet boundary conditions use the same
+one-sided gradient as the scalar problem (its divergence is the same G).
+
+Pressure penalty (parity unpinned in absolute terms: the paper takes its
+constants from an earlier work): E_p = sum over interior faces of
+c_p * h / max(mu_L, mu_R) * int_F [p][q]; this has the h^d / mu scaling the
+paper states in Section 3.3.
+
+Per element the unknowns are ordered [u_1 (bs_s), .., u_d (bs_s), p (bs_s)]
+with bs_s = (p+1)^d, so the element block has (d+1) bs_s unknowns
+(Section 3.2: a block is velocity and pressure together).
+"""
+from __future__ import annotations
+
+from typing import List
+
+import numpy as np
+import scipy.sparse as sp
+
+from .ldg import (Grid, ElementMatrices, assemble_gradient, assemble_penalty,
+                  block_diag, to_bsr)
+from .hierarchy import Level, level_sizes, injection, coarsen_factors
+
+
+def _perm_comp_to_elem(ne: int, bss: int, ncomp: int) -> np.ndarray:
+    """perm[i_elem_major] = index in component-major ordering."""
+    e = np.arange(ne)[:, None, None]
+    c = np.arange(ncomp)[None, :, None]
+    a = np.arange(bss)[None, None, :]
+    return (c * ne * bss + e * bss + a).reshape(-1)
+
+
+def stokes_matrix(G, Mmu, M, E, Ep, gamma: int, ne: int, bss: int):
+    """Assemble the element-major saddle-point matrix from scalar factors."""
+    d = len(G)
+    Gc = [g.tocsr() for g in G]
+    Mmu = Mmu.tocsr()
+    M = M.tocsr()
+    lap = E.tocsr()
+    for k in range(d):
+        lap = lap + Gc[k].T @ Mmu @ Gc[k]
+    rows = []
+    for i in range(d):
+        row = []
+        for j in range(d):
+            blk = lap if i == j else sp.csr_matrix(lap.shape)
+            if gamma:
+                blk = blk + gamma * (Gc[j].T @ Mmu @ Gc[i])
+            row.append(blk)
+        row.append(-(Gc[i].T @ M))
+        rows.append(row)
+    rows.append([-(M @ Gc[j]) for j in range(d)] + [-Ep.tocsr()])
+    K = sp.bmat(rows, format="csr")
+    perm = _perm_comp_to_elem(ne, bss, d + 1)
+    K = K[perm][:, perm]
+    return to_bsr(K, (d + 1) * bss)
+
+
+def pressure_penalty(grid: Grid, em: ElementMatrices, mu, cp: float):
+    return assemble_penalty(grid, em, mu, 0.0,
+                            interior_tau=lambda ml, mr: cp * grid.h / max(ml, mr),
+                            dirichlet=False)
+
+
+def stokes_levels(dim: int, n: int, p: int, mu=None, bc=None, gamma: int = 1,
+                  basis: str = "legendre", tau0: float = 1.0, cp: float = 1.0) -> List[Level]:
+    grid = Grid(dim, n, bc)
+    em = ElementMatrices(dim, p, grid.h, basis)
+    mu = np.ones(grid.ne) if mu is None else np.asarray(mu, dtype=np.float64)
+    G = assemble_gradient(grid, em, mu)
+    Mmu = block_diag(grid, [mu[e] * em.M for e in range(grid.ne)])
+    M = block_diag(grid, [em.M] * grid.ne)
+    E = assemble_penalty(grid, em, mu, tau0)
+    Ep = pressure_penalty(grid, em, mu, cp)
+    ncomp = dim + 1
+    A = stokes_matrix(G, Mmu, M, E, Ep, gamma, grid.ne, em.bs)
+    lv = Level(grid, em, G, Mmu, M, E, Ep, A, ncomp * em.bs, "stokes", gamma, None, ncomp)
+    levels = [lv]
+    for _ in level_sizes(n)[1:]:
+        cg, cem, Gc, Mmuc, Mc, Ec, Epc = coarsen_factors(levels[-1])
+        Ac = stokes_matrix(Gc, Mmuc, Mc, Ec, Epc, gamma, cg.ne, cem.bs)
+        levels[-1].I = injection(levels[-1].grid, levels[-1].em, ncomp)
+        levels.append(Level(cg, cem, Gc, Mmuc, Mc, Ec, Epc, Ac, ncomp * cem.bs,
+                            "stokes", gamma, None, ncomp))
+    return levels
+
+
+def pressure_kernel(level: Level) -> np.ndarray:
+    """Coefficient vector of (u = 0, p = 1): the kernel of the velocity-Dirichlet
+    operator.  The constant's coefficients are m^-1 int psi_i per dimension."""
+    ref = level.em.ref
+    c1 = np.linalg.solve(ref.mass, _ones_moments(ref))
+    from .basis import kron_dims
+    cp = kron_dims([c1[:, None]] * level.grid.dim)[:, 0]
+    bss = level.em.bs
+    d = level.grid.dim
+    k = np.zeros((level.grid.ne, (d + 1) * bss))
+    k[:, d * bss:] = cp
+    return k.reshape(-1)
+
+
+def _ones_moments(ref):
+    from .basis import gauss_legendre
+    t, w = gauss_legendre(ref.p + 2)
+    return ref.basis.eval(t) @ w

@@ -1,0 +1,145 @@
+"""Pins of the oracle's LDG discretisation (Section 2.1; Section 3.1)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from ldg_inputs import sample_on_elements, mms_source_2d, mms_solution_2d, mu_box
+from oracle import ldg, hierarchy, stokes
+from oracle.basis import kron_dims
+
+
+def _solve(A, b):
+    return spla.spsolve(A.tocsc(), b)
+
+
+@pytest.mark.parametrize("basis", ["legendre", "gl_nodal"])
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_polynomial_reproduction_dirichlet(basis, dim, p):
+    """u in Q_p globally with u = g on the boundary and f = -Lap u exactly
+    integrated is reproduced exactly (G u = grad u, no jumps)."""
+    n = 3
+    op = ldg.assemble_scalar(dim, n, p, basis=basis)
+    if dim == 2:
+        u = lambda x, y: x ** p * y + 0.5 * y ** p - x + 1.0
+        f = lambda x, y: -(p * (p - 1) * x ** max(p - 2, 0) * y
+                           + 0.5 * p * (p - 1) * y ** max(p - 2, 0))
+    else:
+        u = lambda x, y, z: x ** p * y * z + z - 2 * y
+        f = lambda x, y, z: -(p * (p - 1) * x ** max(p - 2, 0) * y * z)
+    nq = p + 3
+    b = ldg.rhs(op, f_qp=sample_on_elements(dim, n, nq, f), nq=nq, g=u)
+    x = _solve(op.A, b)
+    vals, _ = ldg.evaluate(op, x, nq)
+    assert np.abs(vals - sample_on_elements(dim, n, nq, u)).max() < 1e-11
+
+
+def test_polynomial_reproduction_neumann_mixed():
+    """Dirichlet on x faces, Neumann (flux data) on y faces."""
+    dim, p, n = 2, 2, 4
+    op = ldg.assemble_scalar(dim, n, p, bc=["D", "D", "N", "N"])
+    u = lambda x, y: x * x - y * y + 3 * x * y + 0.25
+    f = lambda x, y: 0.0 * x
+    # outward flux mu du/dn on y = 0 (n = -y) and y = 1 (n = +y)
+    hflux = lambda x, y: np.where(y < 0.5, -(-2 * y + 3 * x), (-2 * y + 3 * x))
+    b = ldg.rhs(op, f_qp=sample_on_elements(dim, n, 5, f), nq=5, g=u, hflux=hflux)
+    x = _solve(op.A, b)
+    vals, _ = ldg.evaluate(op, x, 5)
+    assert np.abs(vals - sample_on_elements(dim, n, 5, u)).max() < 1e-11
+
+
+@pytest.mark.parametrize("ratio", [1e-4, 1e4])
+def test_polynomial_reproduction_planar_interface(ratio):
+    """Face-aligned interface x = 1/2: u piecewise linear in x with
+    mu u' continuous is reproduced exactly for any viscosity ratio."""
+    dim, p, n = 2, 2, 4
+    grid_mu = np.array([ratio if (e % n) < n // 2 else 1.0 for e in range(n * n)])
+    op = ldg.assemble_scalar(dim, n, p, mu=grid_mu)
+    s_left = 1.0 / ratio                          # mu u' = 1 on both sides
+    u = lambda x, y: np.where(x < 0.5, s_left * x, s_left * 0.5 + (x - 0.5)) + 0.0 * y
+    f = lambda x, y: 0.0 * x
+    b = ldg.rhs(op, f_qp=sample_on_elements(dim, n, 5, f), nq=5, g=u)
+    x = _solve(op.A, b)
+    vals, _ = ldg.evaluate(op, x, 5)
+    ex = sample_on_elements(dim, n, 5, u)
+    assert np.abs(vals - ex).max() < 1e-10 * max(1.0, np.abs(ex).max())
+
+
+def test_mms_convergence_order_p2():
+    """Config-1 manufactured solution sin(2 pi x) sin(3 pi y): the L2 error
+    decays at order p + 1 = 3 (Section 2.1, last bullet)."""
+    p, nq = 2, 6
+    errs = []
+    for n in (8, 16, 32):
+        op = ldg.assemble_scalar(2, n, p, basis="gl_nodal")
+        b = ldg.rhs(op, f_qp=sample_on_elements(2, n, nq, mms_source_2d), nq=nq)
+        x = _solve(op.A, b)
+        vals, W = ldg.evaluate(op, x, nq)
+        ex = sample_on_elements(2, n, nq, mms_solution_2d)
+        errs.append(math.sqrt(np.sum((vals - ex) ** 2 * W[None, :])))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(2.7 < r < 3.4 for r in rates), rates
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 2, 1), (2, 3, 2), (2, 4, 3), (3, 2, 1), (3, 3, 2)])
+def test_symmetric_definite_dirichlet(dim, n, p):
+    A = ldg.assemble_scalar(dim, n, p).A.toarray()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    assert np.linalg.eigvalsh(A).min() > 0
+
+
+@pytest.mark.parametrize("bc", ["P", "N"])
+def test_semidefinite_kernel_is_constant(bc):
+    dim, n, p = 2, 4, 2
+    op = ldg.assemble_scalar(dim, n, p, bc=[bc] * 4)
+    A = op.A.toarray()
+    lam, Q = np.linalg.eigh(A)
+    assert abs(lam[0]) < 1e-12 * lam[-1] and lam[1] > 1e-8 * lam[-1]
+    # constant function in the Legendre basis: only the (0,0) mode, equal on all elements
+    v = Q[:, 0].reshape(op.grid.ne, -1)
+    v = v / v[0, 0]
+    assert np.allclose(v[:, 0], 1.0, atol=1e-10) and np.abs(v[:, 1:]).max() < 1e-10
+
+
+def test_stokes_inertia_velocity_dirichlet():
+    """Saddle point with velocity Dirichlet: n_u positive, n_p - 1 negative and
+    one zero eigenvalue (constant pressure)."""
+    dim, n, p = 2, 3, 1
+    lv = stokes.stokes_levels(dim, n, p, gamma=1, cp=0.1)
+    A = lv[0].A.toarray()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    lam = np.linalg.eigvalsh(A)
+    tol = 1e-10 * np.abs(lam).max()
+    nbs = (p + 1) ** dim
+    n_u, n_p = dim * nbs * n ** dim, nbs * n ** dim
+    assert (lam > tol).sum() == n_u
+    assert (lam < -tol).sum() == n_p - 1
+    assert (np.abs(lam) <= tol).sum() == 1
+    k = stokes.pressure_kernel(lv[0])
+    assert np.abs(A @ k).max() < 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("system", ["poisson", "stokes"])
+def test_factor_coarsening_equals_rediscretisation(system):
+    """Constant viscosity: the factor-coarsened A_2h equals A assembled directly
+    on the n/2 grid (Section 2.2: the two approaches are equivalent)."""
+    dim, n, p = 2, 8, 2
+    if system == "poisson":
+        lv = hierarchy.scalar_levels(dim, n, p)
+        direct = ldg.assemble_scalar(dim, n // 2, p).A
+    else:
+        lv = stokes.stokes_levels(dim, n, p, gamma=1, cp=0.1)
+        direct = stokes.stokes_levels(dim, n // 2, p, gamma=1, cp=0.1)[0].A
+    diff = (lv[1].A - direct).toarray()
+    assert np.abs(diff).max() <= 1e-12 * np.abs(direct.toarray()).max()
+
+
+def test_transfer_identities():
+    """I^T M^h I = M^2h and restriction-of-injection = identity."""
+    lv = hierarchy.scalar_levels(2, 8, 3)
+    I = lv[0].I.tocsr()
+    Mh, M2h = lv[0].M.tocsr(), lv[1].M.tocsr()
+    assert np.abs((I.T @ Mh @ I - M2h).toarray()).max() < 1e-14
+    R = np.linalg.inv(M2h.toarray()) @ (I.T @ Mh).toarray()
+    assert np.allclose(R @ I.toarray(), np.eye(M2h.shape[0]), atol=1e-12)

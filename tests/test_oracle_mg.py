@@ -1,0 +1,233 @@
+"""Pins of the oracle's smoothers, V-cycle and Krylov solvers (Sections 2.2-2.4,
+3.3, tab:sizes)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from ldg_inputs import rhs_normal, rhs_uniform, mu_box, stokes_body_force
+from oracle import hierarchy, stokes, smoothers as sm, vcycle, krylov, solver, ldg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tab_sizes():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "tab_sizes.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        rows.append((t[0], None if t[1] == "-" else int(t[1]), int(t[2]),
+                     [int(v) for v in t[3:9]], [int(v) for v in t[9:12]]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _tab_sizes(), ids=lambda r: f"{r[0]}{r[1]}-{r[2]}d")
+def test_stencil_sizes_reproduce_tab_sizes(row):
+    """Block pattern of A^l around an interior element reproduces tab:sizes
+    (m = |A^{l+1}|, n = |A^l|, cost = |A| + |A^l|)."""
+    system, gamma, dim, mn, cost = row
+    n = 8
+    if system == "poisson":
+        A = ldg.assemble_scalar(dim, n, 1, bc=["P"] * (2 * dim)).A
+        bs = 2 ** dim
+    else:
+        A = stokes.stokes_levels(dim, n, 1, bc=["P"] * (2 * dim), gamma=gamma)[0].A
+        bs = (dim + 1) * 2 ** dim
+    P = sm.block_pattern(A, bs)
+    centre = sum((n // 2) * n ** k for k in range(dim))
+    sizes = [sm.pattern_power(P, l)[centre].nnz for l in range(4)]
+    for l in range(3):
+        assert (sizes[l + 1], sizes[l]) == (mn[2 * l], mn[2 * l + 1])
+        assert sizes[1] + sizes[l] == cost[l]
+
+
+def _small_scalar(dim=2, n=4, p=2, mu=None):
+    return hierarchy.scalar_levels(dim, n, p, mu=mu)
+
+
+def test_sai_normal_equations_and_sai0_closed_form():
+    lv = _small_scalar()
+    A = lv[0].A
+    bs = lv[0].bs
+    alpha = sm.balance_scalar(A, bs)
+    At = (sp.diags(alpha) @ A.tocsr() @ sp.diags(alpha)).toarray()
+    # balanced diagonal blocks have unit Frobenius norm (Section 2.3.3)
+    for i in range(lv[0].grid.ne):
+        assert abs(np.linalg.norm(At[i * bs:(i + 1) * bs, i * bs:(i + 1) * bs]) - 1) < 1e-13
+    for ell in (0, 1):
+        B, _ = sm.sai(A, bs, ell, alpha)
+        Bt = np.diag(1 / alpha) @ B.toarray() @ np.diag(1 / alpha)
+        Pl = sm.pattern_power(sm.block_pattern(A, bs), ell).toarray() > 0
+        for i in range(lv[0].grid.ne):
+            J = np.where(Pl[:, i])[0]
+            cols = np.concatenate([np.arange(j * bs, (j + 1) * bs) for j in J])
+            X = Bt[cols, i * bs:(i + 1) * bs]
+            E = np.zeros((At.shape[0], bs))
+            E[i * bs:(i + 1) * bs] = np.eye(bs)
+            # normal equations of the local least squares problem
+            res = At[:, cols].T @ (At[:, cols] @ X - E)
+            assert np.abs(res).max() < 1e-10
+            if ell == 0:
+                C = At[:, i * bs:(i + 1) * bs]
+                ref = np.linalg.solve(C.T @ C, C[i * bs:(i + 1) * bs].T)
+                assert np.allclose(X, ref, atol=1e-10)
+
+
+def test_sai_full_pattern_is_inverse():
+    """When the pattern of A^l covers the whole grid, B = A^{-1}."""
+    lv = _small_scalar(n=2, p=1)
+    A = lv[0].A
+    B, _ = sm.sai(A, lv[0].bs, 2, sm.balance_scalar(A, lv[0].bs))
+    assert np.allclose(B.toarray() @ A.toarray(), np.eye(A.shape[0]), atol=1e-10)
+
+
+def test_sai_cache_is_exact():
+    lv = _small_scalar(n=8, p=1)
+    A = lv[0].A
+    a = sm.balance_scalar(A, lv[0].bs)
+    B1, nu = sm.sai(A, lv[0].bs, 1, a, use_cache=True)
+    B2, _ = sm.sai(A, lv[0].bs, 1, a, use_cache=False)
+    assert nu < lv[0].grid.ne
+    assert np.abs((B1 - B2).toarray()).max() == 0.0
+
+
+def test_stokes_balancing_norms():
+    """Section 3.3: scaled diagonal block has norms 1 (viscous), zeta (both
+    off-diagonal sub-blocks)."""
+    zeta = 0.131
+    lv = stokes.stokes_levels(2, 4, 2, gamma=1, cp=0.1)
+    A, bs = lv[0].A, lv[0].bs
+    a = sm.balance_stokes(A, bs, 2, zeta)
+    At = (sp.diags(a) @ A.tocsr() @ sp.diags(a)).toarray()
+    nv = 2 * 9
+    for i in range(lv[0].grid.ne):
+        D = At[i * bs:(i + 1) * bs, i * bs:(i + 1) * bs]
+        assert abs(np.linalg.norm(D[:nv, :nv]) - 1) < 1e-12
+        assert abs(np.linalg.norm(D[nv:, :nv]) - zeta) < 1e-12
+        assert abs(np.linalg.norm(D[:nv, nv:]) - zeta) < 1e-12
+
+
+def test_colouring_valid_and_red_black():
+    lv = _small_scalar(n=6, p=1)
+    P = sm.block_pattern(lv[0].A, lv[0].bs)
+    c = sm.greedy_colours(P)
+    Pc = P.tocoo()
+    assert all(c[i] != c[j] for i, j in zip(Pc.row, Pc.col) if i != j)
+    assert c.max() == 1
+    idx = np.arange(36)
+    assert np.array_equal(c, ((idx % 6) + (idx // 6)) % 2)
+
+
+@pytest.mark.parametrize("smoother,order", [("jacobi", "OI"), ("sai", "OI"), ("sai", "IO"),
+                                            ("gs", "OI")])
+def test_vcycle_symmetric_positive(smoother, order):
+    """Jacobi, GS with reversed post-sweeps and SAI OI/IO give a symmetric
+    positive definite V (Section 2.4), checked on the dense matrix of V."""
+    lv = _small_scalar(n=4, p=1)
+    vc = vcycle.build_mg(lv, smoother, 1, order)
+    V = vc.matrix()
+    assert np.abs(V - V.T).max() < 1e-11 * np.abs(V).max()
+    assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+
+
+def test_vcycle_oo_not_symmetric():
+    lv = _small_scalar(n=4, p=1)
+    V = vcycle.build_mg(lv, "sai", 1, "OO").matrix()
+    assert np.abs(V - V.T).max() > 1e-6 * np.abs(V).max()
+
+
+def test_krylov_match_direct_solve():
+    rng = np.random.default_rng(3)
+    n = 40
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    x = np.linalg.solve(A, b)
+    r = krylov.pcg(A, b, lambda v: v, rtol=1e-13, maxit=200)
+    assert np.allclose(r.x, x, rtol=1e-11, atol=1e-12)
+    N = A + 0.3 * rng.standard_normal((n, n))
+    r2 = krylov.gmres_left(N, b, lambda v: v, rtol=1e-13, maxit=n)
+    assert np.allclose(r2.x, np.linalg.solve(N, b), rtol=1e-10, atol=1e-11)
+
+
+def test_eta_estimator():
+    rho = 0.1 ** (1 / 0.7)
+    hist = [3.0 * rho ** k for k in range(8)]
+    assert abs(krylov.eta_from_history(hist) - 0.7) < 1e-12
+
+
+def test_vcycle_cg_matches_direct_solve():
+    lv, vc = solver.build(2, 8, 2)
+    b = rhs_normal(lv[0].A.shape[0], 7)
+    r = solver.solve(lv, vc, b)
+    x = sp.linalg.spsolve(lv[0].A.tocsc(), b)
+    assert r.converged and r.rel_res_true < 2e-10
+    assert np.linalg.norm(r.x - x) / np.linalg.norm(x) < 1e-9
+
+
+def test_headline_textbook_behaviour_poisson():
+    """SAI_1 OI CG: small, grid-independent iteration counts (Section 2.4
+    observation (vi)); Jacobi is not 'slow' (eta < 2)."""
+    its = []
+    for n in (8, 16, 32):
+        lv, vc = solver.build(2, n, 2)
+        b = rhs_uniform(lv[0].A.shape[0], 11)
+        r = solver.solve(lv, vc, b)
+        its.append(r.iters)
+        assert r.converged and r.eta < 1.0
+    assert max(its) - min(its) <= 1 and max(its) <= 10
+    lv, vc = solver.build(2, 16, 2, smoother="jacobi")
+    r = solver.solve(lv, vc, rhs_uniform(lv[0].A.shape[0], 11))
+    assert r.eta < 2.0
+
+
+def test_orderings_and_levels():
+    """IO worse than OI; SAI_0 slower than Jacobi; SAI_2 faster than SAI_1
+    (Section 2.4 observations, Section 4)."""
+    lv = hierarchy.scalar_levels(2, 16, 2)
+    b = rhs_uniform(lv[0].A.shape[0], 5)
+    A = lv[0].A.tocsr()
+
+    def eta(**kw):
+        vc = vcycle.build_mg(lv, **kw)
+        return krylov.pcg(A, b, vc.apply).eta
+
+    e_oi = eta(smoother="sai", sai_level=1, order="OI")
+    e_io = eta(smoother="sai", sai_level=1, order="IO")
+    e_s0 = eta(smoother="sai", sai_level=0, order="OI")
+    e_s2 = eta(smoother="sai", sai_level=2, order="OI")
+    e_j = eta(smoother="jacobi")
+    assert e_io > e_oi
+    assert e_s0 > e_j
+    assert e_s2 < e_oi
+
+
+@pytest.mark.slow
+def test_contrast_insensitivity_box_inclusion():
+    """Section 2.4.3: inner box (1/4,3/4)^2 with viscosity ratio 1e4 or 1e-4:
+    eta stays close to the single-phase value."""
+    n, p = 16, 2
+    etas = {}
+    for ratio in (1.0, 1e4, 1e-4):
+        lv, vc = solver.build(2, n, p, mu=mu_box(2, n, ratio))
+        r = solver.solve(lv, vc, rhs_uniform(lv[0].A.shape[0], 2))
+        etas[ratio] = r.eta
+    assert etas[1e4] < 1.5 * etas[1.0] and etas[1e-4] < 1.5 * etas[1.0]
+
+
+@pytest.mark.slow
+def test_stokes_sai_beats_gs_loose():
+    """Section 3.4.2 (stress form, d = p = 2): GMRES with SAI_1 OI converges
+    faster than GMRES with coloured GS OO; SAI_1 IO is the worst."""
+    n, p = 8, 2
+    b = stokes_body_force(2, n, 9, 0)
+    etas = {}
+    for sm_, order in (("sai", "OI"), ("gs", "OO"), ("sai", "IO")):
+        lv, vc = solver.build(2, n, p, system="stokes", gamma=1, smoother=sm_, order=order)
+        r = solver.solve(lv, vc, b, "gmres")
+        assert r.converged
+        etas[sm_ + order] = r.eta
+    assert etas["saiOI"] < etas["gsOO"] < etas["saiIO"]
+    assert etas["saiOI"] < 1.0
