@@ -1,0 +1,198 @@
+/* ldgmg.h -- C-ABI of the MI355X multigrid library for high-order LDG systems.
+ *
+ * The library solves A_h x_h = b_h, the linear system of a local discontinuous
+ * Galerkin (LDG) discretisation on a uniform n^d Cartesian grid of the unit box
+ * (paper: Saye, "A comparative study of efficient multigrid solvers for
+ * high-order local discontinuous Galerkin methods", arXiv:2412.12506):
+ *   - scalar elliptic (interface) problems, Section 2.1:
+ *       A = sum_k G_k^T M_mu G_k + E;
+ *   - Stokes saddle-point problems, Section 3.1, eq:components.
+ * with the multigrid V-cycle of Algorithm 1 (block Jacobi, multi-coloured
+ * block Gauss-Seidel or balanced block SAI smoothers, Section 2.3 and 3.3) as
+ * the preconditioner of CG or left-preconditioned GMRES (Section 2.2).
+ *
+ * Conventions shared by every entry point
+ *   - Elements are numbered lexicographically with x fastest:
+ *       e = ix + n*iy + n*n*iz.
+ *   - Vectors are element-major: v[e*bs + a].  Inside an element the scalar
+ *     coefficients are ordered with the x-degree fastest; Stokes elements hold
+ *     [u_1 .. u_d, p], each a block of (p+1)^d coefficients, so bs = (d+1)(p+1)^d.
+ *   - "dev" pointers are device (HIP) memory owned by the caller; "host"
+ *     pointers are host memory owned by the caller.  The library never keeps a
+ *     caller pointer after a call returns.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Work is enqueued on that stream; calls that must return host values
+ *     (ldgmg_solve) synchronise that stream only.
+ *   - Every function returns an int status (LDGMG_OK = 0, negative on error)
+ *     and never throws across the ABI; ldgmg_last_error() gives a message
+ *     (per calling thread).
+ *   - A handle is not safe for concurrent use: calls on one handle must be
+ *     serialised by the caller (they share the handle's device workspace).
+ */
+#ifndef LDGMG_H
+#define LDGMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LDGMG_OK = 0,
+  LDGMG_EINVAL = -1,    /* invalid argument (shape, option, NaN/Inf input)    */
+  LDGMG_ENOMEM = -2,    /* over the HBM budget or device allocation failed    */
+  LDGMG_EHIP = -3,      /* HIP runtime error                                  */
+  LDGMG_ENOCONV = -4,   /* maxit reached; the info struct is still filled     */
+  LDGMG_ESINGULAR = -5, /* rank-deficient local problem in the setup          */
+  LDGMG_ESTATE = -6     /* call not valid in the handle's state (e.g. no device data) */
+};
+
+enum { LDGMG_POISSON = 0, LDGMG_STOKES = 1 };
+enum { LDGMG_BASIS_LEGENDRE = 0, LDGMG_BASIS_GL_NODAL = 1 };
+enum { LDGMG_BC_DIRICHLET = 0, LDGMG_BC_NEUMANN = 1, LDGMG_BC_PERIODIC = 2 };
+enum { LDGMG_SMOOTH_JACOBI = 0, LDGMG_SMOOTH_GS = 1, LDGMG_SMOOTH_SAI = 2 };
+/* pre/post ordering (Section 2.4): first letter pre-smoother, second post;
+ * O = forward (eq:B1 / colours in order), I = reverse (eq:BT / colours reversed) */
+enum { LDGMG_ORDER_OO = 0, LDGMG_ORDER_OI = 1, LDGMG_ORDER_IO = 2, LDGMG_ORDER_II = 3 };
+/* precision of the V-cycle's matrices, vectors and smoothers; the outer Krylov
+ * iteration, its operator and inner products are always FP64 */
+enum { LDGMG_FP64 = 0, LDGMG_FP32 = 1 };
+enum { LDGMG_CG = 0, LDGMG_GMRES = 1 };
+
+typedef struct ldgmg_hier* ldgmg_handle;
+
+/* Problem statement (Section 2.1 / 3.1) and solver options (Section 2.2-2.4). */
+typedef struct {
+  int dim;            /* 2 or 3                                                   */
+  int n;              /* elements per side; the grid is n^dim on (0,1)^dim        */
+  int p;              /* polynomial degree, 1..5 (Q_p tensor-product space)       */
+  int basis;          /* LDGMG_BASIS_*                                            */
+  int system;         /* LDGMG_POISSON (scalar / interface) | LDGMG_STOKES        */
+  int gamma;          /* Stokes form: 0 standard, 1 stress                        */
+  int bc[6];          /* per box face (x-, x+, y-, y+, z-, z+): LDGMG_BC_*        */
+  const double* mu;   /* host, n^dim per-element viscosities; NULL means all 1.
+                         Read during setup only.                                  */
+  double tau0;        /* velocity / scalar penalty: tau_F = tau0 mu_F / h         */
+  double cp;          /* Stokes pressure penalty: c_p h / max(mu_L, mu_R)         */
+  int smoother;       /* LDGMG_SMOOTH_*                                           */
+  int sai_level;      /* l of SAI_l (pattern of A^l), 0..2                        */
+  int order;          /* LDGMG_ORDER_*                                            */
+  int nu1, nu2;       /* pre/post smoothing steps (paper: 3, 3)                   */
+  double omega;       /* damping (Jacobi 0.8, coloured GS 1.0); <= 0 -> default   */
+  double zeta;        /* Stokes balancing weight (tab:zeta); <= 0 -> tab:zeta     */
+  int precision;      /* LDGMG_FP64 | LDGMG_FP32                                  */
+  int nthreads;       /* host threads for the setup; <= 0 -> hardware count      */
+  size_t hbm_budget;  /* refuse ldgmg_upload above this many bytes; 0 = no limit */
+} ldgmg_problem;
+
+typedef struct {
+  int iters;               /* Krylov iterations performed                          */
+  int converged;           /* 1 if the stopping test was met                       */
+  double rel_res_true;     /* ||b - A x||_2 / ||b||_2 in FP64 on the device        */
+  double rel_res_krylov;   /* final Krylov-native stopping quantity                */
+  double eta;              /* eq:eta from the Krylov-native residual history       */
+  double* history;         /* host, caller-owned, may be NULL                      */
+  int history_cap;         /* capacity of history                                   */
+  int history_len;         /* entries written                                      */
+  int vcycles;             /* V-cycle applications                                 */
+} ldgmg_info;
+
+/* Fill *p with the paper's defaults: Poisson, Legendre basis, Dirichlet on all
+ * faces, tau0 = 1, cp = 0.1, SAI_1, OI, nu1 = nu2 = 3, FP32 V-cycle. */
+int ldgmg_problem_default(ldgmg_problem* p);
+
+/* Device bytes ldgmg_upload would allocate for this problem (no allocation, no
+ * setup work beyond sizes).  Used for admission by HBM budget. */
+int ldgmg_estimate_bytes(const ldgmg_problem* p, size_t* bytes);
+
+/* Host setup (FP64): LDG assembly, factor coarsening (Section 2.2), smoother
+ * construction (block inverses, colouring, balanced SAI with a cache of
+ * identical least-squares problems), bottom pseudo-inverse.  Needs no GPU.
+ * *out receives a new handle owning all host data. */
+int ldgmg_setup_host(const ldgmg_problem* p, ldgmg_handle* out);
+
+/* Copy a host-built hierarchy to the current HIP device (allocating with
+ * hipMalloc) in the handle's precision; fails with LDGMG_ENOMEM above the
+ * problem's hbm_budget. */
+int ldgmg_upload(ldgmg_handle h, void* stream);
+
+/* ldgmg_setup_host followed by ldgmg_upload. */
+int ldgmg_setup(const ldgmg_problem* p, void* stream, ldgmg_handle* out);
+
+/* Sizes: fine-level unknowns, unknowns per element, number of levels. */
+int ldgmg_sizes(ldgmg_handle h, long long* ndofs, int* bs, int* nlevels);
+
+/* Per-level sizes: elements per side, element count, stored blocks of A,
+ * stored blocks of the smoother matrix (B for SAI, D^-1 otherwise), colours. */
+int ldgmg_level_info(ldgmg_handle h, int level, int* n, int* nelem, int* nnzb_A,
+                     int* nnzb_S, int* ncolours);
+
+/* Volume load b_K[a] = int_K f psi_a (the f part of b_h, Section 2.1), from f
+ * sampled at the nq^dim tensor Gauss-Legendre points of every element
+ * (host array [n^dim][nq^dim], points with the x index fastest), written to
+ * b_dev (device, FP64, fine-level layout).  Scalar problems only. */
+int ldgmg_rhs_volume(ldgmg_handle h, const double* f_qp_host, int nq, double* b_dev,
+                     void* stream);
+
+/* x = V b: one V-cycle of Algorithm 1 with zero initial guess on the fine
+ * level.  b_dev, x_dev: device FP64, fine-level layout (ndofs entries). */
+int ldgmg_vcycle(ldgmg_handle h, const double* b_dev, double* x_dev, void* stream);
+
+/* Solve A x = b from x0 = 0 with the V-cycle as preconditioner of CG
+ * (krylov = LDGMG_CG; needs a symmetric V) or of left-preconditioned GMRES
+ * (LDGMG_GMRES, no restart, at most min(maxit, 200) iterations).  Stops when
+ * ||r||_2 <= rtol ||b||_2 (CG, FP64 recursive residual) or
+ * ||V r||_2 <= rtol ||V b||_2 (GMRES).  Returns LDGMG_ENOCONV if maxit is hit.
+ * info may be NULL. */
+int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov,
+                double rtol, int maxit, ldgmg_info* info, void* stream);
+
+/* Single operations of the V-cycle on one level, for checking each kernel.
+ * in1/in2/out are device vectors of the level in the handle's precision
+ * (FP32 or FP64 per `precision`; LDGMG_OP_APPLY_A64 is always FP64).
+ *   LDGMG_OP_RESIDUAL    out = in2 - A in1                  (b - A x)
+ *   LDGMG_OP_APPLY_A     out = A in1
+ *   LDGMG_OP_APPLY_S     out = S in1, S = B (SAI) or D^-1 (Jacobi / GS)
+ *   LDGMG_OP_APPLY_ST    out = S^T in1
+ *   LDGMG_OP_SMOOTH_FWD  out = in1 after one forward smoothing step with b = in2
+ *   LDGMG_OP_SMOOTH_REV  out = in1 after one reverse smoothing step with b = in2
+ *   LDGMG_OP_RESTRICT    out (level+1) = I^T in1 (level)
+ *   LDGMG_OP_PROLONG_ADD out (level) += I in1 (level+1)
+ *   LDGMG_OP_BOTTOM      out = A^+ in1 on the bottom level
+ *   LDGMG_OP_APPLY_A64   out = A in1 in FP64 on the fine level (Krylov operator)
+ * in2 is read only by RESIDUAL and the SMOOTH ops. */
+enum { LDGMG_OP_RESIDUAL = 0, LDGMG_OP_APPLY_A = 1, LDGMG_OP_APPLY_S = 2,
+       LDGMG_OP_APPLY_ST = 3, LDGMG_OP_SMOOTH_FWD = 4, LDGMG_OP_SMOOTH_REV = 5,
+       LDGMG_OP_RESTRICT = 6, LDGMG_OP_PROLONG_ADD = 7, LDGMG_OP_BOTTOM = 8,
+       LDGMG_OP_APPLY_A64 = 9 };
+int ldgmg_level_op(ldgmg_handle h, int level, int op, const void* in1, const void* in2,
+                   void* out, void* stream);
+
+/* Export host-side setup data (FP64) for checking.  what:
+ *   LDGMG_EXPORT_A     block-sparse A of the level
+ *   LDGMG_EXPORT_S     smoother matrix (B for SAI, block-diagonal D^-1 otherwise)
+ *   LDGMG_EXPORT_PINV  bottom pseudo-inverse (dense, row-major; level ignored)
+ * Block-sparse exports fill row_ptr [nelem+1], col [nnzb] and blocks
+ * [nnzb][bs][bs] (row-major inside a block).  Call with blocks == NULL to get
+ * *nnzb (and *dense_n for PINV) only.  Host pointers, caller-owned. */
+enum { LDGMG_EXPORT_A = 0, LDGMG_EXPORT_S = 1, LDGMG_EXPORT_PINV = 2 };
+int ldgmg_export(ldgmg_handle h, int level, int what, int* row_ptr, int* col,
+                 double* blocks, int* nnzb, int* dense_n);
+
+/* Colours of the multi-coloured Gauss-Seidel smoother (host int[nelem]). */
+int ldgmg_export_colours(ldgmg_handle h, int level, int* colours);
+
+/* Setup statistics: unique SAI least-squares problems solved on the level and
+ * the host setup time in seconds. */
+int ldgmg_setup_stats(ldgmg_handle h, int level, int* sai_unique, double* seconds);
+
+/* Release all host and device memory of the handle. */
+int ldgmg_destroy(ldgmg_handle h);
+
+const char* ldgmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDGMG_H */

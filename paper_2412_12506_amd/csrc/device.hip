@@ -1,0 +1,992 @@
+// Device hierarchy, V-cycle (Algorithm 1), Krylov drivers and the C-ABI.
+//
+// Precision: the V-cycle (matrices, smoothers, transfers, vectors) runs in the
+// handle's precision T (float or double); the outer Krylov iteration, its
+// operator A (fine level) and all inner products are FP64.  The bottom solve
+// is an FP64 dense product with the pseudo-inverse.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ldgmg.h"
+#include "host.hpp"
+#include "launch.hpp"
+
+namespace ldgmg {
+
+namespace {
+
+thread_local std::string g_err;
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct BudgetError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct StateError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    const hipError_t e_ = (x);                                                         \
+    if (e_ != hipSuccess) throw HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevLevel {
+  int n = 0, ne = 0, bs = 0, bss = 0, ncomp = 1;
+  long long N = 0;                  // unknowns on the level
+  int nnzA = 0, nnzS = 0;
+  int* rpA = nullptr;
+  int* ciA = nullptr;
+  void* valA = nullptr;             // working precision
+  int* rpS = nullptr;
+  int* ciS = nullptr;
+  int* tposS = nullptr;
+  void* valS = nullptr;
+  std::vector<int*> colour_rows;    // device lists per colour
+  std::vector<int> colour_count;
+  void* x = nullptr;
+  void* b = nullptr;
+  void* r = nullptr;
+  void* t = nullptr;
+  void* Ic = nullptr;               // child injection matrices [2^d][bss][bss] (this level -> its children)
+  double* pinv = nullptr;           // bottom only
+};
+
+struct DevHier {
+  int prec = LDGMG_FP32;
+  int device = 0;
+  std::vector<DevLevel> L;
+  double* val64 = nullptr;          // fine-level FP64 A values (own copy only in FP32 mode)
+  bool own64 = false;
+  double *kx = nullptr, *kr = nullptr, *kp = nullptr, *kq = nullptr, *kz = nullptr;
+  double* scal = nullptr;           // scalar table
+  double* partial = nullptr;        // reduction partials
+  double* hscal = nullptr;          // pinned host mirror of scal
+  double* Q = nullptr;              // GMRES basis
+  int Qcap = 0;
+  double* hvec = nullptr;           // device small vectors (GMRES coefficients)
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+
+  void* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 16;
+    const hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) throw BudgetError(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    allocs.push_back(p);
+    bytes += n;
+    return p;
+  }
+  ~DevHier() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hscal) (void)hipHostFree(hscal);
+  }
+};
+
+}  // namespace
+}  // namespace ldgmg
+
+struct ldgmg_hier {
+  std::unique_ptr<ldgmg::HostHierarchy> host;
+  std::unique_ptr<ldgmg::DevHier> dev;
+};
+
+namespace ldgmg {
+namespace {
+
+enum { S_BB = 0, S_RZ = 1, S_ALPHA = 2, S_RR = 3, S_BETA = 4, S_PQ = 5, S_TMP = 6, S_W = 7 };
+
+size_t elem_bytes(int prec) { return prec == LDGMG_FP64 ? 8 : 4; }
+
+// bytes one level needs on the device in precision prec
+size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long nnzS, bool bottom,
+                   bool gs, int prec) {
+  const size_t eb = elem_bytes(prec);
+  const size_t N = static_cast<size_t>(ne) * bs;
+  size_t b = 0;
+  b += (ne + 1) * 4 + nnzA * 4 + nnzA * static_cast<size_t>(bs) * bs * eb;
+  if (!bottom) {
+    b += (ne + 1) * 4 + nnzS * 8 + nnzS * static_cast<size_t>(bs) * bs * eb;
+    if (gs) b += ne * 4;
+  } else {
+    b += N * N * 8;
+  }
+  b += 4 * N * eb;
+  b += (static_cast<size_t>(1) << dim) * bss * bss * eb;
+  return b;
+}
+
+template <typename T>
+void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hipStream_t st,
+                  const HostLevel* finer) {
+  dl.n = hl.n;
+  dl.ne = hl.ne;
+  dl.bs = hl.bs;
+  dl.bss = hl.bss;
+  dl.ncomp = hl.ncomp;
+  dl.N = static_cast<long long>(hl.ne) * hl.bs;
+  const size_t bb = static_cast<size_t>(hl.bs) * hl.bs;
+  auto up_ints = [&](const std::vector<int>& v) {
+    int* p = static_cast<int*>(D.alloc(v.size() * sizeof(int)));
+    HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    return p;
+  };
+  // expand a pooled matrix into device blocks of type T (staging the pool and ids)
+  auto expand = [&](const PMat& P, bool transpose) {
+    T* out = static_cast<T*>(D.alloc(static_cast<size_t>(P.nnzb()) * bb * sizeof(T)));
+    double* pool = nullptr;
+    int* ids = nullptr;
+    HIPCHK(hipMalloc(&pool, std::max<size_t>(16, P.pool.data.size() * sizeof(double))));
+    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, P.id.size() * sizeof(int))));
+    HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ids, P.id.data(), P.id.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    expand_blocks<T>(P.nnzb(), hl.bs, ids, pool, out, transpose, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(pool));
+    HIPCHK(hipFree(ids));
+    return out;
+  };
+  dl.nnzA = hl.A.nnzb();
+  dl.rpA = up_ints(hl.A.rp);
+  dl.ciA = up_ints(hl.A.ci);
+  dl.valA = expand(hl.A, false);
+  if (!bottom) {
+    dl.nnzS = hl.S.nnzb();
+    dl.rpS = up_ints(hl.S.rp);
+    dl.ciS = up_ints(hl.S.ci);
+    dl.tposS = up_ints(hl.tpos);
+    dl.valS = expand(hl.S, false);
+    for (const auto& rows : hl.colour_rows) {
+      dl.colour_rows.push_back(up_ints(rows));
+      dl.colour_count.push_back(static_cast<int>(rows.size()));
+    }
+  } else {
+    dl.pinv = static_cast<double*>(D.alloc(hl.pinv.size() * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(dl.pinv, hl.pinv.data(), hl.pinv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  const size_t vb = static_cast<size_t>(dl.N) * sizeof(T);
+  dl.x = D.alloc(vb);
+  dl.b = D.alloc(vb);
+  dl.r = D.alloc(vb);
+  dl.t = D.alloc(vb);
+  HIPCHK(hipMemsetAsync(dl.x, 0, vb, st));
+  HIPCHK(hipMemsetAsync(dl.r, 0, vb, st));
+  HIPCHK(hipMemsetAsync(dl.t, 0, vb, st));
+  // child injection matrices of this level's elements into the finer level (used by the finer level)
+  (void)finer;
+  const int nch = 1 << hl.em.dim;
+  std::vector<T> ic(static_cast<size_t>(nch) * hl.bss * hl.bss);
+  for (int c = 0; c < nch; ++c)
+    for (size_t t = 0; t < static_cast<size_t>(hl.bss) * hl.bss; ++t)
+      ic[static_cast<size_t>(c) * hl.bss * hl.bss + t] = static_cast<T>(hl.em.Ic[c][t]);
+  dl.Ic = D.alloc(ic.size() * sizeof(T));
+  HIPCHK(hipMemcpyAsync(dl.Ic, ic.data(), ic.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+size_t estimate_from_host(const HostHierarchy& H, int prec) {
+  size_t b = 0;
+  const int nl = static_cast<int>(H.levels.size());
+  for (int l = 0; l < nl; ++l) {
+    const HostLevel& L = H.levels[l];
+    b += level_bytes(L.ne, L.bs, L.bss, L.em.dim, L.A.nnzb(), L.S.nnzb(), l == nl - 1,
+                     H.prob.smoother == LDGMG_SMOOTH_GS, prec);
+  }
+  const HostLevel& F = H.levels[0];
+  const size_t N = static_cast<size_t>(F.ne) * F.bs;
+  if (prec != LDGMG_FP64) b += static_cast<size_t>(F.A.nnzb()) * F.bs * F.bs * 8;
+  b += 5 * N * 8 + 64 * 8 + kRedBlocks * 8 * 2;
+  return b;
+}
+
+void upload(ldgmg_hier* h, hipStream_t st) {
+  const HostHierarchy& H = *h->host;
+  const size_t need = estimate_from_host(H, H.prob.precision);
+  if (H.prob.hbm_budget && need > H.prob.hbm_budget)
+    throw BudgetError("hierarchy needs " + std::to_string(need) + " bytes, over the HBM budget of " +
+                      std::to_string(H.prob.hbm_budget));
+  auto D = std::make_unique<DevHier>();
+  D->prec = H.prob.precision;
+  HIPCHK(hipGetDevice(&D->device));
+  const int nl = static_cast<int>(H.levels.size());
+  D->L.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    if (D->prec == LDGMG_FP64)
+      upload_level<double>(*D, D->L[l], H.levels[l], l == nl - 1, st, l ? &H.levels[l - 1] : nullptr);
+    else
+      upload_level<float>(*D, D->L[l], H.levels[l], l == nl - 1, st, l ? &H.levels[l - 1] : nullptr);
+  }
+  const HostLevel& F = H.levels[0];
+  DevLevel& f = D->L[0];
+  if (D->prec == LDGMG_FP64) {
+    D->val64 = static_cast<double*>(f.valA);
+  } else {
+    const size_t bb = static_cast<size_t>(F.bs) * F.bs;
+    D->val64 = static_cast<double*>(D->alloc(static_cast<size_t>(F.A.nnzb()) * bb * sizeof(double)));
+    double* pool = nullptr;
+    int* ids = nullptr;
+    HIPCHK(hipMalloc(&pool, std::max<size_t>(16, F.A.pool.data.size() * sizeof(double))));
+    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, F.A.id.size() * sizeof(int))));
+    HIPCHK(hipMemcpyAsync(pool, F.A.pool.data.data(), F.A.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ids, F.A.id.data(), F.A.id.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    expand_blocks<double>(F.A.nnzb(), F.bs, ids, pool, D->val64, false, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(pool));
+    HIPCHK(hipFree(ids));
+    D->own64 = true;
+  }
+  const size_t vb = static_cast<size_t>(f.N) * sizeof(double);
+  D->kx = static_cast<double*>(D->alloc(vb));
+  D->kr = static_cast<double*>(D->alloc(vb));
+  D->kp = static_cast<double*>(D->alloc(vb));
+  D->kq = static_cast<double*>(D->alloc(vb));
+  D->kz = static_cast<double*>(D->alloc(vb));
+  D->scal = static_cast<double*>(D->alloc(64 * sizeof(double)));
+  D->partial = static_cast<double*>(D->alloc(static_cast<size_t>(kRedBlocks) * 2 * sizeof(double)));
+  HIPCHK(hipMemsetAsync(D->scal, 0, 64 * sizeof(double), st));
+  HIPCHK(hipHostMalloc(&D->hscal, 64 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipStreamSynchronize(st));
+  h->dev = std::move(D);
+}
+
+// ---------------------------------------------------------------------------
+// level operations
+// ---------------------------------------------------------------------------
+struct Ctx {
+  const HostHierarchy& H;
+  DevHier& D;
+  hipStream_t st;
+};
+
+template <typename T>
+BsrArgs<T> argsA(const DevLevel& L) {
+  BsrArgs<T> a;
+  a.nrows = L.ne;
+  a.bs = L.bs;
+  a.rp = L.rpA;
+  a.ci = L.ciA;
+  a.blk = static_cast<const T*>(L.valA);
+  return a;
+}
+template <typename T>
+BsrArgs<T> argsS(const DevLevel& L) {
+  BsrArgs<T> a;
+  a.nrows = L.ne;
+  a.bs = L.bs;
+  a.rp = L.rpS;
+  a.ci = L.ciS;
+  a.tpos = L.tposS;
+  a.blk = static_cast<const T*>(L.valS);
+  return a;
+}
+
+// out = b - A x
+template <typename T>
+void residual(const DevLevel& L, const T* x, const T* b, T* out, hipStream_t st) {
+  BsrArgs<T> a = argsA<T>(L);
+  a.x = x;
+  a.z = b;
+  a.out = out;
+  a.alpha = T(-1);
+  a.beta = T(1);
+  bsr_forward<T>(a, st);
+}
+
+// out = alpha S x + beta z   (transposed: S^T)
+template <typename T>
+void apply_S(const DevLevel& L, bool transposed, const T* x, const T* z, T* out, T alpha, T beta,
+             hipStream_t st) {
+  BsrArgs<T> a = argsS<T>(L);
+  a.x = x;
+  a.z = z;
+  a.out = out;
+  a.alpha = alpha;
+  a.beta = beta;
+  if (transposed) bsr_transposed<T>(a, st);
+  else bsr_forward<T>(a, st);
+}
+
+// one smoothing step on level L with x (in/out), b.  `zero_x`: x is known to be 0.
+// Uses L.r / L.t as scratch.  Returns the buffer holding the result (x or t).
+template <typename T>
+T* smooth_step(const Ctx& c, DevLevel& L, T* x, const T* b, bool forward, bool zero_x) {
+  const int sm = c.H.prob.smoother;
+  const T omega = static_cast<T>(c.H.omega);
+  T* r = static_cast<T*>(L.r);
+  T* t = static_cast<T*>(L.t);
+  if (sm == LDGMG_SMOOTH_SAI) {
+    if (zero_x) {             // x = S b  (eq:B1) or S^T b (eq:BT) from x = 0
+      apply_S<T>(L, !forward, b, nullptr, x, T(1), T(0), c.st);
+      return x;
+    }
+    residual<T>(L, x, b, r, c.st);
+    apply_S<T>(L, !forward, r, x, x, T(1), T(1), c.st);
+    return x;
+  }
+  if (sm == LDGMG_SMOOTH_JACOBI) {
+    if (zero_x) {             // x = w D^-1 b
+      apply_S<T>(L, false, b, nullptr, x, omega, T(0), c.st);
+      return x;
+    }
+    if (fast_bs(L.bs)) {      // t = x + w D^-1 (b - A x)
+      BsrArgs<T> a = argsA<T>(L);
+      a.x = x;
+      a.z = b;
+      a.out = t;
+      a.dinv = static_cast<const T*>(L.valS);
+      a.omega = omega;
+      bsr_forward<T>(a, c.st);
+      return t;
+    }
+    residual<T>(L, x, b, r, c.st);
+    apply_S<T>(L, false, r, x, x, omega, T(1), c.st);
+    return x;
+  }
+  // multi-coloured Gauss-Seidel: colours in order (forward) or reversed
+  if (zero_x) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(T), c.st));
+  const int nc = static_cast<int>(L.colour_rows.size());
+  for (int k = 0; k < nc; ++k) {
+    const int col = forward ? k : nc - 1 - k;
+    if (fast_bs(L.bs)) {
+      BsrArgs<T> a = argsA<T>(L);
+      a.nrows = L.colour_count[col];
+      a.rows = L.colour_rows[col];
+      a.x = x;
+      a.z = b;
+      a.out = x;              // in place: rows of one colour are not coupled
+      a.dinv = static_cast<const T*>(L.valS);
+      a.omega = omega;
+      bsr_forward<T>(a, c.st);
+    } else {
+      BsrArgs<T> a = argsA<T>(L);
+      a.nrows = L.colour_count[col];
+      a.rows = L.colour_rows[col];
+      a.x = x;
+      a.z = b;
+      a.out = r;
+      a.alpha = T(-1);
+      a.beta = T(1);
+      bsr_forward<T>(a, c.st);
+      BsrArgs<T> s = argsS<T>(L);
+      s.nrows = L.colour_count[col];
+      s.rows = L.colour_rows[col];
+      s.x = r;
+      s.z = x;
+      s.out = x;
+      s.alpha = omega;
+      s.beta = T(1);
+      bsr_forward<T>(s, c.st);
+    }
+  }
+  return x;
+}
+
+int order_pre_forward(int order) { return order == LDGMG_ORDER_OO || order == LDGMG_ORDER_OI; }
+int order_post_forward(int order) { return order == LDGMG_ORDER_OO || order == LDGMG_ORDER_IO; }
+
+// x_l = V(E_l, 0, b_l) with b_l in L[l].b, result in L[l].x   (Algorithm 1)
+template <typename T>
+void vcycle_level(const Ctx& c, int l) {
+  DevLevel& L = c.D.L[l];
+  const int nl = static_cast<int>(c.D.L.size());
+  T* x = static_cast<T*>(L.x);
+  T* b = static_cast<T*>(L.b);
+  if (l == nl - 1) {
+    dense_gemv<T>(static_cast<int>(L.N), L.pinv, b, x, c.st);
+    return;
+  }
+  const ldgmg_problem& P = c.H.prob;
+  const bool pre_fwd = order_pre_forward(P.order), post_fwd = order_post_forward(P.order);
+  auto keep = [&](T* res) {
+    if (res != x) {             // Jacobi wrote into t: swap the roles of x and t
+      std::swap(L.x, L.t);
+      x = static_cast<T*>(L.x);
+    }
+  };
+  if (P.nu1 == 0) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(T), c.st));
+  for (int s = 0; s < P.nu1; ++s) keep(smooth_step<T>(c, L, x, b, pre_fwd, s == 0));
+  T* r = static_cast<T*>(L.r);
+  residual<T>(L, x, b, r, c.st);
+  DevLevel& Lc = c.D.L[l + 1];
+  restrict_op<T>(P.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), r, static_cast<T*>(Lc.b), c.st);
+  vcycle_level<T>(c, l + 1);
+  prolong_add<T>(P.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), static_cast<const T*>(Lc.x), x, c.st);
+  for (int s = 0; s < P.nu2; ++s) keep(smooth_step<T>(c, L, x, b, post_fwd, false));
+}
+
+// z = V r in FP64 (cast around the working-precision V-cycle)
+void vcycle64(const Ctx& c, const double* r, double* z) {
+  DevLevel& L = c.D.L[0];
+  if (c.D.prec == LDGMG_FP64) {
+    HIPCHK(hipMemcpyAsync(L.b, r, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
+    vcycle_level<double>(c, 0);
+    HIPCHK(hipMemcpyAsync(z, L.x, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
+  } else {
+    cast<double, float>(L.N, r, static_cast<float*>(L.b), c.st);
+    vcycle_level<float>(c, 0);
+    cast<float, double>(L.N, static_cast<const float*>(L.x), z, c.st);
+  }
+}
+
+void apply_A64(const Ctx& c, const double* x, double* y) {
+  const DevLevel& L = c.D.L[0];
+  BsrArgs<double> a;
+  a.nrows = L.ne;
+  a.bs = L.bs;
+  a.rp = L.rpA;
+  a.ci = L.ciA;
+  a.blk = c.D.val64;
+  a.x = x;
+  a.out = y;
+  bsr_forward<double>(a, c.st);
+}
+
+double dot_host(const Ctx& c, const double* a, const double* b, int slot) {
+  dot_partial(c.D.L[0].N, a, b, c.D.partial, c.st);
+  finalize(c.D.partial, c.D.scal, 0, slot, 0, c.st);
+  HIPCHK(hipMemcpyAsync(c.D.hscal, c.D.scal, 64 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  return c.D.hscal[slot];
+}
+
+double eta_from(const std::vector<double>& hist) {
+  std::vector<double> y;
+  for (double v : hist)
+    if (v > 0) y.push_back(std::log10(v));
+  const int n = static_cast<int>(y.size());
+  if (n < 2) return NAN;
+  double sx = 0, sy = 0, sxx = 0, sxy = 0;
+  for (int k = 0; k < n; ++k) {
+    sx += k;
+    sy += y[k];
+    sxx += static_cast<double>(k) * k;
+    sxy += k * y[k];
+  }
+  const double slope = (n * sxy - sx * sy) / (n * sxx - sx * sx);
+  if (slope >= 0) return INFINITY;
+  return -1.0 / slope;
+}
+
+void finish_info(const Ctx& c, const double* b, double* x, double bnorm2, const std::vector<double>& hist,
+                 int iters, bool conv, double krylov_rel, int vcycles, ldgmg_info* info) {
+  if (!info) return;
+  apply_A64(c, x, c.D.kq);
+  axpby(c.D.L[0].N, b, c.D.kq, c.D.scal, -1, 1.0, -1, -1.0, c.st);   // kq = b - A x
+  const double rr = dot_host(c, c.D.kq, c.D.kq, S_TMP);
+  info->iters = iters;
+  info->converged = conv ? 1 : 0;
+  info->rel_res_true = bnorm2 > 0 ? std::sqrt(rr / bnorm2) : 0.0;
+  info->rel_res_krylov = krylov_rel;
+  info->eta = eta_from(hist);
+  info->vcycles = vcycles;
+  info->history_len = 0;
+  if (info->history && info->history_cap > 0) {
+    const int n = std::min(info->history_cap, static_cast<int>(hist.size()));
+    for (int i = 0; i < n; ++i) info->history[i] = hist[i];
+    info->history_len = n;
+  }
+}
+
+// preconditioned CG (Hestenes-Stiefel), x0 = 0, z = V r
+int solve_cg(const Ctx& c, const double* b, double* x, double rtol, int maxit, ldgmg_info* info) {
+  DevHier& D = c.D;
+  const long long N = D.L[0].N;
+  HIPCHK(hipMemsetAsync(x, 0, N * 8, c.st));
+  HIPCHK(hipMemcpyAsync(D.kr, b, N * 8, hipMemcpyDeviceToDevice, c.st));
+  const double bb = dot_host(c, b, b, S_BB);
+  if (!std::isfinite(bb)) throw std::invalid_argument("right-hand side contains NaN or Inf");
+  std::vector<double> hist;
+  if (bb == 0.0) {
+    finish_info(c, b, x, bb, hist, 0, true, 0.0, 0, info);
+    return LDGMG_OK;
+  }
+  const double tol2 = rtol * rtol * bb;
+  vcycle64(c, D.kr, D.kz);
+  int vcycles = 1;
+  dot_partial(N, D.kr, D.kz, D.partial, c.st);
+  finalize(D.partial, D.scal, 0, S_RZ, 0, c.st);
+  HIPCHK(hipMemcpyAsync(D.kp, D.kz, N * 8, hipMemcpyDeviceToDevice, c.st));
+  int it = 0;
+  bool conv = false;
+  double rr = bb;
+  while (it < maxit) {
+    apply_A64(c, D.kp, D.kq);
+    dot_partial(N, D.kp, D.kq, D.partial, c.st);
+    finalize(D.partial, D.scal, 1, S_ALPHA, S_RZ, c.st);          // alpha = rz / (p.q)
+    cg_update(N, x, D.kr, D.kp, D.kq, D.scal, S_ALPHA, D.partial, c.st);
+    finalize(D.partial, D.scal, 0, S_RR, 0, c.st);
+    HIPCHK(hipMemcpyAsync(D.hscal, D.scal, 64 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    hist.push_back(std::sqrt(std::fabs(D.hscal[S_RZ])));
+    ++it;
+    rr = D.hscal[S_RR];
+    if (!std::isfinite(rr)) throw std::runtime_error("CG breakdown (non-finite residual)");
+    if (rr <= tol2) {
+      conv = true;
+      break;
+    }
+    vcycle64(c, D.kr, D.kz);
+    ++vcycles;
+    dot_partial(N, D.kr, D.kz, D.partial, c.st);
+    finalize(D.partial, D.scal, 2, S_BETA, S_RZ, c.st);           // beta = rz_new / rz; rz = rz_new
+    cg_dir(N, D.kp, D.kz, D.scal, S_BETA, c.st);
+  }
+  finish_info(c, b, x, bb, hist, it, conv, std::sqrt(rr / bb), vcycles, info);
+  return conv ? LDGMG_OK : LDGMG_ENOCONV;
+}
+
+// left-preconditioned GMRES on V A x = V b, x0 = 0, no restart, CGS2
+int solve_gmres(const Ctx& c, const double* b, double* x, double rtol, int maxit, ldgmg_info* info) {
+  DevHier& D = c.D;
+  const long long N = D.L[0].N;
+  maxit = std::max(1, std::min(maxit, 200));
+  if (D.Qcap < maxit + 1) {
+    D.Q = static_cast<double*>(D.alloc(static_cast<size_t>(maxit + 1) * N * 8));
+    D.hvec = static_cast<double*>(D.alloc(static_cast<size_t>(2 * (maxit + 2)) * 8 +
+                                          static_cast<size_t>(maxit + 2) * kMdotBlocks * 8));
+    D.Qcap = maxit + 1;
+  }
+  double* h1 = D.hvec;
+  double* h2 = D.hvec + (maxit + 2);
+  double* part = D.hvec + 2 * (maxit + 2);
+  HIPCHK(hipMemsetAsync(x, 0, N * 8, c.st));
+  const double bb = dot_host(c, b, b, S_BB);
+  if (!std::isfinite(bb)) throw std::invalid_argument("right-hand side contains NaN or Inf");
+  std::vector<double> hist;
+  if (bb == 0.0) {
+    finish_info(c, b, x, bb, hist, 0, true, 0.0, 0, info);
+    return LDGMG_OK;
+  }
+  vcycle64(c, b, D.kz);
+  int vcycles = 1;
+  const double beta2 = dot_host(c, D.kz, D.kz, S_W);
+  const double beta = std::sqrt(beta2);
+  scale_invsqrt(N, D.kz, D.Q, D.scal, S_W, c.st);
+  std::vector<double> H(static_cast<size_t>(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
+  g[0] = beta;
+  hist.push_back(beta);
+  std::vector<double> hh1(maxit + 2), hh2(maxit + 2);
+  int k = 0;
+  bool conv = false;
+  for (int j = 0; j < maxit; ++j) {
+    apply_A64(c, D.Q + static_cast<size_t>(j) * N, D.kq);
+    vcycle64(c, D.kq, D.kz);
+    ++vcycles;
+    mdot(N, j + 1, D.Q, D.kz, part, h1, c.st);
+    maxpy(N, j + 1, D.Q, h1, -1.0, D.kz, c.st);
+    mdot(N, j + 1, D.Q, D.kz, part, h2, c.st);
+    maxpy(N, j + 1, D.Q, h2, -1.0, D.kz, c.st);
+    dot_partial(N, D.kz, D.kz, D.partial, c.st);
+    finalize(D.partial, D.scal, 0, S_W, 0, c.st);
+    HIPCHK(hipMemcpyAsync(hh1.data(), h1, (j + 1) * 8, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(hh2.data(), h2, (j + 1) * 8, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(D.hscal, D.scal, 64 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    const double wn = std::sqrt(D.hscal[S_W]);
+    if (!std::isfinite(wn)) throw std::runtime_error("GMRES breakdown (non-finite vector)");
+    double* hc = &H[static_cast<size_t>(j) * (maxit + 1)];      // column j
+    for (int i = 0; i <= j; ++i) hc[i] = hh1[i] + hh2[i];
+    hc[j + 1] = wn;
+    if (wn > 0) scale_invsqrt(N, D.kz, D.Q + static_cast<size_t>(j + 1) * N, D.scal, S_W, c.st);
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+      hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+      hc[i] = t;
+    }
+    const double den = std::hypot(hc[j], hc[j + 1]);
+    cs[j] = hc[j] / den;
+    sn[j] = hc[j + 1] / den;
+    hc[j] = den;
+    hc[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    k = j + 1;
+    hist.push_back(std::fabs(g[j + 1]));
+    if (std::fabs(g[j + 1]) <= rtol * beta || wn == 0) {
+      conv = std::fabs(g[j + 1]) <= rtol * beta;
+      break;
+    }
+  }
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int t = i + 1; t < k; ++t) s -= H[static_cast<size_t>(t) * (maxit + 1) + i] * y[t];
+    y[i] = s / H[static_cast<size_t>(i) * (maxit + 1) + i];
+  }
+  HIPCHK(hipMemcpyAsync(h1, y.data(), k * 8, hipMemcpyHostToDevice, c.st));
+  maxpy(N, k, D.Q, h1, 1.0, x, c.st);
+  finish_info(c, b, x, bb, hist, k, conv, std::fabs(g[k]) / beta, vcycles, info);
+  return conv ? LDGMG_OK : LDGMG_ENOCONV;
+}
+
+template <typename T>
+void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, void* out) {
+  DevLevel& L = c.D.L[l];
+  const int nl = static_cast<int>(c.D.L.size());
+  const T* a = static_cast<const T*>(in1);
+  const T* b = static_cast<const T*>(in2);
+  T* o = static_cast<T*>(out);
+  const bool bottom = l == nl - 1;
+  switch (op) {
+    case LDGMG_OP_RESIDUAL:
+      residual<T>(L, a, b, o, c.st);
+      return;
+    case LDGMG_OP_APPLY_A: {
+      BsrArgs<T> x = argsA<T>(L);
+      x.x = a;
+      x.out = o;
+      bsr_forward<T>(x, c.st);
+      return;
+    }
+    case LDGMG_OP_APPLY_S:
+    case LDGMG_OP_APPLY_ST:
+      if (bottom) throw std::invalid_argument("no smoother on the bottom level");
+      apply_S<T>(L, op == LDGMG_OP_APPLY_ST, a, nullptr, o, T(1), T(0), c.st);
+      return;
+    case LDGMG_OP_SMOOTH_FWD:
+    case LDGMG_OP_SMOOTH_REV: {
+      if (bottom) throw std::invalid_argument("no smoother on the bottom level");
+      HIPCHK(hipMemcpyAsync(o, a, static_cast<size_t>(L.N) * sizeof(T), hipMemcpyDeviceToDevice, c.st));
+      T* res = smooth_step<T>(c, L, o, b, op == LDGMG_OP_SMOOTH_FWD, false);
+      if (res != o)
+        HIPCHK(hipMemcpyAsync(o, res, static_cast<size_t>(L.N) * sizeof(T), hipMemcpyDeviceToDevice, c.st));
+      return;
+    }
+    case LDGMG_OP_RESTRICT: {
+      if (bottom) throw std::invalid_argument("no coarser level");
+      DevLevel& Lc = c.D.L[l + 1];
+      restrict_op<T>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), a, o, c.st);
+      return;
+    }
+    case LDGMG_OP_PROLONG_ADD: {
+      if (bottom) throw std::invalid_argument("no coarser level");
+      DevLevel& Lc = c.D.L[l + 1];
+      prolong_add<T>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), a, o, c.st);
+      return;
+    }
+    case LDGMG_OP_BOTTOM:
+      if (!bottom) throw std::invalid_argument("LDGMG_OP_BOTTOM needs the bottom level");
+      dense_gemv<T>(static_cast<int>(L.N), L.pinv, a, o, c.st);
+      return;
+    default:
+      throw std::invalid_argument("unknown op");
+  }
+}
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+template <class F>
+int guarded(F&& fn) {
+  try {
+    g_err.clear();
+    return fn();
+  } catch (const BudgetError& e) {
+    return fail(LDGMG_ENOMEM, e.what());
+  } catch (const HipError& e) {
+    return fail(LDGMG_EHIP, e.what());
+  } catch (const StateError& e) {
+    return fail(LDGMG_ESTATE, e.what());
+  } catch (const std::invalid_argument& e) {
+    return fail(LDGMG_EINVAL, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(LDGMG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    const std::string m = e.what();
+    if (m.find("rank-deficient") != std::string::npos) return fail(LDGMG_ESINGULAR, m);
+    return fail(LDGMG_EHIP, m);
+  }
+}
+
+void need_dev(ldgmg_hier* h) {
+  if (!h) throw std::invalid_argument("null handle");
+  if (!h->dev) throw StateError("handle has no device data (call ldgmg_upload)");
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != h->dev->device) throw StateError("current HIP device differs from the device of the handle");
+}
+
+void check_level(ldgmg_hier* h, int level) {
+  if (!h || !h->host) throw std::invalid_argument("null handle");
+  if (level < 0 || level >= static_cast<int>(h->host->levels.size())) throw std::invalid_argument("level out of range");
+}
+
+}  // namespace
+}  // namespace ldgmg
+
+using namespace ldgmg;
+
+extern "C" {
+
+int ldgmg_problem_default(ldgmg_problem* p) {
+  if (!p) return fail(LDGMG_EINVAL, "null problem");
+  std::memset(p, 0, sizeof(*p));
+  p->dim = 2;
+  p->n = 16;
+  p->p = 2;
+  p->basis = LDGMG_BASIS_LEGENDRE;
+  p->system = LDGMG_POISSON;
+  p->gamma = 1;
+  for (int f = 0; f < 6; ++f) p->bc[f] = LDGMG_BC_DIRICHLET;
+  p->mu = nullptr;
+  p->tau0 = 1.0;
+  p->cp = 0.1;
+  p->smoother = LDGMG_SMOOTH_SAI;
+  p->sai_level = 1;
+  p->order = LDGMG_ORDER_OI;
+  p->nu1 = 3;
+  p->nu2 = 3;
+  p->omega = 0.0;
+  p->zeta = 0.0;
+  p->precision = LDGMG_FP32;
+  p->nthreads = 0;
+  p->hbm_budget = 0;
+  return LDGMG_OK;
+}
+
+int ldgmg_estimate_bytes(const ldgmg_problem* p, size_t* bytes) {
+  return guarded([&] {
+    if (!p || !bytes) throw std::invalid_argument("null argument");
+    validate_problem(*p);
+    // interior stencils: |A| (tab:sizes) and the smoother pattern; 2% margin for interfaces
+    const int d = p->dim;
+    const bool stress = p->system == LDGMG_STOKES && p->gamma;
+    const int sA = stress ? (d == 2 ? 7 : 13) : 2 * d + 1;
+    const int sS[3][2] = {{1, 1}, {2 * d + 1, stress ? (d == 2 ? 7 : 13) : 2 * d + 1},
+                          {d == 2 ? 13 : 25, stress ? (d == 2 ? 19 : 55) : (d == 2 ? 13 : 25)}};
+    int bss = 1;
+    for (int k = 0; k < d; ++k) bss *= p->p + 1;
+    const int bs = bss * (p->system == LDGMG_STOKES ? d + 1 : 1);
+    const std::vector<int> sizes = level_sizes(p->n);
+    size_t b = 0;
+    for (size_t l = 0; l < sizes.size(); ++l) {
+      long long ne = 1;
+      for (int k = 0; k < d; ++k) ne *= sizes[l];
+      const bool bottom = l + 1 == sizes.size();
+      const long long nnzA = static_cast<long long>(ne * sA * 1.02) + 1;
+      const long long nnzS = p->smoother == LDGMG_SMOOTH_SAI
+                                 ? static_cast<long long>(ne * sS[p->sai_level][stress ? 1 : 0] * 1.02) + 1
+                                 : ne;
+      b += level_bytes(static_cast<int>(ne), bs, bss, d, nnzA, nnzS, bottom, p->smoother == LDGMG_SMOOTH_GS,
+                       p->precision);
+      if (l == 0) {
+        if (p->precision != LDGMG_FP64) b += static_cast<size_t>(nnzA) * bs * bs * 8;
+        b += 5 * static_cast<size_t>(ne) * bs * 8 + 64 * 8 + kRedBlocks * 16;
+      }
+    }
+    *bytes = b;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_setup_host(const ldgmg_problem* p, ldgmg_handle* out) {
+  return guarded([&] {
+    if (!p || !out) throw std::invalid_argument("null argument");
+    *out = nullptr;
+    auto h = std::make_unique<ldgmg_hier>();
+    h->host = build_host(*p);
+    *out = h.release();
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_upload(ldgmg_handle h, void* stream) {
+  return guarded([&] {
+    if (!h || !h->host) throw std::invalid_argument("null handle");
+    h->dev.reset();
+    upload(h, static_cast<hipStream_t>(stream));
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_setup(const ldgmg_problem* p, void* stream, ldgmg_handle* out) {
+  ldgmg_handle h = nullptr;
+  int rc = ldgmg_setup_host(p, &h);
+  if (rc != LDGMG_OK) return rc;
+  rc = ldgmg_upload(h, stream);
+  if (rc != LDGMG_OK) {
+    const std::string msg = g_err;
+    delete h;
+    g_err = msg;
+    return rc;
+  }
+  *out = h;
+  return LDGMG_OK;
+}
+
+int ldgmg_sizes(ldgmg_handle h, long long* ndofs, int* bs, int* nlevels) {
+  return guarded([&] {
+    if (!h || !h->host) throw std::invalid_argument("null handle");
+    const HostLevel& F = h->host->levels[0];
+    if (ndofs) *ndofs = static_cast<long long>(F.ne) * F.bs;
+    if (bs) *bs = F.bs;
+    if (nlevels) *nlevels = static_cast<int>(h->host->levels.size());
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_level_info(ldgmg_handle h, int level, int* n, int* nelem, int* nnzb_A, int* nnzb_S, int* ncolours) {
+  return guarded([&] {
+    check_level(h, level);
+    const HostLevel& L = h->host->levels[level];
+    if (n) *n = L.n;
+    if (nelem) *nelem = L.ne;
+    if (nnzb_A) *nnzb_A = L.A.nnzb();
+    if (nnzb_S) *nnzb_S = L.S.nnzb();
+    if (ncolours) *ncolours = L.ncolours;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_rhs_volume(ldgmg_handle h, const double* f_qp, int nq, double* b_dev, void* stream) {
+  return guarded([&] {
+    need_dev(h);
+    if (!f_qp || !b_dev || nq < 1 || nq > 16) throw std::invalid_argument("bad rhs arguments");
+    const HostHierarchy& H = *h->host;
+    if (H.prob.system != LDGMG_POISSON) throw std::invalid_argument("volume load is for scalar problems");
+    const HostLevel& F = H.levels[0];
+    const int d = H.prob.dim, q1 = F.em.q1;
+    // 1-D table w_q psi_i(t_q) at the nq Gauss points the caller sampled f at
+    std::vector<double> t, w, v(q1), dv(q1);
+    gauss_legendre(nq, t, w);
+    std::vector<double> tab(static_cast<size_t>(q1) * nq);
+    for (int q = 0; q < nq; ++q) {
+      basis_eval(F.em.p, H.prob.basis, t[q], v.data(), dv.data());
+      for (int i = 0; i < q1; ++i) tab[static_cast<size_t>(i) * nq + q] = w[q] * v[i];
+    }
+    int nqd = 1;
+    for (int k = 0; k < d; ++k) nqd *= nq;
+    const double scale = std::pow(F.h / 2.0, d);
+    std::vector<double> b(static_cast<size_t>(F.ne) * F.bs, 0.0);
+    for (int e = 0; e < F.ne; ++e) {
+      const double* fe = f_qp + static_cast<size_t>(e) * nqd;
+      for (int a = 0; a < F.bs; ++a) {
+        const int a0 = a % q1, a1 = (a / q1) % q1, a2 = a / (q1 * q1);
+        double s = 0.0;
+        for (int qq = 0; qq < nqd; ++qq) {
+          const int q0 = qq % nq, qy = (qq / nq) % nq, qz = qq / (nq * nq);
+          double wgt = tab[static_cast<size_t>(a0) * nq + q0] * tab[static_cast<size_t>(a1) * nq + qy];
+          if (d == 3) wgt *= tab[static_cast<size_t>(a2) * nq + qz];
+          s += wgt * fe[qq];
+        }
+        b[static_cast<size_t>(e) * F.bs + a] = scale * s;
+      }
+    }
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    HIPCHK(hipMemcpyAsync(b_dev, b.data(), b.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_vcycle(ldgmg_handle h, const double* b_dev, double* x_dev, void* stream) {
+  return guarded([&] {
+    need_dev(h);
+    if (!b_dev || !x_dev) throw std::invalid_argument("null vector");
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    vcycle64(c, b_dev, x_dev);
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov, double rtol, int maxit,
+                ldgmg_info* info, void* stream) {
+  return guarded([&] {
+    need_dev(h);
+    if (!b_dev || !x_dev) throw std::invalid_argument("null vector");
+    if (!(rtol > 0) || maxit < 1) throw std::invalid_argument("rtol must be > 0 and maxit >= 1");
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    if (krylov == LDGMG_CG) return solve_cg(c, b_dev, x_dev, rtol, maxit, info);
+    if (krylov == LDGMG_GMRES) return solve_gmres(c, b_dev, x_dev, rtol, maxit, info);
+    throw std::invalid_argument("unknown krylov method");
+  });
+}
+
+int ldgmg_level_op(ldgmg_handle h, int level, int op, const void* in1, const void* in2, void* out, void* stream) {
+  return guarded([&] {
+    need_dev(h);
+    check_level(h, level);
+    if (!in1 || !out) throw std::invalid_argument("null vector");
+    if ((op == LDGMG_OP_RESIDUAL || op == LDGMG_OP_SMOOTH_FWD || op == LDGMG_OP_SMOOTH_REV) && !in2)
+      throw std::invalid_argument("op needs in2");
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    if (op == LDGMG_OP_APPLY_A64) {
+      if (level != 0) throw std::invalid_argument("the FP64 operator lives on level 0");
+      apply_A64(c, static_cast<const double*>(in1), static_cast<double*>(out));
+      return LDGMG_OK;
+    }
+    if (h->dev->prec == LDGMG_FP64) level_op_t<double>(c, level, op, in1, in2, out);
+    else level_op_t<float>(c, level, op, in1, in2, out);
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_export(ldgmg_handle h, int level, int what, int* row_ptr, int* col, double* blocks, int* nnzb,
+                 int* dense_n) {
+  return guarded([&] {
+    check_level(h, level);
+    const HostHierarchy& H = *h->host;
+    if (what == LDGMG_EXPORT_PINV) {
+      const HostLevel& B = H.levels.back();
+      const int N = B.ne * B.bs;
+      if (dense_n) *dense_n = N;
+      if (blocks) std::copy(B.pinv.begin(), B.pinv.end(), blocks);
+      return LDGMG_OK;
+    }
+    const HostLevel& L = H.levels[level];
+    const PMat* P = nullptr;
+    if (what == LDGMG_EXPORT_A) P = &L.A;
+    else if (what == LDGMG_EXPORT_S) P = &L.S;
+    else throw std::invalid_argument("unknown export");
+    if (what == LDGMG_EXPORT_S && level + 1 == static_cast<int>(H.levels.size()))
+      throw std::invalid_argument("no smoother on the bottom level");
+    if (nnzb) *nnzb = P->nnzb();
+    if (!blocks) return LDGMG_OK;
+    if (row_ptr) std::copy(P->rp.begin(), P->rp.end(), row_ptr);
+    if (col) std::copy(P->ci.begin(), P->ci.end(), col);
+    const size_t bb = static_cast<size_t>(L.bs) * L.bs;
+    for (int s = 0; s < P->nnzb(); ++s) std::copy(P->block(s), P->block(s) + bb, blocks + s * bb);
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_export_colours(ldgmg_handle h, int level, int* colours) {
+  return guarded([&] {
+    check_level(h, level);
+    const HostLevel& L = h->host->levels[level];
+    if (!colours) throw std::invalid_argument("null output");
+    if (L.colour.empty()) throw std::invalid_argument("level has no colouring");
+    std::copy(L.colour.begin(), L.colour.end(), colours);
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_setup_stats(ldgmg_handle h, int level, int* sai_unique, double* seconds) {
+  return guarded([&] {
+    check_level(h, level);
+    const HostLevel& L = h->host->levels[level];
+    if (sai_unique) *sai_unique = L.sai_unique;
+    if (seconds) *seconds = L.setup_seconds;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_destroy(ldgmg_handle h) {
+  delete h;
+  return LDGMG_OK;
+}
+
+const char* ldgmg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

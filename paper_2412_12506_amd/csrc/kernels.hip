@@ -1,0 +1,646 @@
+// HIP kernels for gfx950 and their launch wrappers.  Layout and lane mapping:
+// kernels.hpp.  Every wrapper enqueues on the given stream and checks the
+// launch; bounds are the caller's (launch.hpp documents each wrapper).
+#include "kernels.hpp"
+#include "launch.hpp"
+
+#include <stdexcept>
+#include <string>
+
+namespace ldgmg {
+
+namespace {
+
+template <typename T, int V> struct VecT;
+template <> struct VecT<float, 4> { using type = float4; };
+template <> struct VecT<float, 1> { using type = float; };
+template <> struct VecT<double, 2> { using type = double2; };
+template <> struct VecT<double, 1> { using type = double; };
+
+template <typename T> __device__ __forceinline__ T elem(const T& a, int) { return a; }
+__device__ __forceinline__ float elem(const float4& a, int v) {
+  return v == 0 ? a.x : v == 1 ? a.y : v == 2 ? a.z : a.w;
+}
+__device__ __forceinline__ double elem(const double2& a, int v) { return v == 0 ? a.x : a.y; }
+
+template <typename VT> __device__ __forceinline__ VT vzero() { return VT{}; }
+
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// value of lane (g*BS + c) of the caller's group
+template <typename T, int BS>
+__device__ __forceinline__ T group_bcast(T v, int g, int c) {
+  if constexpr (64 / BS == 1) return readlane(v, c);
+  else return __shfl(v, g * BS + c);
+}
+
+constexpr int kWaves = 4;          // wavefronts per workgroup of the BSR kernels
+constexpr int kThreads = 64 * kWaves;
+
+// ---------------------------------------------------------------------------
+// forward BSR kernel
+//   MODE 0: out_i = alpha (M x)_i + beta z_i            (z read only if beta != 0)
+//   MODE 1: out_i = x_i + omega Dinv_i (z_i - (M x)_i)  (fused block-inverse smoothing;
+//           out may alias x when the rows of one launch are not coupled)
+// rows (optional) lists the block rows to process (nrows entries).
+// ---------------------------------------------------------------------------
+template <typename T, int BS, int MODE>
+__global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __restrict__ rows,
+                                                      const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const T* __restrict__ blk, const T* x,
+                                                      const T* z, T* out, T alpha, T beta,
+                                                      const T* __restrict__ dinv, T omega) {
+  using C = BlkCfg<T, BS>;
+  constexpr int V = C::V, G = C::G, NV = C::NV;
+  using VT = typename VecT<T, V>::type;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / BS;
+  const int r = lane - g * BS;
+  const int wave = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int idx = wave * G + g;
+  const bool active = (g < G) && (idx < nrows);
+  const int row = active ? (rows ? rows[idx] : idx) : 0;
+  const int s0 = active ? rp[row] : 0;
+  const int cnt = active ? rp[row + 1] - s0 : 0;
+  int mc = cnt;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o));
+  T acc = T(0);
+  for (int k = 0; k < mc; ++k) {
+    const bool has = k < cnt;
+    const int s = s0 + k;
+    const int j = has ? ci[s] : 0;
+    const T xv = has ? x[static_cast<size_t>(j) * BS + r] : T(0);
+    VT a[NV];
+    const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(has ? s : 0) * (BS * BS)) + r;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) a[q] = has ? bp[q * BS] : vzero<VT>();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc += elem(a[q], v) * group_bcast<T, BS>(xv, g, q * V + v);
+    }
+  }
+  const size_t o = static_cast<size_t>(row) * BS + r;
+  if constexpr (MODE == 1) {
+    const T res = active ? z[o] - acc : T(0);
+    VT d[NV];
+    const VT* dp = reinterpret_cast<const VT*>(dinv + static_cast<size_t>(row) * (BS * BS)) + r;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) d[q] = active ? dp[q * BS] : vzero<VT>();
+    T y = T(0);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) y += elem(d[q], v) * group_bcast<T, BS>(res, g, q * V + v);
+    }
+    if (active) out[o] = x[o] + omega * y;
+  } else {
+    if (active) out[o] = beta != T(0) ? alpha * acc + beta * z[o] : alpha * acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transposed BSR kernel: out_i = alpha sum_{(i,j) stored} (M_ji)^T x_j + beta z_i.
+// tpos[s] is the slot of block (j, i) for slot s = (i, j) (symmetric pattern).
+// Lane r accumulates row r of each (M_ji) scaled by x_j[r]; the BS partial
+// vectors of a group are then summed across lanes.
+// ---------------------------------------------------------------------------
+template <typename T, int BS>
+__global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const int* __restrict__ tpos,
+                                                     const T* __restrict__ blk, const T* x,
+                                                     const T* z, T* out, T alpha, T beta) {
+  using C = BlkCfg<T, BS>;
+  constexpr int V = C::V, G = C::G, NV = C::NV;
+  constexpr bool POW2 = (BS & (BS - 1)) == 0;
+  using VT = typename VecT<T, V>::type;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / BS;
+  const int r = lane - g * BS;
+  const int wid = threadIdx.x >> 6;
+  const int wave = blockIdx.x * kWaves + wid;
+  const int idx = wave * G + g;
+  const bool active = (g < G) && (idx < nrows);
+  const int row = active ? idx : 0;
+  const int s0 = active ? rp[row] : 0;
+  const int cnt = active ? rp[row + 1] - s0 : 0;
+  int mc = cnt;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o));
+  T acc[BS];
+#pragma unroll
+  for (int c = 0; c < BS; ++c) acc[c] = T(0);
+  for (int k = 0; k < mc; ++k) {
+    const bool has = k < cnt;
+    const int s = s0 + k;
+    const int t = has ? tpos[s] : 0;
+    const int j = has ? ci[s] : 0;
+    const T xr = has ? x[static_cast<size_t>(j) * BS + r] : T(0);
+    const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(t) * (BS * BS)) + r;
+    VT a[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) a[q] = has ? bp[q * BS] : vzero<VT>();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[q * V + v] += elem(a[q], v) * xr;
+    }
+  }
+  T y;
+  if constexpr (POW2) {
+    // butterfly transpose-reduction inside the aligned group of BS lanes:
+    // after the stage with offset o the lane keeps the half selected by bit o
+    // of its index, so lane r ends with the sum for column r.
+#pragma unroll
+    for (int o = BS / 2; o >= 1; o >>= 1) {
+      const bool upper = (r & o) != 0;
+#pragma unroll
+      for (int i = 0; i < o; ++i) {
+        const T mine = upper ? acc[i + o] : acc[i];
+        const T send = upper ? acc[i] : acc[i + o];
+        acc[i] = mine + __shfl_xor(send, o);
+      }
+    }
+    y = acc[0];
+  } else {
+    __shared__ T red[kWaves][G][BS][BS + 1];
+    if (g < G) {
+#pragma unroll
+      for (int c = 0; c < BS; ++c) red[wid][g][r][c] = acc[c];
+    }
+    __syncthreads();
+    y = T(0);
+    if (g < G) {
+      for (int rr = 0; rr < BS; ++rr) y += red[wid][g][rr][r];
+    }
+  }
+  if (active) {
+    const size_t o = static_cast<size_t>(row) * BS + r;
+    out[o] = beta != T(0) ? alpha * y + beta * z[o] : alpha * y;
+  }
+}
+
+// generic BSR kernel for any block size: one lane per scalar row.
+// Blocks use the V = 1 layout (entry (r, c) at c * bs + r).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_generic(int nrows, int bs, const int* __restrict__ rows,
+                                                     const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const int* __restrict__ tpos,
+                                                     const T* __restrict__ blk, const T* x,
+                                                     const T* z, T* out, T alpha, T beta) {
+  const long long tid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long idx = tid / bs;
+  const int r = static_cast<int>(tid - idx * bs);
+  if (idx >= nrows) return;
+  const int row = rows ? rows[idx] : static_cast<int>(idx);
+  T acc = T(0);
+  const size_t bb = static_cast<size_t>(bs) * bs;
+  for (int s = rp[row]; s < rp[row + 1]; ++s) {
+    const int j = ci[s];
+    const T* xj = x + static_cast<size_t>(j) * bs;
+    if (tpos) {   // (M_ji)^T[r][c] = M_ji[c][r], stored at r * bs + c
+      const T* b = blk + static_cast<size_t>(tpos[s]) * bb + static_cast<size_t>(r) * bs;
+      for (int c = 0; c < bs; ++c) acc += b[c] * xj[c];
+    } else {
+      const T* b = blk + static_cast<size_t>(s) * bb + r;
+      for (int c = 0; c < bs; ++c) acc += b[static_cast<size_t>(c) * bs] * xj[c];
+    }
+  }
+  const size_t o = static_cast<size_t>(row) * bs + r;
+  out[o] = beta != T(0) ? alpha * acc + beta * z[o] : alpha * acc;
+}
+
+// expand pooled FP64 blocks (row-major) into the device layout of type T
+template <typename T>
+__global__ void k_expand(long long nslots, int bs, int V, const int* __restrict__ ids,
+                         const double* __restrict__ pool, T* __restrict__ out, int transpose) {
+  const long long bb = static_cast<long long>(bs) * bs;
+  const long long total = nslots * bb;
+  for (long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const long long s = t / bb;
+    const int e = static_cast<int>(t - s * bb);
+    const int r = e / bs, c = e - (e / bs) * bs;
+    const double v = transpose ? pool[ids[s] * bb + static_cast<long long>(c) * bs + r]
+                               : pool[ids[s] * bb + e];
+    const size_t dst = (static_cast<size_t>(c / V) * bs + r) * V + (c % V);
+    out[s * bb + dst] = static_cast<T>(v);
+  }
+}
+
+// restriction r_c = I^T r_f: one thread per (coarse element, component, coarse dof)
+template <typename T>
+__global__ void k_restrict(int dim, int nc, int ncomp, int bss, const T* __restrict__ Ic,
+                           const T* __restrict__ rf, T* __restrict__ rc) {
+  long long nce = nc;
+  for (int k = 1; k < dim; ++k) nce *= nc;
+  const long long total = nce * ncomp * bss;
+  const long long tid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= total) return;
+  const int a = static_cast<int>(tid % bss);
+  const long long rest = tid / bss;
+  const int comp = static_cast<int>(rest % ncomp);
+  const long long K = rest / ncomp;
+  const int nf = 2 * nc;
+  const int kx = static_cast<int>(K % nc), ky = static_cast<int>((K / nc) % nc);
+  const int kz = dim == 3 ? static_cast<int>(K / (static_cast<long long>(nc) * nc)) : 0;
+  T sum = T(0);
+  const int nchild = 1 << dim;
+  for (int cp = 0; cp < nchild; ++cp) {
+    const long long fx = 2 * kx + (cp & 1), fy = 2 * ky + ((cp >> 1) & 1);
+    const long long fz = dim == 3 ? 2 * kz + ((cp >> 2) & 1) : 0;
+    const long long f = fx + nf * (fy + static_cast<long long>(nf) * fz);
+    const T* rfe = rf + (f * ncomp + comp) * bss;
+    const T* I = Ic + static_cast<size_t>(cp) * bss * bss;
+    for (int b = 0; b < bss; ++b) sum += I[static_cast<size_t>(b) * bss + a] * rfe[b];
+  }
+  rc[(K * ncomp + comp) * bss + a] = sum;
+}
+
+// prolongation and correction x_f += I x_c: one thread per (fine element, component, dof)
+template <typename T>
+__global__ void k_prolong_add(int dim, int nc, int ncomp, int bss, const T* __restrict__ Ic,
+                              const T* __restrict__ xc, T* __restrict__ xf) {
+  const int nf = 2 * nc;
+  long long nfe = nf;
+  for (int k = 1; k < dim; ++k) nfe *= nf;
+  const long long total = nfe * ncomp * bss;
+  const long long tid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= total) return;
+  const int b = static_cast<int>(tid % bss);
+  const long long rest = tid / bss;
+  const int comp = static_cast<int>(rest % ncomp);
+  const long long f = rest / ncomp;
+  const int fx = static_cast<int>(f % nf), fy = static_cast<int>((f / nf) % nf);
+  const int fz = dim == 3 ? static_cast<int>(f / (static_cast<long long>(nf) * nf)) : 0;
+  const int cp = (fx & 1) | ((fy & 1) << 1) | ((fz & 1) << 2);
+  const long long K = (fx >> 1) + static_cast<long long>(nc) * ((fy >> 1) + static_cast<long long>(nc) * (fz >> 1));
+  const T* I = Ic + (static_cast<size_t>(cp) * bss + b) * bss;
+  const T* xce = xc + (K * ncomp + comp) * bss;
+  T sum = T(0);
+  for (int a = 0; a < bss; ++a) sum += I[a] * xce[a];
+  xf[tid] += sum;
+}
+
+// dense FP64 GEMV (bottom pseudo-inverse): one wavefront per row
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_gemv(int N, const double* __restrict__ P,
+                                                    const T* __restrict__ in, T* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  double s = 0.0;
+  const double* pr = P + static_cast<size_t>(row) * N;
+  for (int c = lane; c < N; c += 64) s += pr[c] * static_cast<double>(in[c]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) out[row] = static_cast<T>(s);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 vector kernels of the Krylov iterations
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[kRedThreads / 64];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kRedThreads / 64; ++i) t += sh[i];
+  return t;   // valid in thread 0
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_dot(long long n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ partial) {
+  double s = 0.0;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    s += a[i] * b[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// x += alpha p; r -= alpha q; partial sums of r.r   (alpha = scal[ia])
+__global__ __launch_bounds__(kRedThreads) void k_cg_update(long long n, double* __restrict__ x,
+                                                           double* __restrict__ r,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ q,
+                                                           const double* __restrict__ scal, int ia,
+                                                           double* __restrict__ partial) {
+  const double alpha = scal[ia];
+  double s = 0.0;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// p = z + beta p   (beta = scal[ib])
+__global__ void k_cg_dir(long long n, double* __restrict__ p, const double* __restrict__ z,
+                         const double* __restrict__ scal, int ib) {
+  const double beta = scal[ib];
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+// reduce partial sums in a fixed order and update the scalar table:
+//   op 0: scal[dst] = v
+//   op 1: scal[dst] = scal[a] / v
+//   op 2: scal[dst] = v / scal[a]; scal[a] = v
+__global__ __launch_bounds__(kRedThreads) void k_finalize(int nparts, const double* __restrict__ partial,
+                                                          double* __restrict__ scal, int op, int dst,
+                                                          int a) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += partial[i];
+  const double v = block_sum(s);
+  if (threadIdx.x == 0) {
+    if (op == 0) {
+      scal[dst] = v;
+    } else if (op == 1) {
+      scal[dst] = scal[a] / v;
+    } else {
+      scal[dst] = v / scal[a];
+      scal[a] = v;
+    }
+  }
+}
+
+template <typename S, typename D>
+__global__ void k_cast(long long n, const S* __restrict__ in, D* __restrict__ out) {
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    out[i] = static_cast<D>(in[i]);
+}
+
+// y = alpha x + beta y with alpha, beta from the scalar table (index < 0 -> literal)
+__global__ void k_axpby(long long n, const double* __restrict__ x, double* __restrict__ y,
+                        const double* __restrict__ scal, int ia, double alpha_lit, int ib,
+                        double beta_lit) {
+  const double alpha = ia >= 0 ? scal[ia] : alpha_lit;
+  const double beta = ib >= 0 ? scal[ib] : beta_lit;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    y[i] = alpha * x[i] + (beta == 0.0 ? 0.0 : beta * y[i]);
+}
+
+// y = x / sqrt(scal[i])  (normalise by a stored squared norm)
+__global__ void k_scale_invsqrt(long long n, const double* __restrict__ x, double* __restrict__ y,
+                                const double* __restrict__ scal, int i) {
+  const double s = 1.0 / sqrt(scal[i]);
+  for (long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += static_cast<long long>(gridDim.x) * blockDim.x)
+    y[t] = x[t] * s;
+}
+
+// partial[j][blk] = sum over the block's chunk of Q_j . w   (blockIdx.y = j)
+__global__ __launch_bounds__(kRedThreads) void k_mdot(long long n, const double* __restrict__ Q,
+                                                      const double* __restrict__ w,
+                                                      double* __restrict__ partial) {
+  const int j = blockIdx.y;
+  const double* q = Q + static_cast<size_t>(j) * n;
+  double s = 0.0;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    s += q[i] * w[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) partial[static_cast<size_t>(j) * gridDim.x + blockIdx.x] = t;
+}
+
+// out[j] = sum_b partial[j][b]  (one block per j, fixed order)
+__global__ __launch_bounds__(kRedThreads) void k_finalize_many(int nparts, const double* __restrict__ partial,
+                                                               double* __restrict__ out) {
+  double s = 0.0;
+  const double* p = partial + static_cast<size_t>(blockIdx.x) * nparts;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += p[i];
+  const double v = block_sum(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+// w += sign * sum_{j<k} h[j] Q_j
+__global__ void k_maxpy(long long n, int k, const double* __restrict__ Q, const double* __restrict__ h,
+                        double sign, double* __restrict__ w) {
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += h[j] * Q[static_cast<size_t>(j) * n + i];
+    w[i] += sign * s;
+  }
+}
+
+void check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int grid_for(long long n, int threads, int cap = 4096) {
+  long long g = (n + threads - 1) / threads;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return static_cast<int>(g);
+}
+
+template <typename T, int BS>
+void launch_fwd_bs(const BsrArgs<T>& a, hipStream_t st) {
+  constexpr int G = 64 / BS;
+  const long long waves = (a.nrows + G - 1) / G;
+  const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
+  if (blocks == 0) return;
+  if (a.dinv)
+    k_bsr_fwd<T, BS, 1><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
+                                                     a.alpha, a.beta, a.dinv, a.omega);
+  else
+    k_bsr_fwd<T, BS, 0><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
+                                                     a.alpha, a.beta, nullptr, T(0));
+  check_launch("bsr_fwd");
+}
+
+template <typename T, int BS>
+void launch_tr_bs(const BsrArgs<T>& a, hipStream_t st) {
+  constexpr int G = 64 / BS;
+  const long long waves = (a.nrows + G - 1) / G;
+  const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
+  if (blocks == 0) return;
+  k_bsr_tr<T, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.rp, a.ci, a.tpos, a.blk, a.x, a.z, a.out,
+                                               a.alpha, a.beta);
+  check_launch("bsr_tr");
+}
+
+#define LDGMG_FOR_BS(X) X(4) X(8) X(9) X(12) X(16) X(25) X(27) X(32) X(36) X(48) X(64)
+
+}  // namespace
+
+bool fast_bs(int bs) {
+  switch (bs) {
+#define CASE(B) case B:
+    LDGMG_FOR_BS(CASE)
+#undef CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T>
+void bsr_forward(const BsrArgs<T>& a, hipStream_t st) {
+  switch (a.bs) {
+#define CASE(B) \
+  case B:       \
+    launch_fwd_bs<T, B>(a, st); \
+    return;
+    LDGMG_FOR_BS(CASE)
+#undef CASE
+    default:
+      break;
+  }
+  if (a.dinv) throw std::runtime_error("fused smoothing needs a block size <= 64");
+  const long long n = static_cast<long long>(a.nrows) * a.bs;
+  if (n == 0) return;
+  k_bsr_generic<T><<<static_cast<int>((n + 255) / 256), 256, 0, st>>>(a.nrows, a.bs, a.rows, a.rp, a.ci,
+                                                                        nullptr, a.blk, a.x, a.z, a.out,
+                                                                        a.alpha, a.beta);
+  check_launch("bsr_generic");
+}
+
+template <typename T>
+void bsr_transposed(const BsrArgs<T>& a, hipStream_t st) {
+  switch (a.bs) {
+#define CASE(B) \
+  case B:       \
+    launch_tr_bs<T, B>(a, st); \
+    return;
+    LDGMG_FOR_BS(CASE)
+#undef CASE
+    default:
+      break;
+  }
+  const long long n = static_cast<long long>(a.nrows) * a.bs;
+  if (n == 0) return;
+  k_bsr_generic<T><<<static_cast<int>((n + 255) / 256), 256, 0, st>>>(a.nrows, a.bs, nullptr, a.rp, a.ci,
+                                                                        a.tpos, a.blk, a.x, a.z, a.out,
+                                                                        a.alpha, a.beta);
+  check_launch("bsr_generic_t");
+}
+
+template <typename T>
+void expand_blocks(long long nslots, int bs, const int* ids, const double* pool, T* out, bool transpose,
+                   hipStream_t st) {
+  if (nslots == 0) return;
+  const int V = device_vec_width(bs, sizeof(T));
+  const long long total = nslots * bs * bs;
+  k_expand<T><<<grid_for(total, 256, 65536), 256, 0, st>>>(nslots, bs, V, ids, pool, out, transpose ? 1 : 0);
+  check_launch("expand");
+}
+
+template <typename T>
+void restrict_op(int dim, int nc, int ncomp, int bss, const T* Ic, const T* rf, T* rc, hipStream_t st) {
+  long long nce = nc;
+  for (int k = 1; k < dim; ++k) nce *= nc;
+  const long long total = nce * ncomp * bss;
+  k_restrict<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, rf, rc);
+  check_launch("restrict");
+}
+
+template <typename T>
+void prolong_add(int dim, int nc, int ncomp, int bss, const T* Ic, const T* xc, T* xf, hipStream_t st) {
+  long long nfe = 2 * nc;
+  for (int k = 1; k < dim; ++k) nfe *= 2 * nc;
+  const long long total = nfe * ncomp * bss;
+  k_prolong_add<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, xc, xf);
+  check_launch("prolong");
+}
+
+template <typename T>
+void dense_gemv(int N, const double* P, const T* in, T* out, hipStream_t st) {
+  k_dense_gemv<T><<<(N + 3) / 4, 256, 0, st>>>(N, P, in, out);
+  check_launch("dense_gemv");
+}
+
+void dot_partial(long long n, const double* a, const double* b, double* partial, hipStream_t st) {
+  k_dot<<<kRedBlocks, kRedThreads, 0, st>>>(n, a, b, partial);
+  check_launch("dot");
+}
+
+void finalize(const double* partial, double* scal, int op, int dst, int a, hipStream_t st) {
+  k_finalize<<<1, kRedThreads, 0, st>>>(kRedBlocks, partial, scal, op, dst, a);
+  check_launch("finalize");
+}
+
+void cg_update(long long n, double* x, double* r, const double* p, const double* q, const double* scal,
+               int ia, double* partial, hipStream_t st) {
+  k_cg_update<<<kRedBlocks, kRedThreads, 0, st>>>(n, x, r, p, q, scal, ia, partial);
+  check_launch("cg_update");
+}
+
+void cg_dir(long long n, double* p, const double* z, const double* scal, int ib, hipStream_t st) {
+  k_cg_dir<<<grid_for(n, 256), 256, 0, st>>>(n, p, z, scal, ib);
+  check_launch("cg_dir");
+}
+
+void axpby(long long n, const double* x, double* y, const double* scal, int ia, double alpha, int ib,
+           double beta, hipStream_t st) {
+  k_axpby<<<grid_for(n, 256), 256, 0, st>>>(n, x, y, scal, ia, alpha, ib, beta);
+  check_launch("axpby");
+}
+
+void scale_invsqrt(long long n, const double* x, double* y, const double* scal, int i, hipStream_t st) {
+  k_scale_invsqrt<<<grid_for(n, 256), 256, 0, st>>>(n, x, y, scal, i);
+  check_launch("scale_invsqrt");
+}
+
+template <typename S, typename D>
+void cast(long long n, const S* in, D* out, hipStream_t st) {
+  k_cast<S, D><<<grid_for(n, 256), 256, 0, st>>>(n, in, out);
+  check_launch("cast");
+}
+
+void mdot(long long n, int k, const double* Q, const double* w, double* partial, double* out, hipStream_t st) {
+  dim3 grid(kMdotBlocks, k);
+  k_mdot<<<grid, kRedThreads, 0, st>>>(n, Q, w, partial);
+  check_launch("mdot");
+  k_finalize_many<<<k, kRedThreads, 0, st>>>(kMdotBlocks, partial, out);
+  check_launch("finalize_many");
+}
+
+void maxpy(long long n, int k, const double* Q, const double* h, double sign, double* w, hipStream_t st) {
+  k_maxpy<<<grid_for(n, 256), 256, 0, st>>>(n, k, Q, h, sign, w);
+  check_launch("maxpy");
+}
+
+template void bsr_forward<float>(const BsrArgs<float>&, hipStream_t);
+template void bsr_forward<double>(const BsrArgs<double>&, hipStream_t);
+template void bsr_transposed<float>(const BsrArgs<float>&, hipStream_t);
+template void bsr_transposed<double>(const BsrArgs<double>&, hipStream_t);
+template void expand_blocks<float>(long long, int, const int*, const double*, float*, bool, hipStream_t);
+template void expand_blocks<double>(long long, int, const int*, const double*, double*, bool, hipStream_t);
+template void restrict_op<float>(int, int, int, int, const float*, const float*, float*, hipStream_t);
+template void restrict_op<double>(int, int, int, int, const double*, const double*, double*, hipStream_t);
+template void prolong_add<float>(int, int, int, int, const float*, const float*, float*, hipStream_t);
+template void prolong_add<double>(int, int, int, int, const double*, const double*, double*, hipStream_t);
+template void dense_gemv<float>(int, const double*, const float*, float*, hipStream_t);
+template void dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);
+template void cast<double, float>(long long, const double*, float*, hipStream_t);
+template void cast<float, double>(long long, const float*, double*, hipStream_t);
+
+}  // namespace ldgmg

@@ -1,0 +1,72 @@
+// Launch wrappers of the HIP kernels (kernels.hip).  All pointers are device
+// pointers; every wrapper enqueues on `st` and throws std::runtime_error if the
+// launch fails.  Sizes are trusted: the callers (device.hip) derive them from
+// the hierarchy that allocated the buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ldgmg {
+
+constexpr int kRedBlocks = 1024;   // partial sums per dot product
+constexpr int kRedThreads = 256;
+constexpr int kMdotBlocks = 256;   // partial sums per vector of a multi-dot
+
+// block sizes with a specialised (wave-mapped) kernel; others use the generic one
+bool fast_bs(int bs);
+
+// elements per vector load in the device block layout for block size bs
+inline int device_vec_width(int bs, int elem_bytes) {
+  if (!fast_bs(bs)) return 1;
+  if (elem_bytes == 4) return bs % 4 == 0 ? 4 : 1;
+  return bs % 2 == 0 ? 2 : 1;
+}
+
+template <typename T>
+struct BsrArgs {
+  int nrows = 0;              // block rows to process
+  int bs = 0;
+  const int* rows = nullptr;  // optional list of block rows (nrows entries)
+  const int* rp = nullptr;    // row pointer [nblockrows + 1]
+  const int* ci = nullptr;    // block columns [nnzb]
+  const int* tpos = nullptr;  // transposed kernel: slot of (j,i) for slot (i,j)
+  const T* blk = nullptr;     // blocks [nnzb][bs*bs], device layout
+  const T* x = nullptr;       // input vector
+  const T* z = nullptr;       // added vector (MODE 0) / right-hand side (fused smoothing)
+  T* out = nullptr;
+  T alpha = T(1), beta = T(0);
+  const T* dinv = nullptr;    // fused smoothing: block inverses indexed by block row
+  T omega = T(1);
+};
+
+// out = alpha M x + beta z, or (dinv != null) out = x + omega Dinv (z - M x)
+template <typename T> void bsr_forward(const BsrArgs<T>& a, hipStream_t st);
+// out = alpha M^T x + beta z  (rows must be null; tpos required)
+template <typename T> void bsr_transposed(const BsrArgs<T>& a, hipStream_t st);
+// pooled FP64 row-major blocks -> device layout of T (optionally transposed)
+template <typename T>
+void expand_blocks(long long nslots, int bs, const int* ids, const double* pool, T* out, bool transpose,
+                   hipStream_t st);
+template <typename T>
+void restrict_op(int dim, int nc, int ncomp, int bss, const T* Ic, const T* rf, T* rc, hipStream_t st);
+template <typename T>
+void prolong_add(int dim, int nc, int ncomp, int bss, const T* Ic, const T* xc, T* xf, hipStream_t st);
+template <typename T> void dense_gemv(int N, const double* P, const T* in, T* out, hipStream_t st);
+
+void dot_partial(long long n, const double* a, const double* b, double* partial, hipStream_t st);
+// op 0: scal[dst] = v;  op 1: scal[dst] = scal[a] / v;  op 2: scal[dst] = v / scal[a], scal[a] = v
+void finalize(const double* partial, double* scal, int op, int dst, int a, hipStream_t st);
+void cg_update(long long n, double* x, double* r, const double* p, const double* q, const double* scal,
+               int ia, double* partial, hipStream_t st);
+void cg_dir(long long n, double* p, const double* z, const double* scal, int ib, hipStream_t st);
+// y = alpha x + beta y; alpha = scal[ia] if ia >= 0 else the literal (same for beta)
+void axpby(long long n, const double* x, double* y, const double* scal, int ia, double alpha, int ib,
+           double beta, hipStream_t st);
+void scale_invsqrt(long long n, const double* x, double* y, const double* scal, int i, hipStream_t st);
+template <typename S, typename D> void cast(long long n, const S* in, D* out, hipStream_t st);
+// out[j] = Q_j . w for j < k (Q: k vectors of length n, contiguous); partial: k * kMdotBlocks
+void mdot(long long n, int k, const double* Q, const double* w, double* partial, double* out, hipStream_t st);
+// w += sign * sum_{j<k} h[j] Q_j   (h on the device)
+void maxpy(long long n, int k, const double* Q, const double* h, double sign, double* w, hipStream_t st);
+
+}  // namespace ldgmg

@@ -1,0 +1,302 @@
+"""Thin ctypes binding of libldgmg.so (the C-ABI declared in include/ldgmg.h).
+
+Argument marshalling only: every step of the solver runs in the library.
+Device vectors are passed as torch tensors (their data_ptr) or raw integer
+addresses; streams as torch streams, raw hipStream_t integers or None.
+The library must have been built (paper_2412_12506_amd/build.py); importing
+this module does not load it, the first call does and raises if it is absent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldgmg.so")
+
+# enums (include/ldgmg.h)
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESINGULAR, ESTATE = 0, -1, -2, -3, -4, -5, -6
+POISSON, STOKES = 0, 1
+BASIS = {"legendre": 0, "gl_nodal": 1}
+BC = {"D": 0, "N": 1, "P": 2}
+SMOOTHER = {"jacobi": 0, "gs": 1, "sai": 2}
+ORDER = {"OO": 0, "OI": 1, "IO": 2, "II": 3}
+PRECISION = {"fp64": 0, "fp32": 1}
+KRYLOV = {"cg": 0, "gmres": 1}
+OP = {"residual": 0, "apply_a": 1, "apply_s": 2, "apply_st": 3, "smooth_fwd": 4,
+      "smooth_rev": 5, "restrict": 6, "prolong_add": 7, "bottom": 8, "apply_a64": 9}
+EXPORT = {"A": 0, "S": 1, "PINV": 2}
+
+
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int), ("p", C.c_int), ("basis", C.c_int),
+                ("system", C.c_int), ("gamma", C.c_int), ("bc", C.c_int * 6),
+                ("mu", C.POINTER(C.c_double)), ("tau0", C.c_double), ("cp", C.c_double),
+                ("smoother", C.c_int), ("sai_level", C.c_int), ("order", C.c_int),
+                ("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("zeta", C.c_double),
+                ("precision", C.c_int), ("nthreads", C.c_int), ("hbm_budget", C.c_size_t)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_res_true", C.c_double),
+                ("rel_res_krylov", C.c_double), ("eta", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int),
+                ("history_len", C.c_int), ("vcycles", C.c_int)]
+
+
+class LdgmgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ldgmg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_upload",
+           "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
+           "ldgmg_solve", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
+           "ldgmg_setup_stats", "ldgmg_destroy", "ldgmg_last_error"]
+
+
+def lib():
+    """Load libldgmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2412_12506_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+    H = C.c_void_p
+    L.ldgmg_problem_default.argtypes = [C.POINTER(Problem)]
+    L.ldgmg_estimate_bytes.argtypes = [C.POINTER(Problem), C.POINTER(C.c_size_t)]
+    L.ldgmg_setup_host.argtypes = [C.POINTER(Problem), C.POINTER(H)]
+    L.ldgmg_upload.argtypes = [H, vp]
+    L.ldgmg_setup.argtypes = [C.POINTER(Problem), vp, C.POINTER(H)]
+    L.ldgmg_sizes.argtypes = [H, C.POINTER(C.c_longlong), ip, ip]
+    L.ldgmg_level_info.argtypes = [H, C.c_int, ip, ip, ip, ip, ip]
+    L.ldgmg_rhs_volume.argtypes = [H, dp, C.c_int, vp, vp]
+    L.ldgmg_vcycle.argtypes = [H, vp, vp, vp]
+    L.ldgmg_solve.argtypes = [H, vp, vp, C.c_int, C.c_double, C.c_int, C.POINTER(Info), vp]
+    L.ldgmg_level_op.argtypes = [H, C.c_int, C.c_int, vp, vp, vp, vp]
+    L.ldgmg_export.argtypes = [H, C.c_int, C.c_int, ip, ip, dp, ip, ip]
+    L.ldgmg_export_colours.argtypes = [H, C.c_int, ip]
+    L.ldgmg_setup_stats.argtypes = [H, C.c_int, ip, dp]
+    L.ldgmg_destroy.argtypes = [H]
+    L.ldgmg_last_error.argtypes = []
+    L.ldgmg_last_error.restype = C.c_char_p
+    for s in SYMBOLS[:-1]:
+        getattr(L, s).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, allow=()):
+    if rc != OK and rc not in allow:
+        raise LdgmgError(rc, lib().ldgmg_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def ldgmg_problem_default() -> Problem:
+    p = Problem()
+    _check(lib().ldgmg_problem_default(C.byref(p)))
+    return p
+
+
+def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str = "legendre",
+                 gamma: int = 1, bc=None, mu=None, tau0: float = 1.0, cp: float = 0.1,
+                 smoother: str = "sai", sai_level: int = 1, order: str = "OI", nu1: int = 3,
+                 nu2: int = 3, omega: float = 0.0, zeta: float = 0.0, precision: str = "fp32",
+                 nthreads: int = 0, hbm_budget: int = 0):
+    """Problem struct plus the numpy array that backs `mu` (keep both alive)."""
+    pr = ldgmg_problem_default()
+    pr.dim, pr.n, pr.p = dim, n, p
+    pr.system = POISSON if system == "poisson" else STOKES
+    pr.basis = BASIS[basis]
+    pr.gamma = gamma
+    bc = bc or ["D"] * (2 * dim)
+    for i in range(6):
+        pr.bc[i] = BC[bc[i]] if i < len(bc) else 0
+    mu_arr = None
+    if mu is not None:
+        mu_arr = np.ascontiguousarray(mu, dtype=np.float64)
+        if mu_arr.size != n ** dim:
+            raise ValueError("mu must have n^dim entries")
+        pr.mu = mu_arr.ctypes.data_as(C.POINTER(C.c_double))
+    pr.tau0, pr.cp = tau0, cp
+    pr.smoother = SMOOTHER[smoother]
+    pr.sai_level = sai_level
+    pr.order = ORDER[order]
+    pr.nu1, pr.nu2 = nu1, nu2
+    pr.omega, pr.zeta = omega, zeta
+    pr.precision = PRECISION[precision]
+    pr.nthreads = nthreads
+    pr.hbm_budget = hbm_budget
+    return pr, mu_arr
+
+
+def ldgmg_estimate_bytes(problem: Problem) -> int:
+    out = C.c_size_t(0)
+    _check(lib().ldgmg_estimate_bytes(C.byref(problem), C.byref(out)))
+    return out.value
+
+
+def ldgmg_setup_host(problem: Problem) -> int:
+    h = C.c_void_p()
+    _check(lib().ldgmg_setup_host(C.byref(problem), C.byref(h)))
+    return h.value
+
+
+def ldgmg_upload(h: int, stream=None):
+    _check(lib().ldgmg_upload(h, _stream(stream)))
+
+
+def ldgmg_setup(problem: Problem, stream=None) -> int:
+    h = C.c_void_p()
+    _check(lib().ldgmg_setup(C.byref(problem), _stream(stream), C.byref(h)))
+    return h.value
+
+
+def ldgmg_sizes(h: int):
+    nd, bs, nl = C.c_longlong(), C.c_int(), C.c_int()
+    _check(lib().ldgmg_sizes(h, C.byref(nd), C.byref(bs), C.byref(nl)))
+    return nd.value, bs.value, nl.value
+
+
+def ldgmg_level_info(h: int, level: int):
+    v = [C.c_int() for _ in range(5)]
+    _check(lib().ldgmg_level_info(h, level, *[C.byref(x) for x in v]))
+    return dict(zip(["n", "nelem", "nnzb_A", "nnzb_S", "ncolours"], [x.value for x in v]))
+
+
+def ldgmg_rhs_volume(h: int, f_qp: np.ndarray, nq: int, b, stream=None):
+    f = np.ascontiguousarray(f_qp, dtype=np.float64)
+    _check(lib().ldgmg_rhs_volume(h, f.ctypes.data_as(C.POINTER(C.c_double)), nq, _ptr(b),
+                                  _stream(stream)))
+
+
+def ldgmg_vcycle(h: int, b, x, stream=None):
+    _check(lib().ldgmg_vcycle(h, _ptr(b), _ptr(x), _stream(stream)))
+
+
+def ldgmg_solve(h: int, b, x, krylov: str = "cg", rtol: float = 1e-10, maxit: int = 200,
+                stream=None, history_cap: int = 256) -> dict:
+    hist = np.zeros(history_cap)
+    info = Info()
+    info.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+    info.history_cap = history_cap
+    rc = _check(lib().ldgmg_solve(h, _ptr(b), _ptr(x), KRYLOV[krylov], rtol, maxit,
+                                  C.byref(info), _stream(stream)), allow=(ENOCONV,))
+    return {"iters": info.iters, "converged": bool(info.converged),
+            "rel_res_true": info.rel_res_true, "rel_res_krylov": info.rel_res_krylov,
+            "eta": info.eta, "history": hist[: info.history_len].copy(),
+            "vcycles": info.vcycles, "status": rc}
+
+
+def ldgmg_level_op(h: int, level: int, op: str, in1, in2, out, stream=None):
+    _check(lib().ldgmg_level_op(h, level, OP[op], _ptr(in1), _ptr(in2), _ptr(out),
+                                _stream(stream)))
+
+
+def ldgmg_export(h: int, level: int, what: str):
+    """Host FP64 export: (row_ptr, col, blocks[nnzb, bs, bs]) or a dense array (PINV)."""
+    L = lib()
+    nnzb, dn = C.c_int(0), C.c_int(0)
+    _check(L.ldgmg_export(h, level, EXPORT[what], None, None, None, C.byref(nnzb), C.byref(dn)))
+    if what == "PINV":
+        N = dn.value
+        out = np.zeros((N, N))
+        _check(L.ldgmg_export(h, level, EXPORT[what], None, None,
+                              out.ctypes.data_as(C.POINTER(C.c_double)), None, C.byref(dn)))
+        return out
+    _, bs, _ = ldgmg_sizes(h)
+    info = ldgmg_level_info(h, level)
+    ne = info["nelem"]
+    bs = bs  # same block size on every level
+    rp = np.zeros(ne + 1, dtype=np.int32)
+    ci = np.zeros(nnzb.value, dtype=np.int32)
+    blocks = np.zeros((nnzb.value, bs, bs))
+    _check(L.ldgmg_export(h, level, EXPORT[what], rp.ctypes.data_as(C.POINTER(C.c_int)),
+                          ci.ctypes.data_as(C.POINTER(C.c_int)),
+                          blocks.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nnzb), None))
+    return rp, ci, blocks
+
+
+def ldgmg_export_colours(h: int, level: int) -> np.ndarray:
+    ne = ldgmg_level_info(h, level)["nelem"]
+    out = np.zeros(ne, dtype=np.int32)
+    _check(lib().ldgmg_export_colours(h, level, out.ctypes.data_as(C.POINTER(C.c_int))))
+    return out
+
+
+def ldgmg_setup_stats(h: int, level: int):
+    u, s = C.c_int(), C.c_double()
+    _check(lib().ldgmg_setup_stats(h, level, C.byref(u), C.byref(s)))
+    return u.value, s.value
+
+
+def ldgmg_destroy(h: int):
+    if h:
+        lib().ldgmg_destroy(h)
+
+
+def export_bsr(h: int, level: int, what: str = "A"):
+    """Export as a scipy BSR matrix (test helper)."""
+    import scipy.sparse as sp
+    rp, ci, blocks = ldgmg_export(h, level, what)
+    ne = rp.size - 1
+    bs = blocks.shape[1]
+    return sp.bsr_matrix((blocks, ci, rp), shape=(ne * bs, ne * bs))
+
+
+class Solver:
+    """Owns one handle.  Example:
+        s = Solver(dim=3, n=16, p=3); s.upload(); info = s.solve(b, x)
+    """
+
+    def __init__(self, host_only: bool = False, stream=None, **kw):
+        self.problem, self._mu = make_problem(**kw)
+        self.handle = ldgmg_setup_host(self.problem)
+        self.ndofs, self.bs, self.nlevels = ldgmg_sizes(self.handle)
+        if not host_only:
+            self.upload(stream)
+
+    def upload(self, stream=None):
+        ldgmg_upload(self.handle, stream)
+
+    def vcycle(self, b, x, stream=None):
+        ldgmg_vcycle(self.handle, b, x, stream)
+
+    def solve(self, b, x, krylov="cg", rtol=1e-10, maxit=200, stream=None):
+        return ldgmg_solve(self.handle, b, x, krylov, rtol, maxit, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ldgmg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
