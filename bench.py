@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the multigrid hot path on one MI355X.
+
+Workload (default): 3D Poisson, LDG Q_3 (64 unknowns per element, Legendre
+basis), uniform 64^3 grid of the unit cube (16,777,216 unknowns), Dirichlet
+boundaries, seeded N(0,1) right-hand sides; SAI_1 (OI ordering) V-cycle with
+FP32 block storage and FP64 arithmetic as the preconditioner of FP64 CG, solved
+to a 1e-10 relative residual.  One step = one full solve from x0 = 0 (every
+stage of the path: residuals, SAI applies, transfers, bottom solve, V-cycle
+control, CG).  Inputs are resident in HBM before the timed region.
+
+Printed JSON (one line on stdout):
+  value        V-cycle DOF/s = fine unknowns x V-cycles in the timed solves / time
+  solves_per_s, p50_ms / p99_ms per solve, iterations, eta, true residual
+  fp64_path    the same solves with FP64 block storage (same MI355X)
+  roofline     the dominant kernel (forward BSR apply with FP32 blocks on the
+               fine level), timed with HIP events inside the library over the
+               timed region; algorithmic bytes per launch / mean duration
+  cpu_baseline the CPU oracle timed on this host on a bounded sample
+Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "V-cycle DOF/s & solves/s to 1e-10 rel. residual (FP32 vs FP64); p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+def run_path(L, torch, args, precision, rhs, prof):
+    """Set up one precision, warm up, time args.steps solves.  Returns stats."""
+    t0 = time.time()
+    s = L.Solver(dim=3, n=args.n, p=args.p, smoother="sai", sai_level=1, order="OI",
+                 precision=precision)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    log(f"[{precision}] setup {setup_s:.1f}s ndofs {s.ndofs} levels {s.nlevels}")
+    x = torch.empty_like(rhs[0])
+    for i in range(args.warmup):
+        info = s.solve(rhs[i], x, "cg", 1e-10, 200)
+        log(f"[{precision}] warmup {i}: iters {info['iters']}")
+    stream = torch.cuda.current_stream()
+    if prof:
+        L.ldgmg_profile(s.handle, True)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    infos = []
+    t0 = time.time()
+    for k in range(args.steps):
+        b = rhs[args.warmup + k]
+        ev[k][0].record(stream)
+        info = s.solve(b, x, "cg", 1e-10, 200, stream=stream)
+        ev[k][1].record(stream)
+        infos.append(info)
+        log(f"[{precision}] step {k}: iters {info['iters']} rel_res {info['rel_res_true']:.2e}")
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    lat = [a.elapsed_time(b) for a, b in ev]
+    total_ms = ev[0][0].elapsed_time(ev[-1][1])
+    vcycles = sum(i["vcycles"] for i in infos)
+    out = {
+        "setup_s": setup_s,
+        "total_ms": total_ms,
+        "wall_s": wall,
+        "ms_per_solve": total_ms / args.steps,
+        "solves_per_s": 1000.0 * args.steps / total_ms,
+        "vcycle_dof_per_s": s.ndofs * vcycles / (total_ms / 1000.0),
+        "p50_ms": percentile(lat, 50),
+        "p99_ms": percentile(lat, 99),
+        "iters": [i["iters"] for i in infos],
+        "eta": float(sum(i["eta"] for i in infos) / len(infos)),
+        "rel_res_true_max": max(i["rel_res_true"] for i in infos),
+        "vcycles": vcycles,
+        "ndofs": s.ndofs,
+    }
+    if prof:
+        info0 = L.ldgmg_level_info(s.handle, 0)
+        bs = s.bs
+        N = s.ndofs
+        ne = info0["nelem"]
+        eb = 4 if precision == "fp32" else 8
+        kinds = {}
+        for kind in ("A", "S", "ST", "A64"):
+            cnt, ms = L.ldgmg_profile_read(s.handle, kind)
+            nnzb = info0["nnzb_A"] if kind in ("A", "A64") else info0["nnzb_S"]
+            ebk = 8 if kind == "A64" else eb
+            # algorithmic bytes per launch: stored blocks + block indices + vectors
+            # (FP64 input read, FP64 added vector read, FP64 output written)
+            vec = 3 * N * 8 if kind != "A64" else 2 * N * 8
+            idx = (ne + 1) * 4 + nnzb * 4 + (nnzb * 4 if kind == "ST" else 0)
+            byts = nnzb * bs * bs * ebk + idx + vec
+            kinds[kind] = {"count": cnt, "ms_total": ms, "bytes_per_launch": byts,
+                           "mean_ms": ms / cnt if cnt else None,
+                           "gbs": (byts / (ms / cnt) / 1e6) if cnt else None}
+        out["kernels"] = kinds
+        L.ldgmg_profile(s.handle, False)
+    s.close()
+    torch.cuda.synchronize()
+    return out
+
+
+def cpu_baseline(n_cpu):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    3D Poisson Q_3, SAI_1 OI V-cycle in CG, on an n_cpu^3 grid (setup untimed;
+    one full CG solve timed)."""
+    import numpy as np
+    from oracle import solver as osolver
+    from ldg_inputs import rhs_normal
+    t0 = time.time()
+    lv, vc = osolver.build(3, n_cpu, 3)
+    log(f"[cpu] oracle setup {time.time() - t0:.1f}s")
+    b = rhs_normal(lv[0].A.shape[0], 0)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):       # the oracle's products run on one core
+        t0 = time.time()
+        r = osolver.solve(lv, vc, b, "cg")
+        dt = time.time() - t0
+    vcycles = r.iters + 1 - (1 if r.converged else 0)
+    ndofs = b.size
+    return {"value": ndofs * vcycles / dt, "unit": "DOF/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"one FP64 CG solve (to 1e-10, {r.iters} iterations, {vcycles} V-cycles) "
+                       f"of the same workload on a {n_cpu}^3 grid ({ndofs} unknowns), "
+                       f"one host thread (BLAS limited to 1); setup untimed"),
+            "seconds": dt, "solves_per_s": 1.0 / dt, "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=64, help="grid size per side")
+    ap.add_argument("--p", type=int, default=3, help="polynomial degree")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=8, help="grid of the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
+              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2412_12506_amd import ldgmg as L
+    from ldg_inputs import rhs_normal, BASE_SEED
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ndofs = args.n ** 3 * (args.p + 1) ** 3
+    nrhs = args.warmup + args.steps
+    rhs = [torch.from_numpy(rhs_normal(ndofs, BASE_SEED + i)).to(dev) for i in range(nrhs)]
+    torch.cuda.synchronize()
+    fp32 = run_path(L, torch, args, "fp32", rhs, prof=True)
+    fp64 = None if args.no_fp64 else run_path(L, torch, args, "fp64", rhs, prof=False)
+    del rhs
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_n)
+
+    k = fp32["kernels"]
+    # dominant kernel: forward BSR with FP32 blocks on the fine level (A residuals and B applies)
+    cnt = k["A"]["count"] + k["S"]["count"]
+    ms = k["A"]["ms_total"] + k["S"]["ms_total"]
+    byts = (k["A"]["bytes_per_launch"] * k["A"]["count"] + k["S"]["bytes_per_launch"] * k["S"]["count"]) / max(cnt, 1)
+    mean_s = ms / max(cnt, 1) / 1000.0
+    achieved = byts / mean_s / 1e9 if cnt else None
+    roof = {"bound": "hbm", "kernel": "k_bsr_fwd<fp32 blocks, fp64 vectors, bs=64> (fine level)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "launches": cnt, "mean_ms": ms / max(cnt, 1), "bytes_per_launch": byts,
+            "other_kernels": {kk: {"mean_ms": v["mean_ms"], "gbs": v["gbs"], "count": v["count"]}
+                              for kk, v in k.items() if kk in ("ST", "A64")}}
+    line = {
+        "metric": METRIC,
+        "value": fp32["vcycle_dof_per_s"],
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp32["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "block_storage": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"poisson3d_p{args.p}_n{args.n}_sai1_oi_cg",
+                   "fine_dofs": ndofs, "rtol": 1e-10, "rhs": "N(0,1) seeded",
+                   "smoother": "SAI_1 OI, nu1=nu2=3", "outer": "FP64 CG"},
+        "solves_per_s": fp32["solves_per_s"],
+        "p50_ms": fp32["p50_ms"],
+        "p99_ms": fp32["p99_ms"],
+        "iters": fp32["iters"],
+        "eta": fp32["eta"],
+        "rel_res_true_max": fp32["rel_res_true_max"],
+        "setup_s": fp32["setup_s"],
+        "fp64_path": None if fp64 is None else {
+            k2: fp64[k2] for k2 in ("vcycle_dof_per_s", "solves_per_s", "ms_per_solve", "p50_ms",
+                                    "p99_ms", "iters", "rel_res_true_max", "setup_s")},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

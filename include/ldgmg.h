@@ -55,8 +55,11 @@ enum { LDGMG_SMOOTH_JACOBI = 0, LDGMG_SMOOTH_GS = 1, LDGMG_SMOOTH_SAI = 2 };
 /* pre/post ordering (Section 2.4): first letter pre-smoother, second post;
  * O = forward (eq:B1 / colours in order), I = reverse (eq:BT / colours reversed) */
 enum { LDGMG_ORDER_OO = 0, LDGMG_ORDER_OI = 1, LDGMG_ORDER_IO = 2, LDGMG_ORDER_II = 3 };
-/* precision of the V-cycle's matrices, vectors and smoothers; the outer Krylov
- * iteration, its operator and inner products are always FP64 */
+/* storage precision of the V-cycle's matrices (A on every level, the smoother
+ * matrix B or D^-1): FP64 or FP32.  V-cycle vectors, transfers and all
+ * arithmetic are FP64 in both modes (FP32 blocks are widened as they are
+ * read); the outer Krylov iteration, its FP64 operator and inner products are
+ * FP64. */
 enum { LDGMG_FP64 = 0, LDGMG_FP32 = 1 };
 enum { LDGMG_CG = 0, LDGMG_GMRES = 1 };
 
@@ -81,7 +84,7 @@ typedef struct {
   int nu1, nu2;       /* pre/post smoothing steps (paper: 3, 3)                   */
   double omega;       /* damping (Jacobi 0.8, coloured GS 1.0); <= 0 -> default   */
   double zeta;        /* Stokes balancing weight (tab:zeta); <= 0 -> tab:zeta     */
-  int precision;      /* LDGMG_FP64 | LDGMG_FP32                                  */
+  int precision;      /* LDGMG_FP64 | LDGMG_FP32 (block storage of the V-cycle)  */
   int nthreads;       /* host threads for the setup; <= 0 -> hardware count      */
   size_t hbm_budget;  /* refuse ldgmg_upload above this many bytes; 0 = no limit */
 } ldgmg_problem;
@@ -149,8 +152,8 @@ int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov,
                 double rtol, int maxit, ldgmg_info* info, void* stream);
 
 /* Single operations of the V-cycle on one level, for checking each kernel.
- * in1/in2/out are device vectors of the level in the handle's precision
- * (FP32 or FP64 per `precision`; LDGMG_OP_APPLY_A64 is always FP64).
+ * in1/in2/out are device FP64 vectors of the level (ne*bs entries; the
+ * coarse vector of RESTRICT / PROLONG_ADD has the next level's size).
  *   LDGMG_OP_RESIDUAL    out = in2 - A in1                  (b - A x)
  *   LDGMG_OP_APPLY_A     out = A in1
  *   LDGMG_OP_APPLY_S     out = S in1, S = B (SAI) or D^-1 (Jacobi / GS)
@@ -186,6 +189,17 @@ int ldgmg_export_colours(ldgmg_handle h, int level, int* colours);
 /* Setup statistics: unique SAI least-squares problems solved on the level and
  * the host setup time in seconds. */
 int ldgmg_setup_stats(ldgmg_handle h, int level, int* sai_unique, double* seconds);
+
+/* Kernel timing of the fine level (diagnostics, for roofline measurements).
+ * While enabled, every block-sparse launch on level 0 is bracketed by HIP
+ * events on the stream it is launched on.  kind: 0 = A (residual / apply),
+ * 1 = smoother matrix forward, 2 = smoother matrix transposed, 3 = FP64 Krylov
+ * operator, 4 = fused block-inverse smoothing (A and D^-1).
+ * ldgmg_profile_read synchronises the recorded events and returns the launch
+ * count and the summed duration in milliseconds of one kind; enabling again
+ * clears the records.  At most 4096 launches are recorded per enable. */
+int ldgmg_profile(ldgmg_handle h, int enable);
+int ldgmg_profile_read(ldgmg_handle h, int kind, int* count, double* total_ms);
 
 /* Release all host and device memory of the handle. */
 int ldgmg_destroy(ldgmg_handle h);

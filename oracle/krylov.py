@@ -45,7 +45,9 @@ def eta_from_history(hist) -> float:
 
 
 def pcg(A, b, V: Callable, rtol=1e-10, maxit=200) -> SolveResult:
-    """Preconditioned CG (Hestenes-Stiefel form), x0 = 0, z = V r."""
+    """Preconditioned CG (Hestenes-Stiefel form), x0 = 0, z = V r.  The
+    history holds sqrt(r_k^T V r_k) for k = 0 .. iters-1 (no V-cycle is spent
+    on the converged residual)."""
     x = np.zeros_like(b)
     r = b.copy()
     nb = np.linalg.norm(b)
@@ -63,11 +65,10 @@ def pcg(A, b, V: Callable, rtol=1e-10, maxit=200) -> SolveResult:
         it += 1
         if np.linalg.norm(r) <= rtol * nb:
             converged = True
+            break
         z = V(r)
         rz_new = float(r @ z)
         hist.append(np.sqrt(abs(rz_new)))
-        if converged:
-            break
         p = z + (rz_new / rz) * p
         rz = rz_new
     rel = np.linalg.norm(b - A @ x) / nb

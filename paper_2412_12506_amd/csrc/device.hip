@@ -41,6 +41,7 @@ struct StateError : std::runtime_error {
   } while (0)
 
 struct DevLevel {
+  int index = 0;
   int n = 0, ne = 0, bs = 0, bss = 0, ncomp = 1;
   long long N = 0;                  // unknowns on the level
   int nnzA = 0, nnzS = 0;
@@ -53,11 +54,11 @@ struct DevLevel {
   void* valS = nullptr;
   std::vector<int*> colour_rows;    // device lists per colour
   std::vector<int> colour_count;
-  void* x = nullptr;
-  void* b = nullptr;
-  void* r = nullptr;
-  void* t = nullptr;
-  void* Ic = nullptr;               // child injection matrices [2^d][bss][bss] (this level -> its children)
+  double* x = nullptr;              // level vectors are FP64 in both precisions
+  double* b = nullptr;
+  double* r = nullptr;
+  double* t = nullptr;
+  double* Ic = nullptr;             // child injection matrices [2^d][bss][bss]
   double* pinv = nullptr;           // bottom only
 };
 
@@ -76,6 +77,14 @@ struct DevHier {
   double* hvec = nullptr;           // device small vectors (GMRES coefficients)
   std::vector<void*> allocs;
   size_t bytes = 0;
+  // fine-level launch timing (ldgmg_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
 
   void* alloc(size_t n) {
     void* p = nullptr;
@@ -87,6 +96,7 @@ struct DevHier {
     return p;
   }
   ~DevHier() {
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (hscal) (void)hipHostFree(hscal);
   }
@@ -120,14 +130,13 @@ size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long n
   } else {
     b += N * N * 8;
   }
-  b += 4 * N * eb;
-  b += (static_cast<size_t>(1) << dim) * bss * bss * eb;
+  b += 4 * N * 8;
+  b += (static_cast<size_t>(1) << dim) * bss * bss * 8;
   return b;
 }
 
-template <typename T>
-void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hipStream_t st,
-                  const HostLevel* finer) {
+template <typename T>   // T: element type of the stored blocks
+void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hipStream_t st) {
   dl.n = hl.n;
   dl.ne = hl.ne;
   dl.bs = hl.bs;
@@ -173,23 +182,21 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
     dl.pinv = static_cast<double*>(D.alloc(hl.pinv.size() * sizeof(double)));
     HIPCHK(hipMemcpyAsync(dl.pinv, hl.pinv.data(), hl.pinv.size() * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  const size_t vb = static_cast<size_t>(dl.N) * sizeof(T);
-  dl.x = D.alloc(vb);
-  dl.b = D.alloc(vb);
-  dl.r = D.alloc(vb);
-  dl.t = D.alloc(vb);
+  const size_t vb = static_cast<size_t>(dl.N) * sizeof(double);
+  dl.x = static_cast<double*>(D.alloc(vb));
+  dl.b = static_cast<double*>(D.alloc(vb));
+  dl.r = static_cast<double*>(D.alloc(vb));
+  dl.t = static_cast<double*>(D.alloc(vb));
   HIPCHK(hipMemsetAsync(dl.x, 0, vb, st));
   HIPCHK(hipMemsetAsync(dl.r, 0, vb, st));
   HIPCHK(hipMemsetAsync(dl.t, 0, vb, st));
-  // child injection matrices of this level's elements into the finer level (used by the finer level)
-  (void)finer;
+  // child injection matrices (the same for every level: they depend on p only)
   const int nch = 1 << hl.em.dim;
-  std::vector<T> ic(static_cast<size_t>(nch) * hl.bss * hl.bss);
+  std::vector<double> ic(static_cast<size_t>(nch) * hl.bss * hl.bss);
   for (int c = 0; c < nch; ++c)
-    for (size_t t = 0; t < static_cast<size_t>(hl.bss) * hl.bss; ++t)
-      ic[static_cast<size_t>(c) * hl.bss * hl.bss + t] = static_cast<T>(hl.em.Ic[c][t]);
-  dl.Ic = D.alloc(ic.size() * sizeof(T));
-  HIPCHK(hipMemcpyAsync(dl.Ic, ic.data(), ic.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    std::copy(hl.em.Ic[c].begin(), hl.em.Ic[c].end(), ic.begin() + static_cast<size_t>(c) * hl.bss * hl.bss);
+  dl.Ic = static_cast<double*>(D.alloc(ic.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(dl.Ic, ic.data(), ic.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
 }
 
@@ -220,10 +227,11 @@ void upload(ldgmg_hier* h, hipStream_t st) {
   const int nl = static_cast<int>(H.levels.size());
   D->L.resize(nl);
   for (int l = 0; l < nl; ++l) {
+    D->L[l].index = l;
     if (D->prec == LDGMG_FP64)
-      upload_level<double>(*D, D->L[l], H.levels[l], l == nl - 1, st, l ? &H.levels[l - 1] : nullptr);
+      upload_level<double>(*D, D->L[l], H.levels[l], l == nl - 1, st);
     else
-      upload_level<float>(*D, D->L[l], H.levels[l], l == nl - 1, st, l ? &H.levels[l - 1] : nullptr);
+      upload_level<float>(*D, D->L[l], H.levels[l], l == nl - 1, st);
   }
   const HostLevel& F = H.levels[0];
   DevLevel& f = D->L[0];
@@ -267,9 +275,30 @@ struct Ctx {
   hipStream_t st;
 };
 
+// brackets one launch on level 0 with events when profiling is enabled
+struct ProfScope {
+  DevHier& D;
+  hipStream_t st;
+  int kind;
+  hipEvent_t b = nullptr;
+  ProfScope(DevHier& d, const DevLevel& L, hipStream_t s, int k) : D(d), st(s), kind(k) {
+    if (!D.prof || L.index != 0 || D.recs.size() * 2 + 2 > D.evpool.size()) return;
+    hipEvent_t a = D.evpool[D.recs.size() * 2];
+    b = D.evpool[D.recs.size() * 2 + 1];
+    HIPCHK(hipEventRecord(a, st));
+    D.recs.push_back({kind, a, b});
+  }
+  ~ProfScope() {
+    if (b) (void)hipEventRecord(b, st);
+  }
+};
+enum { K_A = 0, K_SF = 1, K_ST = 2, K_A64 = 3, K_FUSED = 4 };
+
+using Vd = double;   // vector / arithmetic type of the V-cycle
+
 template <typename T>
-BsrArgs<T> argsA(const DevLevel& L) {
-  BsrArgs<T> a;
+BsrArgs<T, Vd> argsA(const DevLevel& L) {
+  BsrArgs<T, Vd> a;
   a.nrows = L.ne;
   a.bs = L.bs;
   a.rp = L.rpA;
@@ -278,8 +307,8 @@ BsrArgs<T> argsA(const DevLevel& L) {
   return a;
 }
 template <typename T>
-BsrArgs<T> argsS(const DevLevel& L) {
-  BsrArgs<T> a;
+BsrArgs<T, Vd> argsS(const DevLevel& L) {
+  BsrArgs<T, Vd> a;
   a.nrows = L.ne;
   a.bs = L.bs;
   a.rp = L.rpS;
@@ -291,73 +320,87 @@ BsrArgs<T> argsS(const DevLevel& L) {
 
 // out = b - A x
 template <typename T>
-void residual(const DevLevel& L, const T* x, const T* b, T* out, hipStream_t st) {
-  BsrArgs<T> a = argsA<T>(L);
+void residual(const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st) {
+  BsrArgs<T, Vd> a = argsA<T>(L);
   a.x = x;
   a.z = b;
   a.out = out;
-  a.alpha = T(-1);
-  a.beta = T(1);
-  bsr_forward<T>(a, st);
+  a.alpha = -1.0;
+  a.beta = 1.0;
+  bsr_forward<T, Vd>(a, st);
+}
+
+template <typename T>
+void residual(DevHier& D, const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st) {
+  ProfScope ps(D, L, st, K_A);
+  residual<T>(L, x, b, out, st);
 }
 
 // out = alpha S x + beta z   (transposed: S^T)
 template <typename T>
-void apply_S(const DevLevel& L, bool transposed, const T* x, const T* z, T* out, T alpha, T beta,
+void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* out, Vd alpha, Vd beta,
              hipStream_t st) {
-  BsrArgs<T> a = argsS<T>(L);
+  BsrArgs<T, Vd> a = argsS<T>(L);
   a.x = x;
   a.z = z;
   a.out = out;
   a.alpha = alpha;
   a.beta = beta;
-  if (transposed) bsr_transposed<T>(a, st);
-  else bsr_forward<T>(a, st);
+  if (transposed) bsr_transposed<T, Vd>(a, st);
+  else bsr_forward<T, Vd>(a, st);
+}
+
+template <typename T>
+void apply_S(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* out, Vd alpha,
+             Vd beta, hipStream_t st) {
+  ProfScope ps(D, L, st, transposed ? K_ST : K_SF);
+  apply_S<T>(L, transposed, x, z, out, alpha, beta, st);
 }
 
 // one smoothing step on level L with x (in/out), b.  `zero_x`: x is known to be 0.
 // Uses L.r / L.t as scratch.  Returns the buffer holding the result (x or t).
 template <typename T>
-T* smooth_step(const Ctx& c, DevLevel& L, T* x, const T* b, bool forward, bool zero_x) {
+Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, bool zero_x) {
   const int sm = c.H.prob.smoother;
-  const T omega = static_cast<T>(c.H.omega);
-  T* r = static_cast<T*>(L.r);
-  T* t = static_cast<T*>(L.t);
+  const Vd omega = c.H.omega;
+  Vd* r = L.r;
+  Vd* t = L.t;
   if (sm == LDGMG_SMOOTH_SAI) {
     if (zero_x) {             // x = S b  (eq:B1) or S^T b (eq:BT) from x = 0
-      apply_S<T>(L, !forward, b, nullptr, x, T(1), T(0), c.st);
+      apply_S<T>(c.D, L, !forward, b, nullptr, x, 1.0, 0.0, c.st);
       return x;
     }
-    residual<T>(L, x, b, r, c.st);
-    apply_S<T>(L, !forward, r, x, x, T(1), T(1), c.st);
+    residual<T>(c.D, L, x, b, r, c.st);
+    apply_S<T>(c.D, L, !forward, r, x, x, 1.0, 1.0, c.st);
     return x;
   }
   if (sm == LDGMG_SMOOTH_JACOBI) {
     if (zero_x) {             // x = w D^-1 b
-      apply_S<T>(L, false, b, nullptr, x, omega, T(0), c.st);
+      apply_S<T>(c.D, L, false, b, nullptr, x, omega, 0.0, c.st);
       return x;
     }
     if (fast_bs(L.bs)) {      // t = x + w D^-1 (b - A x)
-      BsrArgs<T> a = argsA<T>(L);
+      BsrArgs<T, Vd> a = argsA<T>(L);
       a.x = x;
       a.z = b;
       a.out = t;
       a.dinv = static_cast<const T*>(L.valS);
       a.omega = omega;
-      bsr_forward<T>(a, c.st);
+      ProfScope ps(c.D, L, c.st, K_FUSED);
+      bsr_forward<T, Vd>(a, c.st);
       return t;
     }
-    residual<T>(L, x, b, r, c.st);
-    apply_S<T>(L, false, r, x, x, omega, T(1), c.st);
+    residual<T>(c.D, L, x, b, r, c.st);
+    apply_S<T>(c.D, L, false, r, x, x, omega, 1.0, c.st);
     return x;
   }
   // multi-coloured Gauss-Seidel: colours in order (forward) or reversed
-  if (zero_x) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(T), c.st));
+  if (zero_x) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(Vd), c.st));
   const int nc = static_cast<int>(L.colour_rows.size());
   for (int k = 0; k < nc; ++k) {
     const int col = forward ? k : nc - 1 - k;
     if (fast_bs(L.bs)) {
-      BsrArgs<T> a = argsA<T>(L);
+      BsrArgs<T, Vd> a = argsA<T>(L);
       a.nrows = L.colour_count[col];
       a.rows = L.colour_rows[col];
       a.x = x;
@@ -365,26 +408,27 @@ T* smooth_step(const Ctx& c, DevLevel& L, T* x, const T* b, bool forward, bool z
       a.out = x;              // in place: rows of one colour are not coupled
       a.dinv = static_cast<const T*>(L.valS);
       a.omega = omega;
-      bsr_forward<T>(a, c.st);
+      ProfScope ps(c.D, L, c.st, K_FUSED);
+      bsr_forward<T, Vd>(a, c.st);
     } else {
-      BsrArgs<T> a = argsA<T>(L);
+      BsrArgs<T, Vd> a = argsA<T>(L);
       a.nrows = L.colour_count[col];
       a.rows = L.colour_rows[col];
       a.x = x;
       a.z = b;
       a.out = r;
-      a.alpha = T(-1);
-      a.beta = T(1);
-      bsr_forward<T>(a, c.st);
-      BsrArgs<T> s = argsS<T>(L);
+      a.alpha = -1.0;
+      a.beta = 1.0;
+      bsr_forward<T, Vd>(a, c.st);
+      BsrArgs<T, Vd> s = argsS<T>(L);
       s.nrows = L.colour_count[col];
       s.rows = L.colour_rows[col];
       s.x = r;
       s.z = x;
       s.out = x;
       s.alpha = omega;
-      s.beta = T(1);
-      bsr_forward<T>(s, c.st);
+      s.beta = 1.0;
+      bsr_forward<T, Vd>(s, c.st);
     }
   }
   return x;
@@ -398,48 +442,42 @@ template <typename T>
 void vcycle_level(const Ctx& c, int l) {
   DevLevel& L = c.D.L[l];
   const int nl = static_cast<int>(c.D.L.size());
-  T* x = static_cast<T*>(L.x);
-  T* b = static_cast<T*>(L.b);
+  Vd* x = L.x;
+  const Vd* b = L.b;
   if (l == nl - 1) {
-    dense_gemv<T>(static_cast<int>(L.N), L.pinv, b, x, c.st);
+    dense_gemv<Vd>(static_cast<int>(L.N), L.pinv, b, x, c.st);
     return;
   }
   const ldgmg_problem& P = c.H.prob;
   const bool pre_fwd = order_pre_forward(P.order), post_fwd = order_post_forward(P.order);
-  auto keep = [&](T* res) {
+  auto keep = [&](Vd* res) {
     if (res != x) {             // Jacobi wrote into t: swap the roles of x and t
       std::swap(L.x, L.t);
-      x = static_cast<T*>(L.x);
+      x = L.x;
     }
   };
-  if (P.nu1 == 0) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(T), c.st));
+  if (P.nu1 == 0) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(Vd), c.st));
   for (int s = 0; s < P.nu1; ++s) keep(smooth_step<T>(c, L, x, b, pre_fwd, s == 0));
-  T* r = static_cast<T*>(L.r);
-  residual<T>(L, x, b, r, c.st);
+  residual<T>(c.D, L, x, b, L.r, c.st);
   DevLevel& Lc = c.D.L[l + 1];
-  restrict_op<T>(P.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), r, static_cast<T*>(Lc.b), c.st);
+  restrict_op<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, L.r, Lc.b, c.st);
   vcycle_level<T>(c, l + 1);
-  prolong_add<T>(P.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), static_cast<const T*>(Lc.x), x, c.st);
+  prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, Lc.x, x, c.st);
   for (int s = 0; s < P.nu2; ++s) keep(smooth_step<T>(c, L, x, b, post_fwd, false));
 }
 
-// z = V r in FP64 (cast around the working-precision V-cycle)
+// z = V r (FP64 vectors in and out; the stored blocks are FP32 or FP64)
 void vcycle64(const Ctx& c, const double* r, double* z) {
   DevLevel& L = c.D.L[0];
-  if (c.D.prec == LDGMG_FP64) {
-    HIPCHK(hipMemcpyAsync(L.b, r, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
-    vcycle_level<double>(c, 0);
-    HIPCHK(hipMemcpyAsync(z, L.x, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
-  } else {
-    cast<double, float>(L.N, r, static_cast<float*>(L.b), c.st);
-    vcycle_level<float>(c, 0);
-    cast<float, double>(L.N, static_cast<const float*>(L.x), z, c.st);
-  }
+  HIPCHK(hipMemcpyAsync(L.b, r, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
+  if (c.D.prec == LDGMG_FP64) vcycle_level<double>(c, 0);
+  else vcycle_level<float>(c, 0);
+  HIPCHK(hipMemcpyAsync(z, L.x, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
 }
 
 void apply_A64(const Ctx& c, const double* x, double* y) {
   const DevLevel& L = c.D.L[0];
-  BsrArgs<double> a;
+  BsrArgs<double, double> a;
   a.nrows = L.ne;
   a.bs = L.bs;
   a.rp = L.rpA;
@@ -447,7 +485,8 @@ void apply_A64(const Ctx& c, const double* x, double* y) {
   a.blk = c.D.val64;
   a.x = x;
   a.out = y;
-  bsr_forward<double>(a, c.st);
+  ProfScope ps(c.D, L, c.st, K_A64);
+  bsr_forward<double, double>(a, c.st);
 }
 
 double dot_host(const Ctx& c, const double* a, const double* b, int slot) {
@@ -632,50 +671,50 @@ template <typename T>
 void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, void* out) {
   DevLevel& L = c.D.L[l];
   const int nl = static_cast<int>(c.D.L.size());
-  const T* a = static_cast<const T*>(in1);
-  const T* b = static_cast<const T*>(in2);
-  T* o = static_cast<T*>(out);
+  const Vd* a = static_cast<const Vd*>(in1);
+  const Vd* b = static_cast<const Vd*>(in2);
+  Vd* o = static_cast<Vd*>(out);
   const bool bottom = l == nl - 1;
   switch (op) {
     case LDGMG_OP_RESIDUAL:
-      residual<T>(L, a, b, o, c.st);
+      residual<T>(c.D, L, a, b, o, c.st);
       return;
     case LDGMG_OP_APPLY_A: {
-      BsrArgs<T> x = argsA<T>(L);
+      BsrArgs<T, Vd> x = argsA<T>(L);
       x.x = a;
       x.out = o;
-      bsr_forward<T>(x, c.st);
+      bsr_forward<T, Vd>(x, c.st);
       return;
     }
     case LDGMG_OP_APPLY_S:
     case LDGMG_OP_APPLY_ST:
       if (bottom) throw std::invalid_argument("no smoother on the bottom level");
-      apply_S<T>(L, op == LDGMG_OP_APPLY_ST, a, nullptr, o, T(1), T(0), c.st);
+      apply_S<T>(c.D, L, op == LDGMG_OP_APPLY_ST, a, nullptr, o, 1.0, 0.0, c.st);
       return;
     case LDGMG_OP_SMOOTH_FWD:
     case LDGMG_OP_SMOOTH_REV: {
       if (bottom) throw std::invalid_argument("no smoother on the bottom level");
-      HIPCHK(hipMemcpyAsync(o, a, static_cast<size_t>(L.N) * sizeof(T), hipMemcpyDeviceToDevice, c.st));
-      T* res = smooth_step<T>(c, L, o, b, op == LDGMG_OP_SMOOTH_FWD, false);
+      HIPCHK(hipMemcpyAsync(o, a, static_cast<size_t>(L.N) * sizeof(Vd), hipMemcpyDeviceToDevice, c.st));
+      Vd* res = smooth_step<T>(c, L, o, b, op == LDGMG_OP_SMOOTH_FWD, false);
       if (res != o)
-        HIPCHK(hipMemcpyAsync(o, res, static_cast<size_t>(L.N) * sizeof(T), hipMemcpyDeviceToDevice, c.st));
+        HIPCHK(hipMemcpyAsync(o, res, static_cast<size_t>(L.N) * sizeof(Vd), hipMemcpyDeviceToDevice, c.st));
       return;
     }
     case LDGMG_OP_RESTRICT: {
       if (bottom) throw std::invalid_argument("no coarser level");
       DevLevel& Lc = c.D.L[l + 1];
-      restrict_op<T>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), a, o, c.st);
+      restrict_op<Vd>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, a, o, c.st);
       return;
     }
     case LDGMG_OP_PROLONG_ADD: {
       if (bottom) throw std::invalid_argument("no coarser level");
       DevLevel& Lc = c.D.L[l + 1];
-      prolong_add<T>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, static_cast<const T*>(Lc.Ic), a, o, c.st);
+      prolong_add<Vd>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, a, o, c.st);
       return;
     }
     case LDGMG_OP_BOTTOM:
       if (!bottom) throw std::invalid_argument("LDGMG_OP_BOTTOM needs the bottom level");
-      dense_gemv<T>(static_cast<int>(L.N), L.pinv, a, o, c.st);
+      dense_gemv<Vd>(static_cast<int>(L.N), L.pinv, a, o, c.st);
       return;
     default:
       throw std::invalid_argument("unknown op");
@@ -978,6 +1017,40 @@ int ldgmg_setup_stats(ldgmg_handle h, int level, int* sai_unique, double* second
     const HostLevel& L = h->host->levels[level];
     if (sai_unique) *sai_unique = L.sai_unique;
     if (seconds) *seconds = L.setup_seconds;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_profile(ldgmg_handle h, int enable) {
+  return guarded([&] {
+    need_dev(h);
+    DevHier& D = *h->dev;
+    if (D.evpool.empty() && enable) {
+      D.evpool.resize(8192);
+      for (auto& e : D.evpool) HIPCHK(hipEventCreate(&e));
+    }
+    D.recs.clear();
+    D.prof = enable != 0;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_profile_read(ldgmg_handle h, int kind, int* count, double* total_ms) {
+  return guarded([&] {
+    need_dev(h);
+    DevHier& D = *h->dev;
+    int cnt = 0;
+    double tot = 0.0;
+    for (const auto& r : D.recs) {
+      if (r.kind != kind) continue;
+      HIPCHK(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+      tot += ms;
+      ++cnt;
+    }
+    if (count) *count = cnt;
+    if (total_ms) *total_ms = tot;
     return LDGMG_OK;
   });
 }

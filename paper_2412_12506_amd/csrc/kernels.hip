@@ -52,16 +52,16 @@ constexpr int kThreads = 64 * kWaves;
 //           out may alias x when the rows of one launch are not coupled)
 // rows (optional) lists the block rows to process (nrows entries).
 // ---------------------------------------------------------------------------
-template <typename T, int BS, int MODE>
+template <typename TM, typename T, int BS, int MODE>
 __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __restrict__ rows,
                                                       const int* __restrict__ rp,
                                                       const int* __restrict__ ci,
-                                                      const T* __restrict__ blk, const T* x,
+                                                      const TM* __restrict__ blk, const T* x,
                                                       const T* z, T* out, T alpha, T beta,
-                                                      const T* __restrict__ dinv, T omega) {
-  using C = BlkCfg<T, BS>;
+                                                      const TM* __restrict__ dinv, T omega) {
+  using C = BlkCfg<TM, BS>;
   constexpr int V = C::V, G = C::G, NV = C::NV;
-  using VT = typename VecT<T, V>::type;
+  using VT = typename VecT<TM, V>::type;
   const int lane = threadIdx.x & 63;
   const int g = lane / BS;
   const int r = lane - g * BS;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc += elem(a[q], v) * group_bcast<T, BS>(xv, g, q * V + v);
+      for (int v = 0; v < V; ++v) acc += static_cast<T>(elem(a[q], v)) * group_bcast<T, BS>(xv, g, q * V + v);
     }
   }
   const size_t o = static_cast<size_t>(row) * BS + r;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) y += elem(d[q], v) * group_bcast<T, BS>(res, g, q * V + v);
+      for (int v = 0; v < V; ++v) y += static_cast<T>(elem(d[q], v)) * group_bcast<T, BS>(res, g, q * V + v);
     }
     if (active) out[o] = x[o] + omega * y;
   } else {
@@ -115,16 +115,16 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
 // Lane r accumulates row r of each (M_ji) scaled by x_j[r]; the BS partial
 // vectors of a group are then summed across lanes.
 // ---------------------------------------------------------------------------
-template <typename T, int BS>
+template <typename TM, typename T, int BS>
 __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
                                                      const int* __restrict__ tpos,
-                                                     const T* __restrict__ blk, const T* x,
+                                                     const TM* __restrict__ blk, const T* x,
                                                      const T* z, T* out, T alpha, T beta) {
-  using C = BlkCfg<T, BS>;
+  using C = BlkCfg<TM, BS>;
   constexpr int V = C::V, G = C::G, NV = C::NV;
   constexpr bool POW2 = (BS & (BS - 1)) == 0;
-  using VT = typename VecT<T, V>::type;
+  using VT = typename VecT<TM, V>::type;
   const int lane = threadIdx.x & 63;
   const int g = lane / BS;
   const int r = lane - g * BS;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[q * V + v] += elem(a[q], v) * xr;
+      for (int v = 0; v < V; ++v) acc[q * V + v] += static_cast<T>(elem(a[q], v)) * xr;
     }
   }
   T y;
@@ -193,12 +193,12 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 
 // generic BSR kernel for any block size: one lane per scalar row.
 // Blocks use the V = 1 layout (entry (r, c) at c * bs + r).
-template <typename T>
+template <typename TM, typename T>
 __global__ __launch_bounds__(256) void k_bsr_generic(int nrows, int bs, const int* __restrict__ rows,
                                                      const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
                                                      const int* __restrict__ tpos,
-                                                     const T* __restrict__ blk, const T* x,
+                                                     const TM* __restrict__ blk, const T* x,
                                                      const T* z, T* out, T alpha, T beta) {
   const long long tid = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const long long idx = tid / bs;
@@ -211,11 +211,11 @@ __global__ __launch_bounds__(256) void k_bsr_generic(int nrows, int bs, const in
     const int j = ci[s];
     const T* xj = x + static_cast<size_t>(j) * bs;
     if (tpos) {   // (M_ji)^T[r][c] = M_ji[c][r], stored at r * bs + c
-      const T* b = blk + static_cast<size_t>(tpos[s]) * bb + static_cast<size_t>(r) * bs;
-      for (int c = 0; c < bs; ++c) acc += b[c] * xj[c];
+      const TM* b = blk + static_cast<size_t>(tpos[s]) * bb + static_cast<size_t>(r) * bs;
+      for (int c = 0; c < bs; ++c) acc += static_cast<T>(b[c]) * xj[c];
     } else {
-      const T* b = blk + static_cast<size_t>(s) * bb + r;
-      for (int c = 0; c < bs; ++c) acc += b[static_cast<size_t>(c) * bs] * xj[c];
+      const TM* b = blk + static_cast<size_t>(s) * bb + r;
+      for (int c = 0; c < bs; ++c) acc += static_cast<T>(b[static_cast<size_t>(c) * bs]) * xj[c];
     }
   }
   const size_t o = static_cast<size_t>(row) * bs + r;
@@ -461,28 +461,28 @@ int grid_for(long long n, int threads, int cap = 4096) {
   return static_cast<int>(g);
 }
 
-template <typename T, int BS>
-void launch_fwd_bs(const BsrArgs<T>& a, hipStream_t st) {
+template <typename TM, typename T, int BS>
+void launch_fwd_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
   constexpr int G = 64 / BS;
   const long long waves = (a.nrows + G - 1) / G;
   const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
   if (blocks == 0) return;
   if (a.dinv)
-    k_bsr_fwd<T, BS, 1><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
+    k_bsr_fwd<TM, T, BS, 1><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
                                                      a.alpha, a.beta, a.dinv, a.omega);
   else
-    k_bsr_fwd<T, BS, 0><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
+    k_bsr_fwd<TM, T, BS, 0><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
                                                      a.alpha, a.beta, nullptr, T(0));
   check_launch("bsr_fwd");
 }
 
-template <typename T, int BS>
-void launch_tr_bs(const BsrArgs<T>& a, hipStream_t st) {
+template <typename TM, typename T, int BS>
+void launch_tr_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
   constexpr int G = 64 / BS;
   const long long waves = (a.nrows + G - 1) / G;
   const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
   if (blocks == 0) return;
-  k_bsr_tr<T, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.rp, a.ci, a.tpos, a.blk, a.x, a.z, a.out,
+  k_bsr_tr<TM, T, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.rp, a.ci, a.tpos, a.blk, a.x, a.z, a.out,
                                                a.alpha, a.beta);
   check_launch("bsr_tr");
 }
@@ -502,12 +502,12 @@ bool fast_bs(int bs) {
   }
 }
 
-template <typename T>
-void bsr_forward(const BsrArgs<T>& a, hipStream_t st) {
+template <typename TM, typename T>
+void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st) {
   switch (a.bs) {
 #define CASE(B) \
   case B:       \
-    launch_fwd_bs<T, B>(a, st); \
+    launch_fwd_bs<TM, T, B>(a, st); \
     return;
     LDGMG_FOR_BS(CASE)
 #undef CASE
@@ -517,18 +517,18 @@ void bsr_forward(const BsrArgs<T>& a, hipStream_t st) {
   if (a.dinv) throw std::runtime_error("fused smoothing needs a block size <= 64");
   const long long n = static_cast<long long>(a.nrows) * a.bs;
   if (n == 0) return;
-  k_bsr_generic<T><<<static_cast<int>((n + 255) / 256), 256, 0, st>>>(a.nrows, a.bs, a.rows, a.rp, a.ci,
+  k_bsr_generic<TM, T><<<static_cast<int>((n + 255) / 256), 256, 0, st>>>(a.nrows, a.bs, a.rows, a.rp, a.ci,
                                                                         nullptr, a.blk, a.x, a.z, a.out,
                                                                         a.alpha, a.beta);
   check_launch("bsr_generic");
 }
 
-template <typename T>
-void bsr_transposed(const BsrArgs<T>& a, hipStream_t st) {
+template <typename TM, typename T>
+void bsr_transposed(const BsrArgs<TM, T>& a, hipStream_t st) {
   switch (a.bs) {
 #define CASE(B) \
   case B:       \
-    launch_tr_bs<T, B>(a, st); \
+    launch_tr_bs<TM, T, B>(a, st); \
     return;
     LDGMG_FOR_BS(CASE)
 #undef CASE
@@ -537,7 +537,7 @@ void bsr_transposed(const BsrArgs<T>& a, hipStream_t st) {
   }
   const long long n = static_cast<long long>(a.nrows) * a.bs;
   if (n == 0) return;
-  k_bsr_generic<T><<<static_cast<int>((n + 255) / 256), 256, 0, st>>>(a.nrows, a.bs, nullptr, a.rp, a.ci,
+  k_bsr_generic<TM, T><<<static_cast<int>((n + 255) / 256), 256, 0, st>>>(a.nrows, a.bs, nullptr, a.rp, a.ci,
                                                                         a.tpos, a.blk, a.x, a.z, a.out,
                                                                         a.alpha, a.beta);
   check_launch("bsr_generic_t");
@@ -628,10 +628,10 @@ void maxpy(long long n, int k, const double* Q, const double* h, double sign, do
   check_launch("maxpy");
 }
 
-template void bsr_forward<float>(const BsrArgs<float>&, hipStream_t);
-template void bsr_forward<double>(const BsrArgs<double>&, hipStream_t);
-template void bsr_transposed<float>(const BsrArgs<float>&, hipStream_t);
-template void bsr_transposed<double>(const BsrArgs<double>&, hipStream_t);
+template void bsr_forward<float, double>(const BsrArgs<float, double>&, hipStream_t);
+template void bsr_forward<double, double>(const BsrArgs<double, double>&, hipStream_t);
+template void bsr_transposed<float, double>(const BsrArgs<float, double>&, hipStream_t);
+template void bsr_transposed<double, double>(const BsrArgs<double, double>&, hipStream_t);
 template void expand_blocks<float>(long long, int, const int*, const double*, float*, bool, hipStream_t);
 template void expand_blocks<double>(long long, int, const int*, const double*, double*, bool, hipStream_t);
 template void restrict_op<float>(int, int, int, int, const float*, const float*, float*, hipStream_t);

@@ -22,7 +22,8 @@ inline int device_vec_width(int bs, int elem_bytes) {
   return bs % 2 == 0 ? 2 : 1;
 }
 
-template <typename T>
+// TM: element type of the stored blocks; T: vectors and arithmetic
+template <typename TM, typename T>
 struct BsrArgs {
   int nrows = 0;              // block rows to process
   int bs = 0;
@@ -30,19 +31,19 @@ struct BsrArgs {
   const int* rp = nullptr;    // row pointer [nblockrows + 1]
   const int* ci = nullptr;    // block columns [nnzb]
   const int* tpos = nullptr;  // transposed kernel: slot of (j,i) for slot (i,j)
-  const T* blk = nullptr;     // blocks [nnzb][bs*bs], device layout
+  const TM* blk = nullptr;    // blocks [nnzb][bs*bs], device layout
   const T* x = nullptr;       // input vector
   const T* z = nullptr;       // added vector (MODE 0) / right-hand side (fused smoothing)
   T* out = nullptr;
   T alpha = T(1), beta = T(0);
-  const T* dinv = nullptr;    // fused smoothing: block inverses indexed by block row
+  const TM* dinv = nullptr;   // fused smoothing: block inverses indexed by block row
   T omega = T(1);
 };
 
 // out = alpha M x + beta z, or (dinv != null) out = x + omega Dinv (z - M x)
-template <typename T> void bsr_forward(const BsrArgs<T>& a, hipStream_t st);
+template <typename TM, typename T> void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st);
 // out = alpha M^T x + beta z  (rows must be null; tpos required)
-template <typename T> void bsr_transposed(const BsrArgs<T>& a, hipStream_t st);
+template <typename TM, typename T> void bsr_transposed(const BsrArgs<TM, T>& a, hipStream_t st);
 // pooled FP64 row-major blocks -> device layout of T (optionally transposed)
 template <typename T>
 void expand_blocks(long long nslots, int bs, const int* ids, const double* pool, T* out, bool transpose,

@@ -58,7 +58,8 @@ _lib = None
 SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
-           "ldgmg_setup_stats", "ldgmg_destroy", "ldgmg_last_error"]
+           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_destroy",
+           "ldgmg_last_error"]
 
 
 def lib():
@@ -86,6 +87,8 @@ def lib():
     L.ldgmg_export.argtypes = [H, C.c_int, C.c_int, ip, ip, dp, ip, ip]
     L.ldgmg_export_colours.argtypes = [H, C.c_int, ip]
     L.ldgmg_setup_stats.argtypes = [H, C.c_int, ip, dp]
+    L.ldgmg_profile.argtypes = [H, C.c_int]
+    L.ldgmg_profile_read.argtypes = [H, C.c_int, ip, dp]
     L.ldgmg_destroy.argtypes = [H]
     L.ldgmg_last_error.argtypes = []
     L.ldgmg_last_error.restype = C.c_char_p
@@ -253,6 +256,20 @@ def ldgmg_setup_stats(h: int, level: int):
     u, s = C.c_int(), C.c_double()
     _check(lib().ldgmg_setup_stats(h, level, C.byref(u), C.byref(s)))
     return u.value, s.value
+
+
+PROFILE_KIND = {"A": 0, "S": 1, "ST": 2, "A64": 3, "FUSED": 4}
+
+
+def ldgmg_profile(h: int, enable: bool):
+    _check(lib().ldgmg_profile(h, 1 if enable else 0))
+
+
+def ldgmg_profile_read(h: int, kind: str):
+    """(launch count, summed milliseconds) of one kind of fine-level launch."""
+    cnt, ms = C.c_int(), C.c_double()
+    _check(lib().ldgmg_profile_read(h, PROFILE_KIND[kind], C.byref(cnt), C.byref(ms)))
+    return cnt.value, ms.value
 
 
 def ldgmg_destroy(h: int):

@@ -1,0 +1,193 @@
+"""GPU parity: every V-cycle kernel, the V-cycle and the Krylov solves of the
+HIP library (called through the C-ABI) against the CPU oracle, on the same
+seeded inputs.
+
+Tolerances (derived from the arithmetic, not tuned):
+  * FP64 level operations: |y - y_ref| <= 1e-12 max(|A||x| + |b|): the host
+    setups agree to ~1e-15 and a row sums at most a few hundred products.
+  * FP32 block storage (vectors and accumulation stay FP64): the only new
+    error is the rounding of each stored entry, |fl(a) - a| <= u32 |a|, so
+    |y - y_ref| <= 4 u32 |A||x| (u32 = 2^-24, with slack for the FP64 sums).
+  * V-cycle: FP64 within 1e-10 relative (a bounded linear operator of a few
+    dozen stages); FP32 storage within 1e-5 relative (entry rounding of every
+    stage, amplified by the operator norms).
+  * Solves: iteration count within +-1 of the oracle; solution within 1e-8
+    relative of the oracle's and true FP64 residual <= 2e-10.
+Sizes span several workgroups and ragged tails on every level.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from ldg_inputs import rhs_normal, stokes_body_force
+from tests.gpu_common import lib_kwargs, oracle_build, smoother_matrix
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+CASES = [
+    dict(id="p2d-p2-gl-jacobi", dim=2, n=16, p=2, basis="gl_nodal", smoother="jacobi"),
+    dict(id="p3d-p3-sai1", dim=3, n=6, p=3, smoother="sai", sai_level=1),
+    dict(id="i3d-p2-sphere-sai1", dim=3, n=8, p=2, smoother="sai", mu=("sphere", 0.3, 1e4)),
+    dict(id="i2d-p1-box-gs", dim=2, n=12, p=1, smoother="gs", mu=("box", 0.0, 1e-4)),
+    dict(id="p2d-p3-sai2", dim=2, n=8, p=3, smoother="sai", sai_level=2),
+    dict(id="s2d-p2-stress-disc-sai1", dim=2, n=8, p=2, system="stokes", gamma=1,
+         smoother="sai", mu=("disc", 0.25, 1e3), krylov="gmres"),
+    dict(id="s2d-p1-std-gs", dim=2, n=8, p=1, system="stokes", gamma=0, smoother="gs",
+         order="OO", krylov="gmres"),
+]
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module",
+                params=[(c, pr) for c in CASES for pr in ("fp64", "fp32")],
+                ids=lambda cp: f"{cp[0]['id']}-{cp[1]}")
+def built(request):
+    from paper_2412_12506_amd import ldgmg as L
+    case, prec = request.param
+    print(f"\n[case {case['id']} {prec}]", flush=True)
+    s = L.Solver(**lib_kwargs(case, prec))
+    lv, vc = oracle_build(case)
+    yield case, prec, s, lv, vc
+    s.close()
+
+
+def _t(a, prec=None):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(_dev())
+
+
+def _round(a, prec):
+    return a
+
+
+def _tol_op(prec, A):
+    return 1e-12 if prec == "fp64" else 4 * U32
+
+
+def test_level_operations(built):
+    from paper_2412_12506_amd import ldgmg as L
+    case, prec, s, lv, vc = built
+    rng = np.random.default_rng(1234)
+    nl = len(lv)
+    assert s.nlevels == nl
+    for l in range(nl):
+        A = vc.levels[l].A
+        N = A.shape[0]
+        x = _round(rng.standard_normal(N), prec)
+        b = _round(rng.standard_normal(N), prec)
+        xt, bt = _t(x, prec), _t(b, prec)
+        out = torch.empty_like(xt)
+        absAx = abs(A) @ np.abs(x)
+        tol = _tol_op(prec, A)
+        # residual and operator apply (a1)
+        L.ldgmg_level_op(s.handle, l, "residual", xt, bt, out)
+        torch.cuda.synchronize()
+        ref = b - A @ x
+        err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(absAx + np.abs(b))
+        assert err <= tol, (l, "residual", err, tol)
+        if l == nl - 1:
+            L.ldgmg_level_op(s.handle, l, "bottom", bt, None, out)
+            torch.cuda.synchronize()
+            ref = vc.levels[l].pinv @ b
+            err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(vc.levels[l].pinv) @ np.abs(b))
+            assert err <= 1e-11, (l, "bottom", err)
+            continue
+        # smoother matrix forward / transposed (a2, a3)
+        S = smoother_matrix(vc, l)
+        stol = _tol_op(prec, S)
+        for op, M in (("apply_s", S), ("apply_st", S.T.tocsr())):
+            L.ldgmg_level_op(s.handle, l, op, xt, None, out)
+            torch.cuda.synchronize()
+            ref = M @ x
+            err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(abs(M) @ np.abs(x))
+            assert err <= stol, (l, op, err, stol)
+        # smoothing steps (a2 / a3 / a4)
+        for op, fwd in (("smooth_fwd", True), ("smooth_rev", False)):
+            L.ldgmg_level_op(s.handle, l, op, xt, bt, out)
+            torch.cuda.synchronize()
+            ref = vc.smooth(vc.levels[l], x, b, fwd)
+            scale = np.max(np.abs(ref)) + np.max(np.abs(x))
+            err = np.max(np.abs(out.cpu().numpy() - ref)) / scale
+            assert err <= (1e-11 if prec == "fp64" else 1e-6), (l, op, err)
+        # transfers (a5, a6)
+        I = vc.levels[l].I
+        Nc = I.shape[1]
+        rc = torch.empty(Nc, dtype=torch.float64, device=_dev())
+        L.ldgmg_level_op(s.handle, l, "restrict", xt, None, rc)
+        torch.cuda.synchronize()
+        ref = I.T @ x
+        err = np.max(np.abs(rc.cpu().numpy() - ref)) / np.max(abs(I.T) @ np.abs(x))
+        assert err <= 1e-13, (l, "restrict", err)
+        xc = _round(rng.standard_normal(Nc), prec)
+        o2 = xt.clone()
+        L.ldgmg_level_op(s.handle, l, "prolong_add", _t(xc, prec), None, o2)
+        torch.cuda.synchronize()
+        ref = x + I @ xc
+        err = np.max(np.abs(o2.cpu().numpy() - ref)) / np.max(np.abs(x) + abs(I) @ np.abs(xc))
+        assert err <= 1e-13, (l, "prolong", err)
+    # FP64 Krylov operator on the fine level (a10)
+    A = vc.levels[0].A
+    x = rng.standard_normal(A.shape[0])
+    xt = torch.from_numpy(x).to(_dev())
+    out = torch.empty_like(xt)
+    L.ldgmg_level_op(s.handle, 0, "apply_a64", xt, None, out)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(out.cpu().numpy() - A @ x)) / np.max(abs(A) @ np.abs(x))
+    assert err <= 1e-12
+
+
+def _rhs(case, N, seed):
+    if case.get("system") == "stokes":
+        return stokes_body_force(case["dim"], case["n"], (case["p"] + 1) ** case["dim"], seed)
+    return rhs_normal(N, seed)
+
+
+def test_vcycle(built):
+    from paper_2412_12506_amd import ldgmg as L
+    case, prec, s, lv, vc = built
+    N = lv[0].A.shape[0]
+    b = _rhs(case, N, 7)
+    bt = torch.from_numpy(b).to(_dev())
+    xt = torch.empty_like(bt)
+    L.ldgmg_vcycle(s.handle, bt, xt)
+    torch.cuda.synchronize()
+    ref = vc.apply(b)
+    err = np.linalg.norm(xt.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= (1e-10 if prec == "fp64" else 1e-5), err
+    # a second call on the same handle gives the same result (no stale state)
+    xt2 = torch.empty_like(bt)
+    L.ldgmg_vcycle(s.handle, bt, xt2)
+    torch.cuda.synchronize()
+    assert torch.equal(xt, xt2)
+
+
+def test_solve(built):
+    from paper_2412_12506_amd import ldgmg as L
+    from oracle import solver as osolver
+    case, prec, s, lv, vc = built
+    N = lv[0].A.shape[0]
+    b = _rhs(case, N, 11)
+    krylov = case.get("krylov", "cg")
+    ref = osolver.solve(lv, vc, b, krylov)
+    bt = torch.from_numpy(b).to(_dev())
+    xt = torch.empty_like(bt)
+    info = L.ldgmg_solve(s.handle, bt, xt, krylov, 1e-10, 200)
+    assert info["converged"] and ref.converged
+    assert abs(info["iters"] - ref.iters) <= 1, (info["iters"], ref.iters)
+    x = xt.cpu().numpy()
+    if case.get("system") == "stokes":     # compare modulo the constant-pressure kernel
+        from oracle import stokes
+        k = stokes.pressure_kernel(lv[0])
+        proj = lambda v: v - (v @ k) / (k @ k) * k
+        x, xr = proj(x), proj(ref.x)
+    else:
+        xr = ref.x
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-8
+    assert info["rel_res_true"] <= 2e-10
+    if prec == "fp64":
+        assert abs(info["eta"] - ref.eta) <= 0.05 * ref.eta
