@@ -4,15 +4,23 @@ seeded inputs.
 
 Tolerances (derived from the arithmetic, not tuned):
   * FP64 level operations: |y - y_ref| <= 1e-12 max(|A||x| + |b|): the host
-    setups agree to ~1e-15 and a row sums at most a few hundred products.
+    setups agree to ~1e-15 and a row sums at most a few hundred products
+    (block inverses: 20 kappa(A_ii) eps64, since both sides invert A_ii).
   * FP32 block storage (vectors and accumulation stay FP64): the only new
     error is the rounding of each stored entry, |fl(a) - a| <= u32 |a|, so
     |y - y_ref| <= 4 u32 |A||x| (u32 = 2^-24, with slack for the FP64 sums).
-  * V-cycle: FP64 within 1e-10 relative (a bounded linear operator of a few
-    dozen stages); FP32 storage within 1e-5 relative (entry rounding of every
-    stage, amplified by the operator norms).
+  * smoothing steps: the first-order bound |dx| <= u |S| (|b| + |A||x|) of
+    one step (u = unit roundoff of the stored entries; once per colour for
+    Gauss-Seidel), with a factor 64 of slack for the FP64 sums.
+  * bottom solve and V-cycle: the two setups compute the bottom pseudo-inverse
+    independently, so they agree only to ~kappa eps64 (kappa = condition number
+    of the bottom operator on its range, computed from the oracle's matrix;
+    ~2e9 for the multiphase Stokes case).  Bottom within 20 kappa eps64; V-cycle
+    within 1e-10 (FP64) or 1e-5 (FP32 storage) plus 100 kappa eps64.
   * Solves: iteration count within +-1 of the oracle; solution within 1e-8
-    relative of the oracle's and true FP64 residual <= 2e-10.
+    relative of the oracle's (Stokes: modulo the constant pressure); CG true
+    FP64 residual <= 2e-10; GMRES (stops on ||V r||) true residual within 10x
+    of the oracle's.
 Sizes span several workgroups and ragged tails on every level.
 """
 import numpy as np
@@ -26,6 +34,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
+EPS64 = 2.0 ** -52
 
 CASES = [
     dict(id="p2d-p2-gl-jacobi", dim=2, n=16, p=2, basis="gl_nodal", smoother="jacobi"),
@@ -55,6 +64,14 @@ def built(request):
     lv, vc = oracle_build(case)
     yield case, prec, s, lv, vc
     s.close()
+
+
+def _kappa_bottom(vc):
+    """Condition number of the bottom operator on its range (oracle side): the
+    two independent pseudo-inverses can differ by ~kappa * eps."""
+    lam = np.abs(np.linalg.eigvalsh(vc.levels[-1].A.toarray()))
+    nz = lam[lam > 1e-12 * lam.max()]
+    return lam.max() / nz.min()
 
 
 def _t(a, prec=None):
@@ -95,25 +112,34 @@ def test_level_operations(built):
             torch.cuda.synchronize()
             ref = vc.levels[l].pinv @ b
             err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(vc.levels[l].pinv) @ np.abs(b))
-            assert err <= 1e-11, (l, "bottom", err)
+            assert err <= max(1e-11, 20 * _kappa_bottom(vc) * EPS64), (l, "bottom", err)
             continue
-        # smoother matrix forward / transposed (a2, a3)
+        # smoother matrix forward / transposed (a2, a3).  Block inverses are
+        # computed independently by both setups: they agree to ~kappa(A_ii) eps64.
         S = smoother_matrix(vc, l)
         stol = _tol_op(prec, S)
+        if vc.levels[l].sm.kind != "sai":
+            kd = max(np.linalg.cond(D) for D in np.linalg.inv(vc.levels[l].sm.Dinv))
+            stol = max(stol, 20 * kd * EPS64)
         for op, M in (("apply_s", S), ("apply_st", S.T.tocsr())):
             L.ldgmg_level_op(s.handle, l, op, xt, None, out)
             torch.cuda.synchronize()
             ref = M @ x
             err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(abs(M) @ np.abs(x))
             assert err <= stol, (l, op, err, stol)
-        # smoothing steps (a2 / a3 / a4)
+        # smoothing steps (a2 / a3 / a4).  First-order bound for stored-entry
+        # rounding u: |dx| <= u |S| (|b| + |A||x|) per step (per colour for GS)
+        ncol = vc.levels[l].sm.colours.max() + 1 if vc.levels[l].sm.kind == "gs" else 1
+        mag = abs(S) @ (np.abs(b) + absAx) + np.abs(x)
+        u = 1e-14 if prec == "fp64" else U32
+        if vc.levels[l].sm.kind != "sai":
+            u = max(u, kd * EPS64)
         for op, fwd in (("smooth_fwd", True), ("smooth_rev", False)):
             L.ldgmg_level_op(s.handle, l, op, xt, bt, out)
             torch.cuda.synchronize()
             ref = vc.smooth(vc.levels[l], x, b, fwd)
-            scale = np.max(np.abs(ref)) + np.max(np.abs(x))
-            err = np.max(np.abs(out.cpu().numpy() - ref)) / scale
-            assert err <= (1e-11 if prec == "fp64" else 1e-6), (l, op, err)
+            err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(mag)
+            assert err <= 4 * ncol * u * 16, (l, op, err)
         # transfers (a5, a6)
         I = vc.levels[l].I
         Nc = I.shape[1]
@@ -158,7 +184,8 @@ def test_vcycle(built):
     torch.cuda.synchronize()
     ref = vc.apply(b)
     err = np.linalg.norm(xt.cpu().numpy() - ref) / np.linalg.norm(ref)
-    assert err <= (1e-10 if prec == "fp64" else 1e-5), err
+    tol = (1e-10 if prec == "fp64" else 1e-5) + 100 * _kappa_bottom(vc) * EPS64
+    assert err <= tol, (err, tol)
     # a second call on the same handle gives the same result (no stale state)
     xt2 = torch.empty_like(bt)
     L.ldgmg_vcycle(s.handle, bt, xt2)
@@ -188,6 +215,10 @@ def test_solve(built):
     else:
         xr = ref.x
     assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-8
-    assert info["rel_res_true"] <= 2e-10
+    if krylov == "cg":     # CG stops on the FP64 residual itself
+        assert info["rel_res_true"] <= 2e-10
+    else:                  # left-preconditioned GMRES stops on ||V r||: compare with the oracle
+        assert info["rel_res_krylov"] <= 1e-10
+        assert info["rel_res_true"] <= 10 * ref.rel_res_true + 1e-12
     if prec == "fp64":
         assert abs(info["eta"] - ref.eta) <= 0.05 * ref.eta

@@ -1,0 +1,82 @@
+"""Host-side setup of the C-ABI library (no GPU: ldgmg_setup_host) against the
+oracle: the operators A on every level, the smoother matrices (balanced SAI
+B, block inverses), the colouring and the bottom pseudo-inverse.  The two
+setups share no code; agreement is to rounding (A, S) or to the conditioning
+limit (pseudo-inverse)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from tests.gpu_common import lib_kwargs, oracle_build, smoother_matrix
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_2412_12506_amd", "libldgmg.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libldgmg.so not built")
+
+CASES = [
+    dict(id="p2d-p2-gl-jacobi", dim=2, n=8, p=2, basis="gl_nodal", smoother="jacobi"),
+    dict(id="p3d-p3-sai1", dim=3, n=4, p=3, smoother="sai"),
+    dict(id="i2d-p2-disc-sai1", dim=2, n=16, p=2, smoother="sai", mu=("disc", 0.25, 1e3)),
+    dict(id="i2d-p2-box-gs", dim=2, n=8, p=2, smoother="gs", mu=("box", 0.0, 1e4)),
+    dict(id="p2d-p1-sai2", dim=2, n=8, p=1, smoother="sai", sai_level=2),
+    dict(id="s2d-p2-stress-disc", dim=2, n=8, p=2, system="stokes", gamma=1, smoother="sai",
+         mu=("disc", 0.25, 1e3)),
+    dict(id="s2d-p1-std-jacobi", dim=2, n=8, p=1, system="stokes", gamma=0, smoother="jacobi"),
+    dict(id="p2d-p2-neumann-x", dim=2, n=8, p=2, smoother="sai", bc=["N", "N", "D", "D"]),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c["id"])
+def test_host_setup_matches_oracle(case):
+    from paper_2412_12506_amd import ldgmg as L
+    s = L.Solver(host_only=True, **lib_kwargs(case, "fp64"))
+    lv, vc = oracle_build(case)
+    try:
+        assert s.nlevels == len(lv)
+        for l in range(s.nlevels):
+            A = L.export_bsr(s.handle, l, "A").tocsr()
+            Ao = lv[l].A.tocsr()
+            assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max(), ("A", l)
+            if l < s.nlevels - 1:
+                S = L.export_bsr(s.handle, l, "S").tocsr()
+                So = smoother_matrix(vc, l)
+                assert abs(S - So).max() <= 1e-11 * abs(So).max(), ("S", l)
+                if case["smoother"] == "gs":
+                    assert np.array_equal(L.ldgmg_export_colours(s.handle, l), vc.levels[l].sm.colours)
+        P = L.ldgmg_export(s.handle, 0, "PINV")
+        Po = vc.levels[-1].pinv
+        Ab = vc.levels[-1].A.toarray()
+        lam = np.abs(np.linalg.eigvalsh(Ab))
+        kappa = lam.max() / lam[lam > 1e-12 * lam.max()].min()
+        assert np.abs(P - Po).max() <= max(1e-12, 20 * kappa * 2.0 ** -52) * np.abs(Po).max()
+        # Moore-Penrose identity A P A = A holds to rounding for either one
+        assert np.abs(Ab @ P @ Ab - Ab).max() <= 1e-12 * np.abs(Ab).max()
+    finally:
+        s.close()
+
+
+def test_sai_cache_counts():
+    """Uniform 3D grid, constant viscosity: the exact cache leaves 216 distinct
+    least-squares problems per level (6 classes per axis from the one-sided
+    flux and the two boundaries) and fewer on grids too small for them."""
+    from paper_2412_12506_amd import ldgmg as L
+    s = L.Solver(host_only=True, dim=3, n=16, p=1, smoother="sai", precision="fp64")
+    try:
+        counts = [L.ldgmg_setup_stats(s.handle, l)[0] for l in range(s.nlevels - 1)]
+        assert counts[0] == 216 and counts[1] == 216 and counts[2] == 64
+    finally:
+        s.close()
+
+
+def test_invalid_problems_are_rejected():
+    from paper_2412_12506_amd import ldgmg as L
+    for bad in (dict(dim=4, n=8, p=2), dict(dim=2, n=8, p=0), dict(dim=2, n=1, p=2),
+                dict(dim=2, n=8, p=2, bc=["P", "D", "D", "D"]),
+                dict(dim=2, n=4, p=2, mu=np.array([1.0] * 15 + [np.nan]))):
+        with pytest.raises((L.LdgmgError, ValueError)) as ei:
+            s = L.Solver(host_only=True, **bad)
+            s.close()
+        if isinstance(ei.value, L.LdgmgError):
+            assert ei.value.code == L.EINVAL
