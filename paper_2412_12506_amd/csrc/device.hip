@@ -52,6 +52,7 @@ struct DevLevel {
   int* ciS = nullptr;
   int* tposS = nullptr;
   void* valS = nullptr;
+  void* valST = nullptr;            // transposed copy: block (i,j) holds (S_ji)^T (fast kernels only)
   std::vector<int*> colour_rows;    // device lists per colour
   std::vector<int> colour_count;
   double* x = nullptr;              // level vectors are FP64 in both precisions
@@ -125,7 +126,7 @@ size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long n
   size_t b = 0;
   b += (ne + 1) * 4 + nnzA * 4 + nnzA * static_cast<size_t>(bs) * bs * eb;
   if (!bottom) {
-    b += (ne + 1) * 4 + nnzS * 8 + nnzS * static_cast<size_t>(bs) * bs * eb;
+    b += (ne + 1) * 4 + nnzS * 8 + nnzS * static_cast<size_t>(bs) * bs * eb * (fast_bs(bs) ? 2 : 1);
     if (gs) b += ne * 4;
   } else {
     b += N * N * 8;
@@ -174,6 +175,19 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
     dl.ciS = up_ints(hl.S.ci);
     dl.tposS = up_ints(hl.tpos);
     dl.valS = expand(hl.S, false);
+    if (fast_bs(hl.bs)) {   // S^T applies stream a transposed copy through the forward kernel
+      PMat st;
+      st.nbr = hl.S.nbr;
+      st.nbc = hl.S.nbc;
+      st.rp = hl.S.rp;
+      st.ci = hl.S.ci;
+      st.id.resize(hl.S.id.size());
+      for (size_t t = 0; t < st.id.size(); ++t) st.id[t] = hl.S.id[hl.tpos[t]];
+      st.pool.r = hl.S.pool.r;
+      st.pool.c = hl.S.pool.c;
+      st.pool.data = hl.S.pool.data;
+      dl.valST = expand(st, true);
+    }
     for (const auto& rows : hl.colour_rows) {
       dl.colour_rows.push_back(up_ints(rows));
       dl.colour_count.push_back(static_cast<int>(rows.size()));
@@ -346,8 +360,14 @@ void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* o
   a.out = out;
   a.alpha = alpha;
   a.beta = beta;
-  if (transposed) bsr_transposed<T, Vd>(a, st);
-  else bsr_forward<T, Vd>(a, st);
+  if (transposed && L.valST) {
+    a.blk = static_cast<const T*>(L.valST);
+    bsr_forward<T, Vd>(a, st);
+  } else if (transposed) {
+    bsr_transposed<T, Vd>(a, st);
+  } else {
+    bsr_forward<T, Vd>(a, st);
+  }
 }
 
 template <typename T>

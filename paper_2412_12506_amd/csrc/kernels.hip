@@ -28,6 +28,7 @@ template <typename VT> __device__ __forceinline__ VT vzero() { return VT{}; }
 __device__ __forceinline__ float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
+__device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ double readlane(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
@@ -61,51 +62,95 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
                                                       const TM* __restrict__ dinv, T omega) {
   using C = BlkCfg<TM, BS>;
   constexpr int V = C::V, G = C::G, NV = C::NV;
+  constexpr int CH = BS < 8 ? BS : 8;   // slots whose column index and x entry are fetched together
+  constexpr int NA = 4;                 // independent accumulators (breaks the FMA dependency chain)
   using VT = typename VecT<TM, V>::type;
+  // Every load below is unconditional from an address that is valid for every
+  // lane (idle lanes and missing slots point at row 0 / slot 0) and the unwanted
+  // values are masked afterwards: a load inside a divergent branch forces a
+  // wait for it before the branch joins, which would serialise the block loads.
   const int lane = threadIdx.x & 63;
   const int g = lane / BS;
   const int r = lane - g * BS;
   const int wave = blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int idx = wave * G + g;
   const bool active = (g < G) && (idx < nrows);
-  const int row = active ? (rows ? rows[idx] : idx) : 0;
-  const int s0 = active ? rp[row] : 0;
+  const int ridx = active ? idx : 0;
+  const int row_l = rows ? rows[ridx] : ridx;
+  const int row = active ? row_l : 0;
+  const int s0 = rp[row];
   const int cnt = active ? rp[row + 1] - s0 : 0;
   int mc = cnt;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o));
-  T acc = T(0);
-  for (int k = 0; k < mc; ++k) {
-    const bool has = k < cnt;
-    const int s = s0 + k;
-    const int j = has ? ci[s] : 0;
-    const T xv = has ? x[static_cast<size_t>(j) * BS + r] : T(0);
-    VT a[NV];
-    const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(has ? s : 0) * (BS * BS)) + r;
+  T acc[NA];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) a[q] = has ? bp[q * BS] : vzero<VT>();
+  for (int i = 0; i < NA; ++i) acc[i] = T(0);
+  for (int k0 = 0; k0 < mc; k0 += CH) {
+    // lane t < CH of each group fetches the column of slot k0 + t; every lane
+    // then fetches its entries of those CH neighbour vectors, so the block
+    // loads below wait for one memory latency only
+    const bool own = r < CH && k0 + r < cnt;
+    const int cl = ci[own ? s0 + k0 + r : 0];
+    const int cidx = own ? cl : -1;
+    T xv[CH];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
+    for (int t = 0; t < CH; ++t) {
+      const int j = group_bcast<int, BS>(cidx, g, t);
+      const T xl = x[static_cast<size_t>(j >= 0 ? j : 0) * BS + r];
+      xv[t] = j >= 0 ? xl : T(0);            // missing slot: multiplier 0
+    }
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc += static_cast<T>(elem(a[q], v)) * group_bcast<T, BS>(xv, g, q * V + v);
+    for (int t = 0; t < CH; ++t) {
+      if (k0 + t >= mc) break;                // wave-uniform
+      const int sl = k0 + t < cnt ? s0 + k0 + t : 0;
+      const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(sl) * (BS * BS)) + r;
+      VT a[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) a[q] = bp[q * BS];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        // keep the widening of each loaded vector next to its use (otherwise the
+        // scheduler widens the whole block at once and doubles the registers)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          acc[(q * V + v) % NA] += static_cast<T>(elem(a[q], v)) * group_bcast<T, BS>(xv[t], g, q * V + v);
+      }
     }
   }
+  T sum = acc[0];
+#pragma unroll
+  for (int i = 1; i < NA; ++i) sum += acc[i];
   const size_t o = static_cast<size_t>(row) * BS + r;
   if constexpr (MODE == 1) {
-    const T res = active ? z[o] - acc : T(0);
+    const T zo = z[o];
+    const T res = active ? zo - sum : T(0);
     VT d[NV];
     const VT* dp = reinterpret_cast<const VT*>(dinv + static_cast<size_t>(row) * (BS * BS)) + r;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) d[q] = active ? dp[q * BS] : vzero<VT>();
-    T y = T(0);
+    for (int q = 0; q < NV; ++q) d[q] = dp[q * BS];
+    T y[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) y[i] = T(0);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) y += static_cast<T>(elem(d[q], v)) * group_bcast<T, BS>(res, g, q * V + v);
+      for (int v = 0; v < V; ++v)
+        y[(q * V + v) % NA] += static_cast<T>(elem(d[q], v)) * group_bcast<T, BS>(res, g, q * V + v);
     }
-    if (active) out[o] = x[o] + omega * y;
+    T ys = y[0];
+#pragma unroll
+    for (int i = 1; i < NA; ++i) ys += y[i];
+    const T xo = x[o];
+    if (active) out[o] = xo + omega * ys;
   } else {
-    if (active) out[o] = beta != T(0) ? alpha * acc + beta * z[o] : alpha * acc;
+    if (beta != T(0)) {
+      const T zo = z[o];
+      if (active) out[o] = alpha * sum + beta * zo;
+    } else {
+      if (active) out[o] = alpha * sum;
+    }
   }
 }
 
@@ -133,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
   const int idx = wave * G + g;
   const bool active = (g < G) && (idx < nrows);
   const int row = active ? idx : 0;
-  const int s0 = active ? rp[row] : 0;
+  const int s0 = rp[row];
   const int cnt = active ? rp[row + 1] - s0 : 0;
   int mc = cnt;
 #pragma unroll
@@ -143,14 +188,15 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
   for (int c = 0; c < BS; ++c) acc[c] = T(0);
   for (int k = 0; k < mc; ++k) {
     const bool has = k < cnt;
-    const int s = s0 + k;
-    const int t = has ? tpos[s] : 0;
-    const int j = has ? ci[s] : 0;
-    const T xr = has ? x[static_cast<size_t>(j) * BS + r] : T(0);
+    const int s = has ? s0 + k : 0;
+    const int t = tpos[s];
+    const int j = ci[s];
+    const T xl = x[static_cast<size_t>(j) * BS + r];
+    const T xr = has ? xl : T(0);
     const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(t) * (BS * BS)) + r;
     VT a[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) a[q] = has ? bp[q * BS] : vzero<VT>();
+    for (int q = 0; q < NV; ++q) a[q] = bp[q * BS];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
 #pragma unroll
