@@ -115,6 +115,25 @@ def run_path(L, torch, args, precision, rhs, prof):
     return out
 
 
+def counter_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if that summary was taken with the current kernel source
+    (None otherwise)."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "bsr_fwd_fp32_bs64_poisson3d_n64_counters.json")
+    src_path = os.path.join(ROOT, "paper_2412_12506_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(prof))
+        src = open(src_path).read()
+        a = src.index("template <typename TM, typename T, int BS, int MODE>\n__global__ __launch_bounds__(kThreads) void k_bsr_fwd")
+        b = src.index("// ---------------------------------------------------------------------------\n// transposed BSR kernel")
+        if hashlib.sha256(src[a:b].encode()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def cpu_baseline(n_cpu):
     """The oracle, as it stands, on a bounded sample of the same workload:
     3D Poisson Q_3, SAI_1 OI V-cycle in CG, on an n_cpu^3 grid (setup untimed;
@@ -151,6 +170,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=8, help="grid of the CPU oracle sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
@@ -158,6 +179,17 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes BYTES each, so the
+        # HBM counters of this dispatch give the scale for the solver's kernels
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "launches": 3}), flush=True)
+        return
     from paper_2412_12506_amd import ldgmg as L
     from ldg_inputs import rhs_normal, BASE_SEED
 
@@ -181,7 +213,7 @@ def main():
     achieved = byts / mean_s / 1e9 if cnt else None
     roof = {"bound": "hbm", "kernel": "k_bsr_fwd<fp32 blocks, fp64 vectors, bs=64> (fine level)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": counter_traffic(),
             "launches": cnt, "mean_ms": ms / max(cnt, 1), "bytes_per_launch": byts,
             "other_kernels": {kk: {"mean_ms": v["mean_ms"], "gbs": v["gbs"], "count": v["count"]}
                               for kk, v in k.items() if kk in ("ST", "A64")}}

@@ -60,6 +60,8 @@ struct DevLevel {
   double* r = nullptr;
   double* t = nullptr;
   double* Ic = nullptr;             // child injection matrices [2^d][bss][bss]
+  double* P1 = nullptr;             // 1-D child matrices [2][p+1][p+1]
+  int q1 = 0;
   double* pinv = nullptr;           // bottom only
 };
 
@@ -132,7 +134,7 @@ size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long n
     b += N * N * 8;
   }
   b += 4 * N * 8;
-  b += (static_cast<size_t>(1) << dim) * bss * bss * 8;
+  b += (static_cast<size_t>(1) << dim) * bss * bss * 8 + 2 * 64 * 8;
   return b;
 }
 
@@ -211,6 +213,11 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
     std::copy(hl.em.Ic[c].begin(), hl.em.Ic[c].end(), ic.begin() + static_cast<size_t>(c) * hl.bss * hl.bss);
   dl.Ic = static_cast<double*>(D.alloc(ic.size() * sizeof(double)));
   HIPCHK(hipMemcpyAsync(dl.Ic, ic.data(), ic.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  dl.q1 = hl.em.q1;
+  std::vector<double> p1(hl.em.P[0]);
+  p1.insert(p1.end(), hl.em.P[1].begin(), hl.em.P[1].end());
+  dl.P1 = static_cast<double*>(D.alloc(p1.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(dl.P1, p1.data(), p1.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
 }
 
@@ -480,9 +487,9 @@ void vcycle_level(const Ctx& c, int l) {
   for (int s = 0; s < P.nu1; ++s) keep(smooth_step<T>(c, L, x, b, pre_fwd, s == 0));
   residual<T>(c.D, L, x, b, L.r, c.st);
   DevLevel& Lc = c.D.L[l + 1];
-  restrict_op<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, L.r, Lc.b, c.st);
+  restrict_op<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, L.r, Lc.b, c.st);
   vcycle_level<T>(c, l + 1);
-  prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, Lc.x, x, c.st);
+  prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, Lc.x, x, c.st);
   for (int s = 0; s < P.nu2; ++s) keep(smooth_step<T>(c, L, x, b, post_fwd, false));
 }
 
@@ -723,13 +730,13 @@ void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, v
     case LDGMG_OP_RESTRICT: {
       if (bottom) throw std::invalid_argument("no coarser level");
       DevLevel& Lc = c.D.L[l + 1];
-      restrict_op<Vd>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, a, o, c.st);
+      restrict_op<Vd>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, a, o, c.st);
       return;
     }
     case LDGMG_OP_PROLONG_ADD: {
       if (bottom) throw std::invalid_argument("no coarser level");
       DevLevel& Lc = c.D.L[l + 1];
-      prolong_add<Vd>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, Lc.Ic, a, o, c.st);
+      prolong_add<Vd>(c.H.prob.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, a, o, c.st);
       return;
     }
     case LDGMG_OP_BOTTOM:

@@ -340,6 +340,106 @@ __global__ void k_prolong_add(int dim, int nc, int ncomp, int bss, const T* __re
   xf[tid] += sum;
 }
 
+// Sum-factorised transfers (bss <= 64): one wavefront per (element,
+// component); lane = scalar coefficient (digit k of the lane index is the
+// degree in dimension k).  The tensor-product child matrix is applied one
+// dimension at a time through LDS: (p+1) products per lane and dimension
+// instead of bss.  P1 holds the 1-D child matrices, P1[c][i][j] = coefficient
+// i on child c of the coarse basis function j.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_sf(int dim, int nc, int ncomp, int q1, int bss,
+                                                    const T* __restrict__ P1, const T* __restrict__ xc,
+                                                    T* __restrict__ xf, long long nwork) {
+  __shared__ T buf[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long work = static_cast<long long>(blockIdx.x) * 4 + w;
+  const bool valid = work < nwork;
+  const long long wk = valid ? work : 0;
+  const long long f = wk / ncomp;
+  const int comp = static_cast<int>(wk - f * ncomp);
+  const int nf = 2 * nc;
+  const int fx = static_cast<int>(f % nf), fy = static_cast<int>((f / nf) % nf);
+  const int fz = dim == 3 ? static_cast<int>(f / (static_cast<long long>(nf) * nf)) : 0;
+  const int cb[3] = {fx & 1, fy & 1, fz & 1};
+  const long long K = (fx >> 1) + static_cast<long long>(nc) * ((fy >> 1) + static_cast<long long>(nc) * (fz >> 1));
+  const bool act = lane < bss;
+  const int li = act ? lane : 0;
+  int dg[3] = {0, 0, 0};
+  {
+    int rem = li;
+    for (int k = 0; k < dim; ++k) {
+      dg[k] = rem % q1;
+      rem /= q1;
+    }
+  }
+  const T xl = xc[(K * ncomp + comp) * bss + li];
+  T v = act ? xl : T(0);
+  int stride = 1;
+  for (int k = 0; k < dim; ++k) {
+    buf[w][lane] = v;
+    __syncthreads();
+    T sum = T(0);
+    const T* Pr = P1 + (cb[k] * q1 + dg[k]) * q1;
+    const int base = li - dg[k] * stride;
+    for (int j = 0; j < q1; ++j) sum += Pr[j] * buf[w][base + j * stride];
+    __syncthreads();
+    v = sum;
+    stride *= q1;
+  }
+  const size_t o = static_cast<size_t>((f * ncomp + comp) * bss + li);
+  const T old = xf[o];
+  if (valid && act) xf[o] = old + v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_sf(int dim, int nc, int ncomp, int q1, int bss,
+                                                     const T* __restrict__ P1, const T* __restrict__ rf,
+                                                     T* __restrict__ rc, long long nwork) {
+  __shared__ T buf[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long work = static_cast<long long>(blockIdx.x) * 4 + w;
+  const bool valid = work < nwork;
+  const long long wk = valid ? work : 0;
+  const long long K = wk / ncomp;
+  const int comp = static_cast<int>(wk - K * ncomp);
+  const int kx = static_cast<int>(K % nc), ky = static_cast<int>((K / nc) % nc);
+  const int kz = dim == 3 ? static_cast<int>(K / (static_cast<long long>(nc) * nc)) : 0;
+  const int nf = 2 * nc;
+  const bool act = lane < bss;
+  const int li = act ? lane : 0;
+  int dg[3] = {0, 0, 0};
+  {
+    int rem = li;
+    for (int k = 0; k < dim; ++k) {
+      dg[k] = rem % q1;
+      rem /= q1;
+    }
+  }
+  T acc = T(0);
+  const int nchild = 1 << dim;
+  for (int cp = 0; cp < nchild; ++cp) {
+    const int cb[3] = {cp & 1, (cp >> 1) & 1, (cp >> 2) & 1};
+    const long long f = (2 * kx + cb[0]) +
+                        static_cast<long long>(nf) * ((2 * ky + cb[1]) + static_cast<long long>(nf) * (dim == 3 ? 2 * kz + cb[2] : 0));
+    const T rl = rf[(f * ncomp + comp) * bss + li];
+    T v = act ? rl : T(0);
+    int stride = 1;
+    for (int k = 0; k < dim; ++k) {
+      buf[w][lane] = v;
+      __syncthreads();
+      T sum = T(0);
+      const int base = li - dg[k] * stride;
+      // transpose of the child matrix: sum over the child degree j of P1[c][j][a]
+      for (int j = 0; j < q1; ++j) sum += P1[(cb[k] * q1 + j) * q1 + dg[k]] * buf[w][base + j * stride];
+      __syncthreads();
+      v = sum;
+      stride *= q1;
+    }
+    acc += v;
+  }
+  if (valid && act) rc[(K * ncomp + comp) * bss + li] = acc;
+}
+
 // dense FP64 GEMV (bottom pseudo-inverse): one wavefront per row
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_gemv(int N, const double* __restrict__ P,
@@ -600,18 +700,32 @@ void expand_blocks(long long nslots, int bs, const int* ids, const double* pool,
 }
 
 template <typename T>
-void restrict_op(int dim, int nc, int ncomp, int bss, const T* Ic, const T* rf, T* rc, hipStream_t st) {
+void restrict_op(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* rf, T* rc,
+                 hipStream_t st) {
   long long nce = nc;
   for (int k = 1; k < dim; ++k) nce *= nc;
+  if (bss <= 64) {
+    const long long nwork = nce * ncomp;
+    k_restrict_sf<T><<<static_cast<int>((nwork + 3) / 4), 256, 0, st>>>(dim, nc, ncomp, q1, bss, P1, rf, rc, nwork);
+    check_launch("restrict_sf");
+    return;
+  }
   const long long total = nce * ncomp * bss;
   k_restrict<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, rf, rc);
   check_launch("restrict");
 }
 
 template <typename T>
-void prolong_add(int dim, int nc, int ncomp, int bss, const T* Ic, const T* xc, T* xf, hipStream_t st) {
+void prolong_add(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* xc, T* xf,
+                 hipStream_t st) {
   long long nfe = 2 * nc;
   for (int k = 1; k < dim; ++k) nfe *= 2 * nc;
+  if (bss <= 64) {
+    const long long nwork = nfe * ncomp;
+    k_prolong_sf<T><<<static_cast<int>((nwork + 3) / 4), 256, 0, st>>>(dim, nc, ncomp, q1, bss, P1, xc, xf, nwork);
+    check_launch("prolong_sf");
+    return;
+  }
   const long long total = nfe * ncomp * bss;
   k_prolong_add<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, xc, xf);
   check_launch("prolong");
@@ -680,10 +794,10 @@ template void bsr_transposed<float, double>(const BsrArgs<float, double>&, hipSt
 template void bsr_transposed<double, double>(const BsrArgs<double, double>&, hipStream_t);
 template void expand_blocks<float>(long long, int, const int*, const double*, float*, bool, hipStream_t);
 template void expand_blocks<double>(long long, int, const int*, const double*, double*, bool, hipStream_t);
-template void restrict_op<float>(int, int, int, int, const float*, const float*, float*, hipStream_t);
-template void restrict_op<double>(int, int, int, int, const double*, const double*, double*, hipStream_t);
-template void prolong_add<float>(int, int, int, int, const float*, const float*, float*, hipStream_t);
-template void prolong_add<double>(int, int, int, int, const double*, const double*, double*, hipStream_t);
+template void restrict_op<double>(int, int, int, int, int, const double*, const double*, const double*, double*,
+                                  hipStream_t);
+template void prolong_add<double>(int, int, int, int, int, const double*, const double*, const double*, double*,
+                                  hipStream_t);
 template void dense_gemv<float>(int, const double*, const float*, float*, hipStream_t);
 template void dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);
 template void cast<double, float>(long long, const double*, float*, hipStream_t);

@@ -48,10 +48,15 @@ template <typename TM, typename T> void bsr_transposed(const BsrArgs<TM, T>& a, 
 template <typename T>
 void expand_blocks(long long nslots, int bs, const int* ids, const double* pool, T* out, bool transpose,
                    hipStream_t st);
+// transfers between a level (fine) and the next (coarse, nc elements per side); P1 = the
+// 1-D child matrices [2][q1][q1] (sum-factorised kernels when bss <= 64), Ic = the full
+// tensor-product child matrices [2^dim][bss][bss] (other block sizes)
 template <typename T>
-void restrict_op(int dim, int nc, int ncomp, int bss, const T* Ic, const T* rf, T* rc, hipStream_t st);
+void restrict_op(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* rf, T* rc,
+                 hipStream_t st);
 template <typename T>
-void prolong_add(int dim, int nc, int ncomp, int bss, const T* Ic, const T* xc, T* xf, hipStream_t st);
+void prolong_add(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* xc, T* xf,
+                 hipStream_t st);
 template <typename T> void dense_gemv(int N, const double* P, const T* in, T* out, hipStream_t st);
 
 void dot_partial(long long n, const double* a, const double* b, double* partial, hipStream_t st);
