@@ -166,59 +166,77 @@ class ScalarLDG:
         return self.em.bs
 
 
+def gradient_row(grid: Grid, em: ElementMatrices, mu, e: int, k: int) -> dict:
+    """Block row e of G_k: M (G_k u)_e = int_e d_k u w + sum over the two faces
+    of e normal to e_k of int_F (u-hat - u_e) w n_k, with u-hat from the flux
+    rule; on Dirichlet faces the operator part of u-hat is 0 (the data part is
+    `dirichlet_lifting`).  Returns {column element: block}."""
+    blocks = {}
+    _add(blocks, e, em.D[k])
+    # lower face, outward normal -e_k
+    src, L = flux_source_lower_face(grid, mu, e, k)
+    if src == "nbr":          # -(u_L - u_e)
+        _add(blocks, L, -em.T[k, -1, +1])
+        _add(blocks, e, em.T[k, -1, -1])
+    elif src == "dirichlet":  # -(0 - u_e)
+        _add(blocks, e, em.T[k, -1, -1])
+    # upper face, outward normal +e_k
+    src, R = flux_source_upper_face(grid, mu, e, k)
+    if src == "nbr":          # +(u_R - u_e)
+        _add(blocks, R, em.T[k, +1, -1])
+        _add(blocks, e, -em.T[k, +1, +1])
+    elif src == "dirichlet":  # +(0 - u_e)
+        _add(blocks, e, -em.T[k, +1, +1])
+    return {J: em.Minv @ B for J, B in blocks.items()}
+
+
 def assemble_gradient(grid: Grid, em: ElementMatrices, mu) -> list:
-    """G_k with M (G_k u)_K = int_K d_k u w + sum_{faces} int_F (u-hat - u_K) w n_k,
-    u-hat from the flux rule; Dirichlet faces use u-hat = g, whose operator part
-    is u-hat = 0 (the data part is `dirichlet_lifting`)."""
+    """G_k for k = 1..d as BSR matrices, row by row (`gradient_row`)."""
     G = []
-    bs = em.bs
     for k in range(grid.dim):
         blocks = {}
         for e in range(grid.ne):
-            _add(blocks, (e, e), em.D[k])
-            # lower face, outward normal -e_k
-            src, L = flux_source_lower_face(grid, mu, e, k)
-            if src == "nbr":          # -(u_L - u_e)
-                _add(blocks, (e, L), -em.T[k, -1, +1])
-                _add(blocks, (e, e), em.T[k, -1, -1])
-            elif src == "dirichlet":  # -(0 - u_e)
-                _add(blocks, (e, e), em.T[k, -1, -1])
-            # upper face, outward normal +e_k
-            src, R = flux_source_upper_face(grid, mu, e, k)
-            if src == "nbr":          # +(u_R - u_e)
-                _add(blocks, (e, R), em.T[k, +1, -1])
-                _add(blocks, (e, e), -em.T[k, +1, +1])
-            elif src == "dirichlet":  # +(0 - u_e)
-                _add(blocks, (e, e), -em.T[k, +1, +1])
-        for key in blocks:
-            blocks[key] = em.Minv @ blocks[key]
-        G.append(_bsr(blocks, grid.ne, bs))
+            for J, B in gradient_row(grid, em, mu, e, k).items():
+                blocks[(e, J)] = B
+        G.append(_bsr(blocks, grid.ne, em.bs))
     return G
+
+
+def penalty_row(grid: Grid, em: ElementMatrices, mu, e: int, tau0: float,
+                interior_tau=None, dirichlet=True) -> dict:
+    """Block row e of E = sum_F tau_F int_F [u][v]: interior tau = tau0 min(mu)/h
+    and Dirichlet tau = tau0 mu_e / h (reading of the penalty; see module
+    docstring).  `interior_tau(mu_lower, mu_upper)` overrides the interior
+    weight and `dirichlet=False` drops the boundary faces (pressure penalty)."""
+    h = grid.h
+    tau_of = (lambda a, b: tau0 * min(mu[a], mu[b]) / h) if interior_tau is None else \
+        (lambda a, b: interior_tau(mu[a], mu[b]))
+    blocks = {e: np.zeros((em.bs, em.bs))}
+    for k in range(grid.dim):
+        L = grid.neighbour(e, k, -1)
+        if L is not None:          # face (L, e): e is the upper side
+            tau = tau_of(L, e)
+            _add(blocks, e, tau * em.T[k, -1, -1])
+            _add(blocks, L, -tau * em.T[k, -1, +1])
+        elif dirichlet and grid.boundary_type(k, -1) == "D":
+            _add(blocks, e, tau0 * mu[e] / h * em.T[k, -1, -1])
+        R = grid.neighbour(e, k, +1)
+        if R is not None:          # face (e, R): e is the lower side
+            tau = tau_of(e, R)
+            _add(blocks, e, tau * em.T[k, +1, +1])
+            _add(blocks, R, -tau * em.T[k, +1, -1])
+        elif dirichlet and grid.boundary_type(k, +1) == "D":
+            _add(blocks, e, tau0 * mu[e] / h * em.T[k, +1, +1])
+    return blocks
 
 
 def assemble_penalty(grid: Grid, em: ElementMatrices, mu, tau0: float,
                      interior_tau=None, dirichlet=True) -> sp.bsr_matrix:
-    """E = sum_F tau_F int_F [u][v]; interior tau = tau0 min(mu)/h, Dirichlet
-    tau = tau0 mu_K / h (reading of the penalty; see module docstring).
-    `interior_tau(mu_L, mu_R)` overrides the interior weight and
-    `dirichlet=False` drops the boundary faces (used for the pressure penalty)."""
+    """E as a BSR matrix, row by row (`penalty_row`)."""
     blocks = {}
-    h = grid.h
     for e in range(grid.ne):
-        _add(blocks, (e, e), np.zeros((em.bs, em.bs)))
-        for k in range(grid.dim):
-            R = grid.neighbour(e, k, +1)
-            if R is not None:          # interior face, e lower, R upper
-                tau = (tau0 * min(mu[e], mu[R]) / h if interior_tau is None
-                       else interior_tau(mu[e], mu[R]))
-                _add(blocks, (e, e), tau * em.T[k, +1, +1])
-                _add(blocks, (R, R), tau * em.T[k, -1, -1])
-                _add(blocks, (e, R), -tau * em.T[k, +1, -1])
-                _add(blocks, (R, e), -tau * em.T[k, -1, +1])
-            for side in (-1, 1):
-                if dirichlet and grid.neighbour(e, k, side) is None \
-                        and grid.boundary_type(k, side) == "D":
-                    _add(blocks, (e, e), tau0 * mu[e] / h * em.T[k, side, side])
+        for J, B in penalty_row(grid, em, mu, e, tau0, interior_tau, dirichlet).items():
+            blocks[(e, J)] = B
     return _bsr(blocks, grid.ne, em.bs)
 
 

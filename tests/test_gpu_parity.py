@@ -41,6 +41,7 @@ CASES = [
     dict(id="p3d-p3-sai1", dim=3, n=6, p=3, smoother="sai", sai_level=1),
     dict(id="i3d-p2-sphere-sai1", dim=3, n=8, p=2, smoother="sai", mu=("sphere", 0.3, 1e4)),
     dict(id="i2d-p1-box-gs", dim=2, n=12, p=1, smoother="gs", mu=("box", 0.0, 1e-4)),
+    dict(id="i3d-p1-n12-sphere-sai1", dim=3, n=12, p=1, smoother="sai", mu=("sphere", 0.3, 1e4)),
     dict(id="p2d-p3-sai2", dim=2, n=8, p=3, smoother="sai", sai_level=2),
     dict(id="s2d-p2-stress-disc-sai1", dim=2, n=8, p=2, system="stokes", gamma=1,
          smoother="sai", mu=("disc", 0.25, 1e3), krylov="gmres"),
