@@ -151,6 +151,21 @@ int ldgmg_vcycle(ldgmg_handle h, const double* b_dev, double* x_dev, void* strea
 int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov,
                 double rtol, int maxit, ldgmg_info* info, void* stream);
 
+/* Batched serving step: k <= 8 right-hand sides of the same hierarchy.  Each
+ * right-hand side runs its own preconditioned CG recurrence (as ldgmg_solve
+ * with LDGMG_CG; right-hand sides that converge are frozen), while every
+ * V-cycle stage and every operator apply of the batch streams each matrix
+ * block once for all k vectors.  b_dev / x_dev: host arrays of k device FP64
+ * pointers (fine-level layout).  infos: k entries or NULL.  Returns
+ * LDGMG_ENOCONV if any right-hand side reaches maxit.  Needs workspace of
+ * 9 k-vector sets on the fine level (allocated on the first batched call). */
+int ldgmg_solve_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k,
+                      double rtol, int maxit, ldgmg_info* infos, void* stream);
+
+/* x_q = V b_q for k <= 8 right-hand sides with one batched V-cycle. */
+int ldgmg_vcycle_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k,
+                       void* stream);
+
 /* Single operations of the V-cycle on one level, for checking each kernel.
  * in1/in2/out are device FP64 vectors of the level (ne*bs entries; the
  * coarse vector of RESTRICT / PROLONG_ADD has the next level's size).

@@ -80,6 +80,15 @@ struct DevHier {
   double* hvec = nullptr;           // device small vectors (GMRES coefficients)
   std::vector<void*> allocs;
   size_t bytes = 0;
+  // batched solves (ldgmg_solve_batch): per level [kMaxRhs][N] x, b, r, t and the
+  // fine-level Krylov vectors; allocated on the first batched call
+  struct BatchLevel {
+    double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+  };
+  std::vector<BatchLevel> BL;
+  double *bx = nullptr, *br = nullptr, *bp = nullptr, *bq = nullptr, *bz = nullptr;
+  double* bscal = nullptr;          // per right-hand side scalars [kMaxRhs][8]
+  double* hbscal = nullptr;         // pinned host mirror
   // fine-level launch timing (ldgmg_profile)
   bool prof = false;
   std::vector<hipEvent_t> evpool;
@@ -102,6 +111,7 @@ struct DevHier {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (hscal) (void)hipHostFree(hscal);
+    if (hbscal) (void)hipHostFree(hbscal);
   }
 };
 
@@ -694,6 +704,239 @@ int solve_gmres(const Ctx& c, const double* b, double* x, double rtol, int maxit
   return conv ? LDGMG_OK : LDGMG_ENOCONV;
 }
 
+// ---------------------------------------------------------------------------
+// batched V-cycle and CG: nk right-hand sides on one hierarchy; every level
+// vector holds nk vectors at a stride of the level size
+// ---------------------------------------------------------------------------
+void ensure_batch(DevHier& D, hipStream_t st) {
+  if (!D.BL.empty()) return;
+  D.BL.resize(D.L.size());
+  for (size_t l = 0; l < D.L.size(); ++l) {
+    const size_t vb = static_cast<size_t>(D.L[l].N) * kMaxRhs * sizeof(double);
+    auto& B = D.BL[l];
+    B.x = static_cast<double*>(D.alloc(vb));
+    B.b = static_cast<double*>(D.alloc(vb));
+    B.r = static_cast<double*>(D.alloc(vb));
+    B.t = static_cast<double*>(D.alloc(vb));
+    HIPCHK(hipMemsetAsync(B.r, 0, vb, st));
+    HIPCHK(hipMemsetAsync(B.t, 0, vb, st));
+  }
+  const size_t vb = static_cast<size_t>(D.L[0].N) * kMaxRhs * sizeof(double);
+  D.bx = static_cast<double*>(D.alloc(vb));
+  D.br = static_cast<double*>(D.alloc(vb));
+  D.bp = static_cast<double*>(D.alloc(vb));
+  D.bq = static_cast<double*>(D.alloc(vb));
+  D.bz = static_cast<double*>(D.alloc(vb));
+  D.bscal = static_cast<double*>(D.alloc(kMaxRhs * 8 * sizeof(double)));
+  HIPCHK(hipMemsetAsync(D.bscal, 0, kMaxRhs * 8 * sizeof(double), st));
+  HIPCHK(hipHostMalloc(&D.hbscal, kMaxRhs * 8 * sizeof(double), hipHostMallocDefault));
+}
+
+template <typename T>
+void residual_multi(DevHier& D, const DevLevel& L, const Vd* x, const Vd* b, Vd* out, int nk, hipStream_t st,
+                    int nrows = -1, const int* rows = nullptr) {
+  ProfScope ps(D, L, st, K_A);
+  BsrArgs<T, Vd> a = argsA<T>(L);
+  if (rows) {
+    a.nrows = nrows;
+    a.rows = rows;
+  }
+  a.x = x;
+  a.z = b;
+  a.out = out;
+  a.alpha = -1.0;
+  a.beta = 1.0;
+  bsr_forward_multi<T, Vd>(a, L.N, nk, st);
+}
+
+// out = alpha S x + beta z (S^T through the transposed copy)
+template <typename T>
+void apply_S_multi(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* out, Vd alpha,
+                   Vd beta, int nk, hipStream_t st, int nrows = -1, const int* rows = nullptr) {
+  if (transposed && !L.valST) {
+    for (int q = 0; q < nk; ++q)
+      apply_S<T>(D, L, true, x + q * L.N, z ? z + q * L.N : nullptr, out + q * L.N, alpha, beta, st);
+    return;
+  }
+  ProfScope ps(D, L, st, transposed ? K_ST : K_SF);
+  BsrArgs<T, Vd> a = argsS<T>(L);
+  if (transposed) a.blk = static_cast<const T*>(L.valST);
+  if (rows) {
+    a.nrows = nrows;
+    a.rows = rows;
+  }
+  a.x = x;
+  a.z = z;
+  a.out = out;
+  a.alpha = alpha;
+  a.beta = beta;
+  bsr_forward_multi<T, Vd>(a, L.N, nk, st);
+}
+
+template <typename T>
+void smooth_step_multi(const Ctx& c, DevLevel& L, DevHier::BatchLevel& B, bool forward, bool zero_x, int nk) {
+  const int sm = c.H.prob.smoother;
+  const Vd omega = c.H.omega;
+  const size_t vb = static_cast<size_t>(L.N) * nk * sizeof(Vd);
+  if (sm == LDGMG_SMOOTH_SAI) {
+    if (zero_x) {
+      apply_S_multi<T>(c.D, L, !forward, B.b, nullptr, B.x, 1.0, 0.0, nk, c.st);
+      return;
+    }
+    residual_multi<T>(c.D, L, B.x, B.b, B.r, nk, c.st);
+    apply_S_multi<T>(c.D, L, !forward, B.r, B.x, B.x, 1.0, 1.0, nk, c.st);
+    return;
+  }
+  if (sm == LDGMG_SMOOTH_JACOBI) {
+    if (zero_x) {
+      apply_S_multi<T>(c.D, L, false, B.b, nullptr, B.x, omega, 0.0, nk, c.st);
+      return;
+    }
+    residual_multi<T>(c.D, L, B.x, B.b, B.r, nk, c.st);
+    apply_S_multi<T>(c.D, L, false, B.r, B.x, B.x, omega, 1.0, nk, c.st);
+    return;
+  }
+  if (zero_x) HIPCHK(hipMemsetAsync(B.x, 0, vb, c.st));
+  const int ncol = static_cast<int>(L.colour_rows.size());
+  for (int k = 0; k < ncol; ++k) {
+    const int col = forward ? k : ncol - 1 - k;
+    residual_multi<T>(c.D, L, B.x, B.b, B.r, nk, c.st, L.colour_count[col], L.colour_rows[col]);
+    apply_S_multi<T>(c.D, L, false, B.r, B.x, B.x, omega, 1.0, nk, c.st, L.colour_count[col], L.colour_rows[col]);
+  }
+}
+
+template <typename T>
+void vcycle_level_multi(const Ctx& c, int l, int nk) {
+  DevLevel& L = c.D.L[l];
+  DevHier::BatchLevel& B = c.D.BL[l];
+  const int nl = static_cast<int>(c.D.L.size());
+  if (l == nl - 1) {
+    for (int q = 0; q < nk; ++q)
+      dense_gemv<Vd>(static_cast<int>(L.N), L.pinv, B.b + q * L.N, B.x + q * L.N, c.st);
+    return;
+  }
+  const ldgmg_problem& P = c.H.prob;
+  const bool pre_fwd = order_pre_forward(P.order), post_fwd = order_post_forward(P.order);
+  if (P.nu1 == 0) HIPCHK(hipMemsetAsync(B.x, 0, static_cast<size_t>(L.N) * nk * sizeof(Vd), c.st));
+  for (int s = 0; s < P.nu1; ++s) smooth_step_multi<T>(c, L, B, pre_fwd, s == 0, nk);
+  residual_multi<T>(c.D, L, B.x, B.b, B.r, nk, c.st);
+  DevLevel& Lc = c.D.L[l + 1];
+  DevHier::BatchLevel& Bc = c.D.BL[l + 1];
+  for (int q = 0; q < nk; ++q)
+    restrict_op<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, B.r + q * L.N, Bc.b + q * Lc.N, c.st);
+  vcycle_level_multi<T>(c, l + 1, nk);
+  for (int q = 0; q < nk; ++q)
+    prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, Bc.x + q * Lc.N, B.x + q * L.N, c.st);
+  for (int s = 0; s < P.nu2; ++s) smooth_step_multi<T>(c, L, B, post_fwd, false, nk);
+}
+
+// z_q = V r_q for the nk vectors at r and z (stride N)
+void vcycle64_multi(const Ctx& c, const double* r, double* z, int nk) {
+  DevLevel& L = c.D.L[0];
+  DevHier::BatchLevel& B = c.D.BL[0];
+  const size_t vb = static_cast<size_t>(L.N) * nk * 8;
+  HIPCHK(hipMemcpyAsync(B.b, r, vb, hipMemcpyDeviceToDevice, c.st));
+  if (c.D.prec == LDGMG_FP64) vcycle_level_multi<double>(c, 0, nk);
+  else vcycle_level_multi<float>(c, 0, nk);
+  HIPCHK(hipMemcpyAsync(z, B.x, vb, hipMemcpyDeviceToDevice, c.st));
+}
+
+void apply_A64_multi(const Ctx& c, const double* x, double* y, int nk) {
+  const DevLevel& L = c.D.L[0];
+  BsrArgs<double, double> a;
+  a.nrows = L.ne;
+  a.bs = L.bs;
+  a.rp = L.rpA;
+  a.ci = L.ciA;
+  a.blk = c.D.val64;
+  a.x = x;
+  a.out = y;
+  ProfScope ps(c.D, L, c.st, K_A64);
+  bsr_forward_multi<double, double>(a, L.N, nk, c.st);
+}
+
+// nk preconditioned CG recurrences sharing every V-cycle and operator pass
+int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int nk, double rtol, int maxit,
+                   ldgmg_info* infos) {
+  DevHier& D = c.D;
+  ensure_batch(D, c.st);
+  const long long N = D.L[0].N;
+  double* sc = D.bscal;
+  auto slot = [](int q, int s) { return q * 8 + s; };
+  enum { BB = 0, RZ = 1, AL = 2, RR = 3, BE = 4, TMP = 5 };
+  for (int q = 0; q < nk; ++q) {
+    HIPCHK(hipMemcpyAsync(D.br + q * N, b[q], N * 8, hipMemcpyDeviceToDevice, c.st));
+    dot_partial(N, b[q], b[q], D.partial, c.st);
+    finalize(D.partial, sc, 0, slot(q, BB), 0, c.st);
+  }
+  HIPCHK(hipMemsetAsync(D.bx, 0, static_cast<size_t>(N) * nk * 8, c.st));
+  HIPCHK(hipMemcpyAsync(D.hbscal, sc, kMaxRhs * 8 * 8, hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  std::vector<double> bb(nk), rr(nk), rel(nk, 0.0);
+  std::vector<std::vector<double>> hist(nk);
+  std::vector<int> iters(nk, 0);
+  std::vector<char> done(nk, 0);
+  for (int q = 0; q < nk; ++q) {
+    bb[q] = D.hbscal[slot(q, BB)];
+    if (!std::isfinite(bb[q])) throw std::invalid_argument("right-hand side contains NaN or Inf");
+    done[q] = bb[q] == 0.0;
+  }
+  vcycle64_multi(c, D.br, D.bz, nk);
+  int vcycles = 1;
+  for (int q = 0; q < nk; ++q) {
+    dot_partial(N, D.br + q * N, D.bz + q * N, D.partial, c.st);
+    finalize(D.partial, sc, 0, slot(q, RZ), 0, c.st);
+  }
+  HIPCHK(hipMemcpyAsync(D.bp, D.bz, static_cast<size_t>(N) * nk * 8, hipMemcpyDeviceToDevice, c.st));
+  int it = 0;
+  while (it < maxit) {
+    bool all = true;
+    for (int q = 0; q < nk; ++q) all = all && done[q];
+    if (all) break;
+    apply_A64_multi(c, D.bp, D.bq, nk);
+    for (int q = 0; q < nk; ++q) {
+      if (done[q]) continue;
+      dot_partial(N, D.bp + q * N, D.bq + q * N, D.partial, c.st);
+      finalize(D.partial, sc, 1, slot(q, AL), slot(q, RZ), c.st);
+      cg_update(N, D.bx + q * N, D.br + q * N, D.bp + q * N, D.bq + q * N, sc, slot(q, AL), D.partial, c.st);
+      finalize(D.partial, sc, 0, slot(q, RR), 0, c.st);
+    }
+    HIPCHK(hipMemcpyAsync(D.hbscal, sc, kMaxRhs * 8 * 8, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    ++it;
+    bool more = false;
+    for (int q = 0; q < nk; ++q) {
+      if (done[q]) continue;
+      hist[q].push_back(std::sqrt(std::fabs(D.hbscal[slot(q, RZ)])));
+      iters[q] = it;
+      rr[q] = D.hbscal[slot(q, RR)];
+      if (!std::isfinite(rr[q])) throw std::runtime_error("CG breakdown (non-finite residual)");
+      if (rr[q] <= rtol * rtol * bb[q]) done[q] = 1;
+      else more = true;
+    }
+    if (!more) break;
+    vcycle64_multi(c, D.br, D.bz, nk);
+    ++vcycles;
+    for (int q = 0; q < nk; ++q) {
+      if (done[q]) continue;
+      dot_partial(N, D.br + q * N, D.bz + q * N, D.partial, c.st);
+      finalize(D.partial, sc, 2, slot(q, BE), slot(q, RZ), c.st);
+      cg_dir(N, D.bp + q * N, D.bz + q * N, sc, slot(q, BE), c.st);
+    }
+  }
+  bool all_conv = true;
+  for (int q = 0; q < nk; ++q) {
+    HIPCHK(hipMemcpyAsync(x[q], D.bx + q * N, N * 8, hipMemcpyDeviceToDevice, c.st));
+    all_conv = all_conv && done[q];
+    if (infos) {
+      finish_info(c, b[q], x[q], bb[q], hist[q], iters[q], done[q] != 0,
+                  bb[q] > 0 ? std::sqrt(std::fabs(rr[q]) / bb[q]) : 0.0, vcycles, &infos[q]);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c.st));
+  return all_conv ? LDGMG_OK : LDGMG_ENOCONV;
+}
+
 template <typename T>
 void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, void* out) {
   DevLevel& L = c.D.L[l];
@@ -976,6 +1219,37 @@ int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov, 
     if (krylov == LDGMG_CG) return solve_cg(c, b_dev, x_dev, rtol, maxit, info);
     if (krylov == LDGMG_GMRES) return solve_gmres(c, b_dev, x_dev, rtol, maxit, info);
     throw std::invalid_argument("unknown krylov method");
+  });
+}
+
+int ldgmg_vcycle_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k, void* stream) {
+  return guarded([&] {
+    need_dev(h);
+    if (!b_dev || !x_dev || k < 1 || k > kMaxRhs) throw std::invalid_argument("bad batch arguments");
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    ensure_batch(*h->dev, c.st);
+    const long long N = h->dev->L[0].N;
+    for (int q = 0; q < k; ++q) {
+      if (!b_dev[q] || !x_dev[q]) throw std::invalid_argument("null vector in batch");
+      HIPCHK(hipMemcpyAsync(h->dev->br + q * N, b_dev[q], N * 8, hipMemcpyDeviceToDevice, c.st));
+    }
+    vcycle64_multi(c, h->dev->br, h->dev->bz, k);
+    for (int q = 0; q < k; ++q)
+      HIPCHK(hipMemcpyAsync(x_dev[q], h->dev->bz + q * N, N * 8, hipMemcpyDeviceToDevice, c.st));
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_solve_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k, double rtol,
+                      int maxit, ldgmg_info* infos, void* stream) {
+  return guarded([&] {
+    need_dev(h);
+    if (!b_dev || !x_dev || k < 1 || k > kMaxRhs) throw std::invalid_argument("bad batch arguments");
+    if (!(rtol > 0) || maxit < 1) throw std::invalid_argument("rtol must be > 0 and maxit >= 1");
+    for (int q = 0; q < k; ++q)
+      if (!b_dev[q] || !x_dev[q]) throw std::invalid_argument("null vector in batch");
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    return solve_cg_batch(c, b_dev, x_dev, k, rtol, maxit, infos);
   });
 }
 

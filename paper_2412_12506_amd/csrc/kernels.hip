@@ -155,6 +155,93 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
 }
 
 // ---------------------------------------------------------------------------
+// multi-right-hand-side forward BSR kernel: out_q = alpha (M x_q) + beta z_q for
+// q < nk <= kMaxRhs vectors stored with a stride.  Each block is read from HBM
+// once for all right-hand sides; a lane's entries of the nk neighbour vectors
+// are staged in LDS ([slot][rhs]) and read back as broadcasts, so a column of
+// a block costs one widening and nk FP64 FMAs.  (On gfx950 FP64 matrix cores
+// have the same rate as FP64 vector FMA, so the FP64 accumulation that keeps
+// the Krylov iteration counts stays on the vector units.)
+// ---------------------------------------------------------------------------
+template <typename TM, typename T, int BS>
+__global__ __launch_bounds__(kThreads) void k_bsr_fwd_multi(int nrows, const int* __restrict__ rows,
+                                                            const int* __restrict__ rp,
+                                                            const int* __restrict__ ci,
+                                                            const TM* __restrict__ blk, const T* x,
+                                                            const T* z, T* out, long long stride, int nk,
+                                                            T alpha, T beta) {
+  using C = BlkCfg<TM, BS>;
+  constexpr int V = C::V, G = C::G, NV = C::NV;
+  using VT = typename VecT<TM, V>::type;
+  __shared__ T xs[kWaves][64][kMaxRhs];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int g = lane / BS;
+  const int r = lane - g * BS;
+  const int wave = blockIdx.x * kWaves + wid;
+  const int idx = wave * G + g;
+  const bool active = (g < G) && (idx < nrows);
+  const int ridx = active ? idx : 0;
+  const int row_l = rows ? rows[ridx] : ridx;
+  const int row = active ? row_l : 0;
+  const int s0 = rp[row];
+  const int cnt = active ? rp[row + 1] - s0 : 0;
+  int mc = cnt;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mc = max(mc, __shfl_xor(mc, o));
+  T acc[kMaxRhs];
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) acc[q] = T(0);
+  for (int k = 0; k < mc; ++k) {
+    const bool has = k < cnt;
+    const int sl = has ? s0 + k : 0;
+    const int j = ci[sl];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) {
+      if (q < nk) {                                  // nk is uniform
+        const T xv = x[q * stride + static_cast<long long>(j) * BS + r];
+        xs[wid][lane][q] = has ? xv : T(0);
+      }
+    }
+    // make this wavefront's LDS writes visible to its other lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(sl) * (BS * BS)) + r;
+    VT a[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) a[q] = bp[q * BS];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const T av = static_cast<T>(elem(a[q], v));
+        const T* xc = &xs[wid][g * BS + q * V + v][0];
+#pragma unroll
+        for (int qq = 0; qq < kMaxRhs; ++qq)
+          if (qq < nk) acc[qq] += av * xc[qq];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const long long o = static_cast<long long>(row) * BS + r;
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nk) {
+      if (beta != T(0)) {
+        const T zo = z[q * stride + o];
+        if (active) out[q * stride + o] = alpha * acc[q] + beta * zo;
+      } else {
+        if (active) out[q * stride + o] = alpha * acc[q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // transposed BSR kernel: out_i = alpha sum_{(i,j) stored} (M_ji)^T x_j + beta z_i.
 // tpos[s] is the slot of block (j, i) for slot s = (i, j) (symmetric pattern).
 // Lane r accumulates row r of each (M_ji) scaled by x_j[r]; the BS partial
@@ -633,6 +720,17 @@ void launch_tr_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
   check_launch("bsr_tr");
 }
 
+template <typename TM, typename T, int BS>
+void launch_fwd_multi_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStream_t st) {
+  constexpr int G = 64 / BS;
+  const long long waves = (a.nrows + G - 1) / G;
+  const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
+  if (blocks == 0) return;
+  k_bsr_fwd_multi<TM, T, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
+                                                          stride, nk, a.alpha, a.beta);
+  check_launch("bsr_fwd_multi");
+}
+
 #define LDGMG_FOR_BS(X) X(4) X(8) X(9) X(12) X(16) X(25) X(27) X(32) X(36) X(48) X(64)
 
 }  // namespace
@@ -667,6 +765,29 @@ void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st) {
                                                                         nullptr, a.blk, a.x, a.z, a.out,
                                                                         a.alpha, a.beta);
   check_launch("bsr_generic");
+}
+
+template <typename TM, typename T>
+void bsr_forward_multi(const BsrArgs<TM, T>& a, long long stride, int nk, hipStream_t st) {
+  if (nk < 1 || nk > kMaxRhs) throw std::invalid_argument("bsr_forward_multi: bad right-hand-side count");
+  if (a.dinv) throw std::invalid_argument("bsr_forward_multi: no fused smoothing");
+  switch (a.bs) {
+#define CASE(B) \
+  case B:       \
+    launch_fwd_multi_bs<TM, T, B>(a, stride, nk, st); \
+    return;
+    LDGMG_FOR_BS(CASE)
+#undef CASE
+    default:
+      break;
+  }
+  for (int q = 0; q < nk; ++q) {   // other block sizes: one apply per right-hand side
+    BsrArgs<TM, T> b = a;
+    b.x = a.x + q * stride;
+    b.z = a.z ? a.z + q * stride : nullptr;
+    b.out = a.out + q * stride;
+    bsr_forward<TM, T>(b, st);
+  }
 }
 
 template <typename TM, typename T>
@@ -791,6 +912,8 @@ void maxpy(long long n, int k, const double* Q, const double* h, double sign, do
 template void bsr_forward<float, double>(const BsrArgs<float, double>&, hipStream_t);
 template void bsr_forward<double, double>(const BsrArgs<double, double>&, hipStream_t);
 template void bsr_transposed<float, double>(const BsrArgs<float, double>&, hipStream_t);
+template void bsr_forward_multi<float, double>(const BsrArgs<float, double>&, long long, int, hipStream_t);
+template void bsr_forward_multi<double, double>(const BsrArgs<double, double>&, long long, int, hipStream_t);
 template void bsr_transposed<double, double>(const BsrArgs<double, double>&, hipStream_t);
 template void expand_blocks<float>(long long, int, const int*, const double*, float*, bool, hipStream_t);
 template void expand_blocks<double>(long long, int, const int*, const double*, double*, bool, hipStream_t);

@@ -11,6 +11,7 @@ namespace ldgmg {
 constexpr int kRedBlocks = 1024;   // partial sums per dot product
 constexpr int kRedThreads = 256;
 constexpr int kMdotBlocks = 256;   // partial sums per vector of a multi-dot
+constexpr int kMaxRhs = 8;         // right-hand sides per multi-vector BSR launch
 
 // block sizes with a specialised (wave-mapped) kernel; others use the generic one
 bool fast_bs(int bs);
@@ -42,6 +43,9 @@ struct BsrArgs {
 
 // out = alpha M x + beta z, or (dinv != null) out = x + omega Dinv (z - M x)
 template <typename TM, typename T> void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st);
+// the same for nk <= kMaxRhs vectors at x + q*stride, z + q*stride, out + q*stride
+template <typename TM, typename T>
+void bsr_forward_multi(const BsrArgs<TM, T>& a, long long stride, int nk, hipStream_t st);
 // out = alpha M^T x + beta z  (rows must be null; tpos required)
 template <typename TM, typename T> void bsr_transposed(const BsrArgs<TM, T>& a, hipStream_t st);
 // pooled FP64 row-major blocks -> device layout of T (optionally transposed)

@@ -57,7 +57,7 @@ _lib = None
 
 SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
-           "ldgmg_solve", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
+           "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
            "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_destroy",
            "ldgmg_last_error"]
 
@@ -84,6 +84,9 @@ def lib():
     L.ldgmg_vcycle.argtypes = [H, vp, vp, vp]
     L.ldgmg_solve.argtypes = [H, vp, vp, C.c_int, C.c_double, C.c_int, C.POINTER(Info), vp]
     L.ldgmg_level_op.argtypes = [H, C.c_int, C.c_int, vp, vp, vp, vp]
+    L.ldgmg_solve_batch.argtypes = [H, C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_double, C.c_int,
+                                    C.POINTER(Info), vp]
+    L.ldgmg_vcycle_batch.argtypes = [H, C.POINTER(vp), C.POINTER(vp), C.c_int, vp]
     L.ldgmg_export.argtypes = [H, C.c_int, C.c_int, ip, ip, dp, ip, ip]
     L.ldgmg_export_colours.argtypes = [H, C.c_int, ip]
     L.ldgmg_setup_stats.argtypes = [H, C.c_int, ip, dp]
@@ -214,6 +217,37 @@ def ldgmg_solve(h: int, b, x, krylov: str = "cg", rtol: float = 1e-10, maxit: in
             "rel_res_true": info.rel_res_true, "rel_res_krylov": info.rel_res_krylov,
             "eta": info.eta, "history": hist[: info.history_len].copy(),
             "vcycles": info.vcycles, "status": rc}
+
+
+MAX_BATCH = 8
+
+
+def _ptr_array(ts):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t)
+    return arr
+
+
+def ldgmg_solve_batch(h: int, bs, xs, rtol: float = 1e-10, maxit: int = 200, stream=None,
+                      history_cap: int = 256) -> list:
+    """Batched CG for k = len(bs) <= 8 right-hand sides of one hierarchy."""
+    k = len(bs)
+    hists = [np.zeros(history_cap) for _ in range(k)]
+    infos = (Info * k)()
+    for i in range(k):
+        infos[i].history = hists[i].ctypes.data_as(C.POINTER(C.c_double))
+        infos[i].history_cap = history_cap
+    rc = _check(lib().ldgmg_solve_batch(h, _ptr_array(bs), _ptr_array(xs), k, rtol, maxit, infos,
+                                        _stream(stream)), allow=(ENOCONV,))
+    return [{"iters": infos[i].iters, "converged": bool(infos[i].converged),
+             "rel_res_true": infos[i].rel_res_true, "rel_res_krylov": infos[i].rel_res_krylov,
+             "eta": infos[i].eta, "history": hists[i][: infos[i].history_len].copy(),
+             "vcycles": infos[i].vcycles, "status": rc} for i in range(k)]
+
+
+def ldgmg_vcycle_batch(h: int, bs, xs, stream=None):
+    _check(lib().ldgmg_vcycle_batch(h, _ptr_array(bs), _ptr_array(xs), len(bs), _stream(stream)))
 
 
 def ldgmg_level_op(h: int, level: int, op: str, in1, in2, out, stream=None):
