@@ -160,6 +160,64 @@ def cpu_baseline(n_cpu):
             "seconds": dt, "solves_per_s": 1.0 / dt, "host_cpus": os.cpu_count()}
 
 
+# request catalogues of the serving workload: "full" is the mixed stream of
+# 2D/3D Poisson and box-interface problems (2D 32^2..256^2, 3D 16^3..48^3,
+# p = 1..3, contrast 1..1e4); "lite" keeps its 2D part and the 3D grids up to
+# 32^3 with p <= 2
+CATALOGUES = {
+    "full": dict(grids2d=(32, 64, 128, 256), grids3d=(16, 24, 32, 48), degrees=(1, 2, 3),
+                 contrasts=(1.0, 10.0, 1e2, 1e3, 1e4)),
+    "lite": dict(grids2d=(32, 64, 128, 256), grids3d=(16, 24, 32), degrees=(1, 2),
+                 contrasts=(1.0, 10.0, 1e2, 1e3, 1e4)),
+}
+
+
+def run_serving(args, torch):
+    """Replay the seeded request stream through the serving engine; one JSON
+    line with solves/s and p50/p99 latency (arrival to completion)."""
+    from ldg_inputs import serving_requests
+    from paper_2412_12506_amd.serving import ServingEngine, problem_key, summarize
+    cat = CATALOGUES[args.serving_catalogue]
+    reqs = serving_requests(count=args.serving_requests, rate=args.serving_rate, **cat)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(args.serving_budget_gib * (1 << 30)) if args.serving_budget_gib else int(free * 0.9)
+    eng = ServingEngine(budget, workers=args.serving_workers)
+    keys = sorted({problem_key(r) for r in reqs})
+    log(f"[serving] {len(reqs)} requests, {len(keys)} hierarchies, budget {budget / 2**30:.1f} GiB")
+    setup_s = eng.prebuild(keys, threads=4)
+    log(f"[serving] host tier built in {setup_s:.1f} s")
+    out = {}
+    for mode, scale in (("offered", 1.0), ("saturated", 0.0)):
+        for e in eng.entries.values():          # every replay starts with an empty device tier
+            if e.resident:
+                e.solver.unload()
+                e.resident, e.bytes = False, 0
+        eng.used, eng.peak_used = 0, 0
+        eng.results, eng.evictions, eng.admissions = [], [], []
+        res = eng.run(reqs, time_scale=scale)
+        st = summarize(res)
+        st["uploads"] = len(eng.admissions)
+        st["evictions"] = len(eng.evictions)
+        st["peak_hbm_gib"] = eng.peak_used / 2 ** 30
+        st["dof_per_s"] = st["dofs_solved"] / st["wall_s"] if st["wall_s"] else None
+        out[mode] = st
+        log(f"[serving] {mode}: {st}")
+    eng.close()
+    sat = out["saturated"]
+    line = {
+        "metric": METRIC, "value": sat["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": sat["wall_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "block_storage": "f32", "data": "synthetic",
+        "config": {"workload": f"serving_{len(reqs)}_mixed_{args.serving_catalogue}",
+                   "requests": len(reqs), "hierarchies": len(keys), "rate_per_s": args.serving_rate,
+                   "rtol": 1e-10, "smoother": "SAI_1 OI", "outer": "FP64 CG (batched, k<=8)",
+                   "workers": args.serving_workers, "hbm_budget_gib": budget / 2 ** 30},
+        "p50_ms": out["offered"]["p50_ms"], "p99_ms": out["offered"]["p99_ms"],
+        "offered": out["offered"], "saturated": sat, "host_setup_s": setup_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +230,13 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=8, help="grid of the CPU oracle sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving workload instead (a separate JSON line)")
+    ap.add_argument("--serving-catalogue", choices=sorted(CATALOGUES), default="full")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-rate", type=float, default=100.0, help="mean arrivals per second")
+    ap.add_argument("--serving-workers", type=int, default=4)
+    ap.add_argument("--serving-budget-gib", type=float, default=0.0, help="0: 90%% of free HBM")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
@@ -195,6 +260,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serving:
+        run_serving(args, torch)
+        return
     ndofs = args.n ** 3 * (args.p + 1) ** 3
     nrhs = args.warmup + args.steps
     rhs = [torch.from_numpy(rhs_normal(ndofs, BASE_SEED + i)).to(dev) for i in range(nrhs)]

@@ -123,6 +123,18 @@ int ldgmg_upload(ldgmg_handle h, void* stream);
 /* ldgmg_setup_host followed by ldgmg_upload. */
 int ldgmg_setup(const ldgmg_problem* p, void* stream, ldgmg_handle* out);
 
+/* Free the handle's device memory (levels, Krylov and batch workspaces); the
+ * caller first synchronises the streams that used the handle, as before
+ * ldgmg_destroy.  The host hierarchy stays, so a later
+ * ldgmg_upload restores the handle without repeating the setup.  Until then
+ * every call that needs device data returns LDGMG_ESTATE.  A handle that holds
+ * no device data is left as it is. */
+int ldgmg_unload(ldgmg_handle h);
+
+/* Device bytes the handle holds now (0 when it holds no device data): what
+ * ldgmg_upload allocated plus the batch workspace once a batched call made it. */
+int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes);
+
 /* Sizes: fine-level unknowns, unknowns per element, number of levels. */
 int ldgmg_sizes(ldgmg_handle h, long long* ndofs, int* bs, int* nlevels);
 

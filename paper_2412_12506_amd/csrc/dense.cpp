@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <immintrin.h>
 #include <vector>
 
 namespace ldgmg {
@@ -116,6 +117,147 @@ void apply_panel_t(int m, int r0, int nb, const double* C, int ld, int j0,
   }
 }
 
+// ---- bs x bs tiles, row-major ----------------------------------------------
+
+// C += s * A B  (all bs x bs row-major).  A 4 x 8 block of C is held in eight
+// AVX2 registers while the k loop streams one row of B per step.
+void tile_nn(int bs, const double* A, const double* B, double* C, double s) {
+  const __m256d vs = _mm256_set1_pd(s);
+  int i0 = 0;
+  for (; i0 + 4 <= bs; i0 += 4) {
+    const double* a0 = A + static_cast<size_t>(i0) * bs;
+    const double* a1 = a0 + bs;
+    const double* a2 = a1 + bs;
+    const double* a3 = a2 + bs;
+    int j0 = 0;
+    for (; j0 + 8 <= bs; j0 += 8) {
+      __m256d c00 = _mm256_setzero_pd(), c01 = _mm256_setzero_pd();
+      __m256d c10 = _mm256_setzero_pd(), c11 = _mm256_setzero_pd();
+      __m256d c20 = _mm256_setzero_pd(), c21 = _mm256_setzero_pd();
+      __m256d c30 = _mm256_setzero_pd(), c31 = _mm256_setzero_pd();
+      const double* b = B + j0;
+      for (int k = 0; k < bs; ++k, b += bs) {
+        const __m256d b0 = _mm256_loadu_pd(b), b1 = _mm256_loadu_pd(b + 4);
+        __m256d x = _mm256_broadcast_sd(a0 + k);
+        c00 = _mm256_fmadd_pd(x, b0, c00);
+        c01 = _mm256_fmadd_pd(x, b1, c01);
+        x = _mm256_broadcast_sd(a1 + k);
+        c10 = _mm256_fmadd_pd(x, b0, c10);
+        c11 = _mm256_fmadd_pd(x, b1, c11);
+        x = _mm256_broadcast_sd(a2 + k);
+        c20 = _mm256_fmadd_pd(x, b0, c20);
+        c21 = _mm256_fmadd_pd(x, b1, c21);
+        x = _mm256_broadcast_sd(a3 + k);
+        c30 = _mm256_fmadd_pd(x, b0, c30);
+        c31 = _mm256_fmadd_pd(x, b1, c31);
+      }
+      double* c = C + static_cast<size_t>(i0) * bs + j0;
+      _mm256_storeu_pd(c, _mm256_fmadd_pd(vs, c00, _mm256_loadu_pd(c)));
+      _mm256_storeu_pd(c + 4, _mm256_fmadd_pd(vs, c01, _mm256_loadu_pd(c + 4)));
+      c += bs;
+      _mm256_storeu_pd(c, _mm256_fmadd_pd(vs, c10, _mm256_loadu_pd(c)));
+      _mm256_storeu_pd(c + 4, _mm256_fmadd_pd(vs, c11, _mm256_loadu_pd(c + 4)));
+      c += bs;
+      _mm256_storeu_pd(c, _mm256_fmadd_pd(vs, c20, _mm256_loadu_pd(c)));
+      _mm256_storeu_pd(c + 4, _mm256_fmadd_pd(vs, c21, _mm256_loadu_pd(c + 4)));
+      c += bs;
+      _mm256_storeu_pd(c, _mm256_fmadd_pd(vs, c30, _mm256_loadu_pd(c)));
+      _mm256_storeu_pd(c + 4, _mm256_fmadd_pd(vs, c31, _mm256_loadu_pd(c + 4)));
+    }
+    for (; j0 < bs; ++j0) {
+      double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+      for (int k = 0; k < bs; ++k) {
+        const double b = B[static_cast<size_t>(k) * bs + j0];
+        acc0 += a0[k] * b;
+        acc1 += a1[k] * b;
+        acc2 += a2[k] * b;
+        acc3 += a3[k] * b;
+      }
+      C[static_cast<size_t>(i0) * bs + j0] += s * acc0;
+      C[static_cast<size_t>(i0 + 1) * bs + j0] += s * acc1;
+      C[static_cast<size_t>(i0 + 2) * bs + j0] += s * acc2;
+      C[static_cast<size_t>(i0 + 3) * bs + j0] += s * acc3;
+    }
+  }
+  for (; i0 < bs; ++i0) {
+    const double* a = A + static_cast<size_t>(i0) * bs;
+    double* c = C + static_cast<size_t>(i0) * bs;
+    for (int k = 0; k < bs; ++k) {
+      const double x = s * a[k];
+      const double* b = B + static_cast<size_t>(k) * bs;
+      for (int j = 0; j < bs; ++j) c[j] += x * b[j];
+    }
+  }
+}
+
+void tile_transpose(int bs, const double* A, double* At) {
+  for (int i = 0; i < bs; ++i)
+    for (int j = 0; j < bs; ++j) At[static_cast<size_t>(j) * bs + i] = A[static_cast<size_t>(i) * bs + j];
+}
+
+// lower Cholesky factor of a bs x bs tile in place (upper part left as is);
+// false when a pivot is <= floor
+bool tile_potrf(int bs, double* A, double floor) {
+  for (int j = 0; j < bs; ++j) {
+    double* aj = A + static_cast<size_t>(j) * bs;
+    double d = aj[j];
+    for (int t = 0; t < j; ++t) d -= aj[t] * aj[t];
+    if (!(d > floor)) return false;
+    const double ljj = std::sqrt(d);
+    aj[j] = ljj;
+    const double inv = 1.0 / ljj;
+    for (int i = j + 1; i < bs; ++i) {
+      double* ai = A + static_cast<size_t>(i) * bs;
+      double v = ai[j];
+      for (int t = 0; t < j; ++t) v -= ai[t] * aj[t];
+      ai[j] = v * inv;
+    }
+  }
+  return true;
+}
+
+// X <- X L^-T for the lower factor L (row by row: x L^T = g)
+void tile_trsm_right_lt(int bs, const double* L, double* X) {
+  for (int r = 0; r < bs; ++r) {
+    double* x = X + static_cast<size_t>(r) * bs;
+    for (int j = 0; j < bs; ++j) {
+      const double* lj = L + static_cast<size_t>(j) * bs;
+      double v = x[j];
+      for (int t = 0; t < j; ++t) v -= x[t] * lj[t];
+      x[j] = v / lj[j];
+    }
+  }
+}
+
+// Y <- L^-1 Y (forward substitution over the rows of Y)
+void tile_trsm_left_l(int bs, const double* L, double* Y) {
+  for (int r = 0; r < bs; ++r) {
+    const double* lr = L + static_cast<size_t>(r) * bs;
+    double* y = Y + static_cast<size_t>(r) * bs;
+    for (int t = 0; t < r; ++t) {
+      const double l = lr[t];
+      const double* yt = Y + static_cast<size_t>(t) * bs;
+      for (int j = 0; j < bs; ++j) y[j] -= l * yt[j];
+    }
+    const double inv = 1.0 / lr[r];
+    for (int j = 0; j < bs; ++j) y[j] *= inv;
+  }
+}
+
+// Y <- L^-T Y (backward substitution over the rows of Y)
+void tile_trsm_left_lt(int bs, const double* L, double* Y) {
+  for (int r = bs - 1; r >= 0; --r) {
+    double* y = Y + static_cast<size_t>(r) * bs;
+    for (int t = r + 1; t < bs; ++t) {
+      const double l = L[static_cast<size_t>(t) * bs + r];
+      const double* yt = Y + static_cast<size_t>(t) * bs;
+      for (int j = 0; j < bs; ++j) y[j] -= l * yt[j];
+    }
+    const double inv = 1.0 / L[static_cast<size_t>(r) * bs + r];
+    for (int j = 0; j < bs; ++j) y[j] *= inv;
+  }
+}
+
 }  // namespace
 
 bool ls_householder(int m, int n, int k, double* C, double* R, double* X) {
@@ -185,12 +327,97 @@ bool ls_householder(int m, int n, int k, double* C, double* R, double* X) {
   return true;
 }
 
+bool ls_block_normal(int bs, int mb, int nb,
+                     const std::vector<std::vector<std::pair<int, const double*>>>& rows, int pos,
+                     double* Xout) {
+  const size_t T = static_cast<size_t>(bs) * bs;
+  // tiles of G = C^T C: lower tiles (i >= j) hold G and then its Cholesky
+  // factor; upper tiles (k < j) receive the transposed factor tiles
+  std::vector<double> G(static_cast<size_t>(nb) * nb * T, 0.0);
+  auto g = [&](int i, int j) { return G.data() + (static_cast<size_t>(i) * nb + j) * T; };
+  // transposed copies of the nonzero blocks of C, in the order of rows[a]
+  std::vector<size_t> first(mb + 1, 0);
+  for (int a = 0; a < mb; ++a) first[a + 1] = first[a] + rows[a].size();
+  std::vector<double> Ct(first[mb] * T);
+  for (int a = 0; a < mb; ++a)
+    for (size_t q = 0; q < rows[a].size(); ++q) tile_transpose(bs, rows[a][q].second, &Ct[(first[a] + q) * T]);
+  // Gram tiles: G_{b1 b2} += C_{a b1}^T C_{a b2} for b1 >= b2
+  for (int a = 0; a < mb; ++a)
+    for (size_t q1 = 0; q1 < rows[a].size(); ++q1)
+      for (size_t q2 = 0; q2 < rows[a].size(); ++q2) {
+        const int b1 = rows[a][q1].first, b2 = rows[a][q2].first;
+        if (b1 >= b2) tile_nn(bs, &Ct[(first[a] + q1) * T], rows[a][q2].second, g(b1, b2), 1.0);
+      }
+  double gmax = 0.0;
+  for (int b = 0; b < nb; ++b)
+    for (int r = 0; r < bs; ++r) gmax = std::max(gmax, g(b, b)[static_cast<size_t>(r) * bs + r]);
+  const double floor = 1e-24 * gmax;
+  // right-looking tiled Cholesky, G = L L^T
+  std::vector<double> tmp(T);
+  std::vector<double> colT(static_cast<size_t>(nb) * T);
+  for (int k = 0; k < nb; ++k) {
+    if (!tile_potrf(bs, g(k, k), floor)) return false;
+    for (int r = 0; r < bs; ++r)      // clear the strictly upper part of the diagonal factor tile
+      for (int c = r + 1; c < bs; ++c) g(k, k)[static_cast<size_t>(r) * bs + c] = 0.0;
+    for (int i = k + 1; i < nb; ++i) {
+      tile_trsm_right_lt(bs, g(k, k), g(i, k));
+      tile_transpose(bs, g(i, k), &colT[static_cast<size_t>(i) * T]);
+    }
+    for (int i = k + 1; i < nb; ++i)
+      for (int j = k + 1; j <= i; ++j) tile_nn(bs, g(i, k), &colT[static_cast<size_t>(j) * T], g(i, j), -1.0);
+    for (int j = k + 1; j < nb; ++j)
+      std::memcpy(g(k, j), &colT[static_cast<size_t>(j) * T], T * sizeof(double));
+  }
+  // Y <- (L L^T)^-1 Y, tile rows of Y indexed by block column
+  auto solve = [&](std::vector<double>& Y) {
+    for (int k = 0; k < nb; ++k) {
+      double* yk = &Y[static_cast<size_t>(k) * T];
+      for (int j = 0; j < k; ++j) tile_nn(bs, g(k, j), &Y[static_cast<size_t>(j) * T], yk, -1.0);
+      tile_trsm_left_l(bs, g(k, k), yk);
+    }
+    for (int k = nb - 1; k >= 0; --k) {
+      double* yk = &Y[static_cast<size_t>(k) * T];
+      for (int j = k + 1; j < nb; ++j) tile_nn(bs, g(k, j), &Y[static_cast<size_t>(j) * T], yk, -1.0);
+      tile_trsm_left_lt(bs, g(k, k), yk);
+    }
+  };
+  // X0 from C^T E: the transposed blocks of block row pos
+  std::vector<double> X(static_cast<size_t>(nb) * T, 0.0);
+  for (size_t q = 0; q < rows[pos].size(); ++q)
+    std::memcpy(&X[static_cast<size_t>(rows[pos][q].first) * T], &Ct[(first[pos] + q) * T], T * sizeof(double));
+  solve(X);
+  // one refinement step: D = (C^T C)^-1 C^T (E - C X0)
+  std::vector<double> R(static_cast<size_t>(mb) * T, 0.0), D(static_cast<size_t>(nb) * T, 0.0);
+  for (int r = 0; r < bs; ++r) R[(static_cast<size_t>(pos) * bs + r) * bs + r] = 1.0;
+  for (int a = 0; a < mb; ++a)
+    for (const auto& bp : rows[a])
+      tile_nn(bs, bp.second, &X[static_cast<size_t>(bp.first) * T], &R[static_cast<size_t>(a) * T], -1.0);
+  for (int a = 0; a < mb; ++a)
+    for (size_t q = 0; q < rows[a].size(); ++q)
+      tile_nn(bs, &Ct[(first[a] + q) * T], &R[static_cast<size_t>(a) * T],
+              &D[static_cast<size_t>(rows[a][q].first) * T], 1.0);
+  solve(D);
+  double xmax = 0.0, dmax = 0.0;
+  for (size_t t = 0; t < X.size(); ++t) {
+    X[t] += D[t];
+    xmax = std::max(xmax, std::fabs(X[t]));
+    dmax = std::max(dmax, std::fabs(D[t]));
+  }
+  if (!(dmax <= 1e-8 * xmax)) return false;
+  const size_t n = static_cast<size_t>(nb) * bs;
+  for (int b = 0; b < nb; ++b)
+    for (int r = 0; r < bs; ++r)
+      for (int c = 0; c < bs; ++c)
+        Xout[static_cast<size_t>(c) * n + static_cast<size_t>(b) * bs + r] = X[static_cast<size_t>(b) * T + static_cast<size_t>(r) * bs + c];
+  return true;
+}
+
 void sym_eig(int n, const double* Ain, double* w, double* Vout) {
   // a: working copy (row-major, symmetric); q: accumulated transform, column-major
   std::vector<double> a(Ain, Ain + static_cast<size_t>(n) * n);
   std::vector<double> q(static_cast<size_t>(n) * n, 0.0);
   for (int i = 0; i < n; ++i) q[static_cast<size_t>(i) * n + i] = 1.0;
-  std::vector<double> v(n), p(n), wv(n), d(n), e(n, 0.0);
+  std::vector<double> v(n), p(n), wv(n), d(n), e(n, 0.0), qv(n);
   // Householder tridiagonalisation
   for (int k = 0; k + 2 < n; ++k) {
     const int len = n - k - 1;
@@ -221,12 +448,18 @@ void sym_eig(int n, const double* Ain, double* w, double* Vout) {
       a[static_cast<size_t>(k + 1 + i) * n + k] = 0.0;
       a[static_cast<size_t>(k) * n + k + 1 + i] = 0.0;
     }
-    // Q <- Q H on columns k+1..n-1 (column-major q): Q' -= tau (Q' v) v^T
-    for (int r = 0; r < n; ++r) {
-      double s = 0.0;
-      for (int j = 0; j < len; ++j) s += q[static_cast<size_t>(k + 1 + j) * n + r] * v[j];
-      s *= tau;
-      for (int j = 0; j < len; ++j) q[static_cast<size_t>(k + 1 + j) * n + r] -= s * v[j];
+    // Q <- Q H on columns k+1..n-1 (column-major q): Q' -= tau (Q' v) v^T, both
+    // passes walking whole columns so that every access is contiguous
+    std::fill(qv.begin(), qv.end(), 0.0);
+    for (int j = 0; j < len; ++j) {
+      const double* col = &q[static_cast<size_t>(k + 1 + j) * n];
+      const double vj = v[j];
+      for (int r = 0; r < n; ++r) qv[r] += col[r] * vj;
+    }
+    for (int j = 0; j < len; ++j) {
+      double* col = &q[static_cast<size_t>(k + 1 + j) * n];
+      const double tv = tau * v[j];
+      for (int r = 0; r < n; ++r) col[r] -= qv[r] * tv;
     }
   }
   for (int i = 0; i < n; ++i) d[i] = a[static_cast<size_t>(i) * n + i];

@@ -1119,6 +1119,22 @@ int ldgmg_upload(ldgmg_handle h, void* stream) {
   });
 }
 
+int ldgmg_unload(ldgmg_handle h) {
+  return guarded([&] {
+    if (!h || !h->host) throw std::invalid_argument("null handle");
+    h->dev.reset();
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes) {
+  return guarded([&] {
+    if (!h || !h->host || !bytes) throw std::invalid_argument("null argument");
+    *bytes = h->dev ? h->dev->bytes : 0;
+    return LDGMG_OK;
+  });
+}
+
 int ldgmg_setup(const ldgmg_problem* p, void* stream, ldgmg_handle* out) {
   ldgmg_handle h = nullptr;
   int rc = ldgmg_setup_host(p, &h);

@@ -31,7 +31,8 @@ namespace {
 
 using Vec = std::vector<double>;
 
-int g_threads = 1;
+// Per calling thread, so that setups of different problems can run concurrently.
+thread_local int g_threads = 1;
 
 void parallel_for(int n, const std::function<void(int)>& fn) {
   const int nt = std::max(1, std::min(g_threads, n));
@@ -888,12 +889,44 @@ void build_sai(HostLevel& L, int ell, int system, double zeta) {
   // solve the representative problems: X = argmin || A~[I,J] X - E[I,i] ||
   std::vector<Vec> sol(rep.size());
   std::atomic<bool> singular{false};
+  std::atomic<int> qr_fallback{0};
   parallel_for(static_cast<int>(rep.size()), [&](int u) {
     const int i = rep[u];
     const auto& I = Isets[i];
     const auto& Jc = J[i];
     const int m = static_cast<int>(I.size()) * bs, n = static_cast<int>(Jc.size()) * bs;
-    Vec C(static_cast<size_t>(m) * n, 0.0), R(static_cast<size_t>(m) * bs, 0.0), X(static_cast<size_t>(n) * bs);
+    const int pos = static_cast<int>(std::lower_bound(I.begin(), I.end(), i) - I.begin());
+    Vec X(static_cast<size_t>(n) * bs);
+    {
+      // block-sparse normal equations (only the nonzero blocks of A~[I,J])
+      const size_t T = static_cast<size_t>(bs) * bs;
+      std::vector<std::vector<std::pair<int, const double*>>> brow(I.size());
+      size_t nnz = 0;
+      for (size_t a = 0; a < I.size(); ++a)
+        for (size_t b = 0; b < Jc.size(); ++b) nnz += A.slot(I[a], Jc[b]) >= 0;
+      Vec blocks(nnz * T);
+      size_t q = 0;
+      for (size_t a = 0; a < I.size(); ++a) {
+        const Vec& al = alpha[did[I[a]]];
+        for (size_t b = 0; b < Jc.size(); ++b) {
+          const int s = A.slot(I[a], Jc[b]);
+          if (s < 0) continue;
+          const Vec& be = alpha[did[Jc[b]]];
+          const double* blk = A.block(s);
+          double* out = &blocks[q * T];
+          for (int r = 0; r < bs; ++r)
+            for (int c = 0; c < bs; ++c) out[static_cast<size_t>(r) * bs + c] = al[r] * blk[static_cast<size_t>(r) * bs + c] * be[c];
+          brow[a].push_back({static_cast<int>(b), out});
+          ++q;
+        }
+      }
+      if (ls_block_normal(bs, static_cast<int>(I.size()), static_cast<int>(Jc.size()), brow, pos, X.data())) {
+        sol[u] = std::move(X);
+        return;
+      }
+      ++qr_fallback;
+    }
+    Vec C(static_cast<size_t>(m) * n, 0.0), R(static_cast<size_t>(m) * bs, 0.0);
     for (size_t a = 0; a < I.size(); ++a) {
       const Vec& al = alpha[did[I[a]]];
       for (size_t b = 0; b < Jc.size(); ++b) {
@@ -906,12 +939,12 @@ void build_sai(HostLevel& L, int ell, int system, double zeta) {
             C[static_cast<size_t>(b * bs + c) * m + a * bs + r] = al[r] * blk[static_cast<size_t>(r) * bs + c] * be[c];
       }
     }
-    const int pos = static_cast<int>(std::lower_bound(I.begin(), I.end(), i) - I.begin());
     for (int c = 0; c < bs; ++c) R[static_cast<size_t>(c) * m + pos * bs + c] = 1.0;
     if (!ls_householder(m, n, bs, C.data(), R.data(), X.data())) singular = true;
     sol[u] = std::move(X);
   });
   if (singular) throw std::runtime_error("rank-deficient SAI least-squares problem");
+  L.sai_qr = qr_fallback.load();
   // B(j, i) = diag(alpha_j) X_b diag(alpha_i), stored row-wise with the pattern of A^ell
   std::vector<std::vector<std::pair<int, std::string>>> rows(ne);   // row j: (col i, key)
   for (int i = 0; i < ne; ++i)

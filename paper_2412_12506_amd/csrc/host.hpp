@@ -81,6 +81,7 @@ struct HostLevel {
   std::vector<std::vector<int>> colour_rows;
   std::vector<double> pinv;    // bottom pseudo-inverse, dense (ne*bs)^2
   int sai_unique = 0;
+  int sai_qr = 0;               // of those, solved by Householder QR (normal equations declined)
   double setup_seconds = 0;
 };
 

@@ -58,7 +58,7 @@ _lib = None
 SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
-           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_destroy",
+           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_device_bytes", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -92,6 +92,8 @@ def lib():
     L.ldgmg_setup_stats.argtypes = [H, C.c_int, ip, dp]
     L.ldgmg_profile.argtypes = [H, C.c_int]
     L.ldgmg_profile_read.argtypes = [H, C.c_int, ip, dp]
+    L.ldgmg_unload.argtypes = [H]
+    L.ldgmg_device_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.ldgmg_destroy.argtypes = [H]
     L.ldgmg_last_error.argtypes = []
     L.ldgmg_last_error.restype = C.c_char_p
@@ -306,6 +308,16 @@ def ldgmg_profile_read(h: int, kind: str):
     return cnt.value, ms.value
 
 
+def ldgmg_unload(h: int):
+    _check(lib().ldgmg_unload(h))
+
+
+def ldgmg_device_bytes(h: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().ldgmg_device_bytes(h, C.byref(out)))
+    return out.value
+
+
 def ldgmg_destroy(h: int):
     if h:
         lib().ldgmg_destroy(h)
@@ -334,6 +346,13 @@ class Solver:
 
     def upload(self, stream=None):
         ldgmg_upload(self.handle, stream)
+
+    def unload(self):
+        ldgmg_unload(self.handle)
+
+    @property
+    def device_bytes(self) -> int:
+        return ldgmg_device_bytes(self.handle)
 
     def vcycle(self, b, x, stream=None):
         ldgmg_vcycle(self.handle, b, x, stream)
