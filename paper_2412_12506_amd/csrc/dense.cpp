@@ -2,6 +2,9 @@
 #include "dense.hpp"
 
 #include <algorithm>
+#include <thread>
+#include <functional>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <immintrin.h>
@@ -412,59 +415,127 @@ bool ls_block_normal(int bs, int mb, int nb,
   return true;
 }
 
-void sym_eig(int n, const double* Ain, double* w, double* Vout) {
-  // a: working copy (row-major, symmetric); q: accumulated transform, column-major
-  std::vector<double> a(Ain, Ain + static_cast<size_t>(n) * n);
-  std::vector<double> q(static_cast<size_t>(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) q[static_cast<size_t>(i) * n + i] = 1.0;
-  std::vector<double> v(n), p(n), wv(n), d(n), e(n, 0.0), qv(n);
-  // Householder tridiagonalisation
-  for (int k = 0; k + 2 < n; ++k) {
-    const int len = n - k - 1;
-    for (int i = 0; i < len; ++i) v[i] = a[static_cast<size_t>(k + 1 + i) * n + k];
-    const double tau = make_reflector(len, v.data());
-    if (tau == 0.0) continue;
-    const double beta = v[0];
-    v[0] = 1.0;
-    // p = tau * A' v   (A' = a[k+1:, k+1:])
-    for (int i = 0; i < len; ++i) {
-      const double* row = &a[static_cast<size_t>(k + 1 + i) * n + k + 1];
-      double s = 0.0;
-      for (int j = 0; j < len; ++j) s += row[j] * v[j];
-      p[i] = tau * s;
+namespace {
+
+// Sense-counting barrier for a fixed team of threads (spins, then yields).
+class SpinBarrier {
+ public:
+  explicit SpinBarrier(int n) : n_(n) {}
+  void wait() {
+    if (n_ == 1) return;
+    const int gen = gen_.load(std::memory_order_acquire);
+    if (count_.fetch_add(1, std::memory_order_acq_rel) + 1 == n_) {
+      count_.store(0, std::memory_order_relaxed);
+      gen_.fetch_add(1, std::memory_order_release);
+      return;
     }
-    double pv = 0.0;
-    for (int i = 0; i < len; ++i) pv += p[i] * v[i];
-    const double K = 0.5 * tau * pv;
-    for (int i = 0; i < len; ++i) wv[i] = p[i] - K * v[i];
-    for (int i = 0; i < len; ++i) {
-      double* row = &a[static_cast<size_t>(k + 1 + i) * n + k + 1];
-      const double vi = v[i], wi = wv[i];
-      for (int j = 0; j < len; ++j) row[j] -= vi * wv[j] + wi * v[j];
-    }
-    a[static_cast<size_t>(k + 1) * n + k] = beta;
-    a[static_cast<size_t>(k) * n + k + 1] = beta;
-    for (int i = 1; i < len; ++i) {
-      a[static_cast<size_t>(k + 1 + i) * n + k] = 0.0;
-      a[static_cast<size_t>(k) * n + k + 1 + i] = 0.0;
-    }
-    // Q <- Q H on columns k+1..n-1 (column-major q): Q' -= tau (Q' v) v^T, both
-    // passes walking whole columns so that every access is contiguous
-    std::fill(qv.begin(), qv.end(), 0.0);
-    for (int j = 0; j < len; ++j) {
-      const double* col = &q[static_cast<size_t>(k + 1 + j) * n];
-      const double vj = v[j];
-      for (int r = 0; r < n; ++r) qv[r] += col[r] * vj;
-    }
-    for (int j = 0; j < len; ++j) {
-      double* col = &q[static_cast<size_t>(k + 1 + j) * n];
-      const double tv = tau * v[j];
-      for (int r = 0; r < n; ++r) col[r] -= qv[r] * tv;
-    }
+    for (int spins = 0; gen_.load(std::memory_order_acquire) == gen; ++spins)
+      if (spins > 2000) std::this_thread::yield();
   }
+
+ private:
+  const int n_;
+  std::atomic<int> count_{0}, gen_{0};
+};
+
+// fn(tid) on nt threads, the caller being thread 0; fn must not throw.
+void run_team(int nt, const std::function<void(int)>& fn) {
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(fn, t);
+  fn(0);
+  for (auto& t : th) t.join();
+}
+
+struct Rotation {
+  int i;
+  double c, s;
+};
+
+}  // namespace
+
+void sym_eig(int n, const double* Ain, double* w, double* Vout, int nthreads) {
+  const int nt = n >= 256 ? std::max(1, std::min(nthreads, n / 64)) : 1;
+  // a: working copy, row-major and symmetric; after the reduction its
+  // diagonal and subdiagonal hold the tridiagonal matrix and column k below
+  // the subdiagonal holds the tail of reflector k (unit first entry implied)
+  std::vector<double> a(Ain, Ain + static_cast<size_t>(n) * n);
+  std::vector<double> tau(n, 0.0), v(n), p(n), wv(n);
+  double tau_k = 0.0;
+  SpinBarrier bar(nt);
+  // 1. Householder tridiagonalisation A = Q T Q^T, trailing rows split over the team
+  run_team(nt, [&](int tid) {
+    for (int k = 0; k + 2 < n; ++k) {
+      const int len = n - k - 1;
+      if (tid == 0) {
+        for (int i = 0; i < len; ++i) v[i] = a[static_cast<size_t>(k + 1 + i) * n + k];
+        tau_k = make_reflector(len, v.data());
+        tau[k] = tau_k;
+        if (tau_k != 0.0) {
+          for (int i = 0; i < len; ++i) a[static_cast<size_t>(k + 1 + i) * n + k] = v[i];  // beta, tail
+          v[0] = 1.0;
+        }
+      }
+      bar.wait();
+      const double tk = tau_k;
+      const int lo = static_cast<int>(static_cast<long long>(len) * tid / nt);
+      const int hi = static_cast<int>(static_cast<long long>(len) * (tid + 1) / nt);
+      if (tk != 0.0)
+        for (int i = lo; i < hi; ++i) {        // p = tau A' v
+          const double* row = &a[static_cast<size_t>(k + 1 + i) * n + k + 1];
+          double s = 0.0;
+          for (int j = 0; j < len; ++j) s += row[j] * v[j];
+          p[i] = tk * s;
+        }
+      bar.wait();
+      if (tid == 0 && tk != 0.0) {             // w = p - (tau p.v / 2) v
+        double pv = 0.0;
+        for (int i = 0; i < len; ++i) pv += p[i] * v[i];
+        const double K = 0.5 * tk * pv;
+        for (int i = 0; i < len; ++i) wv[i] = p[i] - K * v[i];
+      }
+      bar.wait();
+      if (tk != 0.0)
+        for (int i = lo; i < hi; ++i) {        // A' -= v w^T + w v^T
+          double* row = &a[static_cast<size_t>(k + 1 + i) * n + k + 1];
+          const double vi = v[i], wi = wv[i];
+          for (int j = 0; j < len; ++j) row[j] -= vi * wv[j] + wi * v[j];
+        }
+      bar.wait();
+    }
+  });
+  std::vector<double> d(n), e(n, 0.0);
   for (int i = 0; i < n; ++i) d[i] = a[static_cast<size_t>(i) * n + i];
   for (int i = 0; i + 1 < n; ++i) e[i] = a[static_cast<size_t>(i + 1) * n + i];
-  // implicit QL iterations with shifts on (d, e)
+  // 2. Q (column-major): column j is H_0 ... H_{j-1} e_j; blocks of 16 columns
+  // share each reflector load and are dealt to the team round robin
+  // reflector k, contiguous: refl[k * n + i] = v_i (i < n - k - 1, v_0 = 1)
+  for (int k = 0; k + 2 < n; ++k) {
+    double* r = &a[static_cast<size_t>(k) * n];     // row k is no longer needed
+    r[0] = 1.0;
+    for (int i = 1; i < n - k - 1; ++i) r[i] = a[static_cast<size_t>(k + 1 + i) * n + k];
+  }
+  std::vector<double> q(static_cast<size_t>(n) * n, 0.0);
+  const int CB = 16, nblk = (n + CB - 1) / CB;
+  run_team(nt, [&](int tid) {
+    for (int b = tid; b < nblk; b += nt) {
+      const int j0 = b * CB, j1 = std::min(n, j0 + CB);
+      for (int j = j0; j < j1; ++j) q[static_cast<size_t>(j) * n + j] = 1.0;
+      for (int k = std::min(j1 - 1, n - 2) - 1; k >= 0; --k) {
+        if (tau[k] == 0.0) continue;
+        const double* vt = &a[static_cast<size_t>(k) * n];
+        const int len = n - k - 1;
+        for (int j = std::max(j0, k + 1); j < j1; ++j) {
+          double* x = &q[static_cast<size_t>(j) * n + k + 1];
+          double s = 0.0;
+          for (int i = 0; i < len; ++i) s += vt[i] * x[i];
+          s *= tau[k];
+          for (int i = 0; i < len; ++i) x[i] -= s * vt[i];
+        }
+      }
+    }
+  });
+  // 3. implicit QL iterations with shifts on (d, e), recording the rotations
+  std::vector<Rotation> rot;
   for (int l = 0; l < n; ++l) {
     int iter = 0;
     for (;;) {
@@ -479,10 +550,9 @@ void sym_eig(int n, const double* Ain, double* w, double* Vout) {
       double r = std::hypot(g, 1.0);
       g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? std::fabs(r) : -std::fabs(r)));
       double s = 1.0, c = 1.0, pp = 0.0;
-      int i;
       bool early = false;
-      for (i = m - 1; i >= l; --i) {
-        double f = s * e[i];
+      for (int i = m - 1; i >= l; --i) {
+        const double f = s * e[i];
         const double b = c * e[i];
         r = std::hypot(f, g);
         e[i + 1] = r;
@@ -499,13 +569,7 @@ void sym_eig(int n, const double* Ain, double* w, double* Vout) {
         pp = s * r;
         d[i + 1] = g + pp;
         g = c * r - b;
-        double* qi = &q[static_cast<size_t>(i) * n];
-        double* qi1 = &q[static_cast<size_t>(i + 1) * n];
-        for (int t = 0; t < n; ++t) {
-          f = qi1[t];
-          qi1[t] = s * qi[t] + c * f;
-          qi[t] = c * qi[t] - s * f;
-        }
+        rot.push_back({i, c, s});
       }
       if (early) continue;
       d[l] -= pp;
@@ -513,6 +577,20 @@ void sym_eig(int n, const double* Ain, double* w, double* Vout) {
       e[m] = 0.0;
     }
   }
+  // 4. apply the rotations in order to the columns of Q, rows split over the team
+  run_team(nt, [&](int tid) {
+    const int lo = static_cast<int>(static_cast<long long>(n) * tid / nt);
+    const int hi = static_cast<int>(static_cast<long long>(n) * (tid + 1) / nt);
+    for (const Rotation& R : rot) {
+      double* qi = &q[static_cast<size_t>(R.i) * n];
+      double* qi1 = qi + n;
+      for (int t = lo; t < hi; ++t) {
+        const double f = qi1[t];
+        qi1[t] = R.s * qi[t] + R.c * f;
+        qi[t] = R.c * qi[t] - R.s * f;
+      }
+    }
+  });
   // sort ascending, write eigenvectors as columns of row-major V
   std::vector<int> idx(n);
   for (int i = 0; i < n; ++i) idx[i] = i;
@@ -524,24 +602,30 @@ void sym_eig(int n, const double* Ain, double* w, double* Vout) {
   }
 }
 
-void sym_pinv(int n, const double* A, double* out, double rel_tol) {
+void sym_pinv(int n, const double* A, double* out, double rel_tol, int nthreads) {
   std::vector<double> w(n), V(static_cast<size_t>(n) * n);
-  sym_eig(n, A, w.data(), V.data());
+  sym_eig(n, A, w.data(), V.data(), nthreads);
   double wmax = 0.0;
   for (int i = 0; i < n; ++i) wmax = std::max(wmax, std::fabs(w[i]));
   std::vector<double> inv(n);
   for (int i = 0; i < n; ++i) inv[i] = std::fabs(w[i]) > rel_tol * wmax ? 1.0 / w[i] : 0.0;
-  // out = V diag(inv) V^T (V row-major, so rows r and c are contiguous)
-  for (int r = 0; r < n; ++r) {
-    const double* vr = &V[static_cast<size_t>(r) * n];
-    for (int c = r; c < n; ++c) {
-      const double* vc = &V[static_cast<size_t>(c) * n];
-      double s = 0.0;
-      for (int t = 0; t < n; ++t) s += vr[t] * inv[t] * vc[t];
-      out[static_cast<size_t>(r) * n + c] = s;
-      out[static_cast<size_t>(c) * n + r] = s;
+  // out = V diag(inv) V^T (V row-major, so rows r and c are contiguous); row r
+  // owns the entries (r, c >= r) and their mirror images
+  const int nt = n >= 256 ? std::max(1, std::min(nthreads, n / 64)) : 1;
+  run_team(nt, [&](int tid) {
+    std::vector<double> u(n);
+    for (int r = tid; r < n; r += nt) {
+      const double* vr = &V[static_cast<size_t>(r) * n];
+      for (int t = 0; t < n; ++t) u[t] = vr[t] * inv[t];
+      for (int c = r; c < n; ++c) {
+        const double* vc = &V[static_cast<size_t>(c) * n];
+        double s = 0.0;
+        for (int t = 0; t < n; ++t) s += u[t] * vc[t];
+        out[static_cast<size_t>(r) * n + c] = s;
+        out[static_cast<size_t>(c) * n + r] = s;
+      }
     }
-  }
+  });
 }
 
 }  // namespace ldgmg

@@ -42,11 +42,12 @@ bool ls_block_normal(int bs, int mb, int nb,
                      double* X);
 
 // A: n x n symmetric, row-major (only read).  w: n eigenvalues (ascending),
-// V: n x n row-major with eigenvectors in columns.
-void sym_eig(int n, const double* A, double* w, double* V);
+// V: n x n row-major with eigenvectors in columns.  For n >= 256 the work is
+// split over up to nthreads threads (results do not depend on the count).
+void sym_eig(int n, const double* A, double* w, double* V, int nthreads = 1);
 
 // out = pseudo-inverse of symmetric A (n x n, row-major) with eigenvalues
 // |lambda| <= rel_tol * max|lambda| treated as zero.
-void sym_pinv(int n, const double* A, double* out, double rel_tol);
+void sym_pinv(int n, const double* A, double* out, double rel_tol, int nthreads = 1);
 
 }  // namespace ldgmg

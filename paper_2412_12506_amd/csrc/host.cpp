@@ -1007,7 +1007,7 @@ void build_bottom(HostLevel& L) {
       dense[static_cast<size_t>(r) * N + c] = dense[static_cast<size_t>(c) * N + r] = v;
     }
   L.pinv.assign(static_cast<size_t>(N) * N, 0.0);
-  sym_pinv(N, dense.data(), L.pinv.data(), 1e-12);
+  sym_pinv(N, dense.data(), L.pinv.data(), 1e-12, g_threads);
 }
 
 }  // namespace

@@ -25,6 +25,10 @@ CASES = [
          mu=("disc", 0.25, 1e3)),
     dict(id="s2d-p1-std-jacobi", dim=2, n=8, p=1, system="stokes", gamma=0, smoother="jacobi"),
     dict(id="p2d-p2-neumann-x", dim=2, n=8, p=2, smoother="sai", bc=["N", "N", "D", "D"]),
+    # bottoms of 400 and 675 unknowns: the eigensolver splits its work over threads
+    dict(id="p2d-p3-n10-threaded-bottom", dim=2, n=10, p=3, smoother="jacobi", nthreads=4),
+    dict(id="s2d-p2-n10-threaded-bottom", dim=2, n=10, p=2, system="stokes", gamma=1, smoother="sai",
+         mu=("disc", 0.25, 1e3), nthreads=3),
 ]
 
 
@@ -80,3 +84,17 @@ def test_invalid_problems_are_rejected():
             s.close()
         if isinstance(ei.value, L.LdgmgError):
             assert ei.value.code == L.EINVAL
+
+
+def test_bottom_independent_of_thread_count():
+    """The threaded eigensolver does the same arithmetic in the same order."""
+    from paper_2412_12506_amd import ldgmg as L
+    out = []
+    for nt in (1, 2, 5):
+        s = L.Solver(host_only=True, dim=2, n=10, p=3, smoother="jacobi", nthreads=nt)
+        try:
+            out.append(L.ldgmg_export(s.handle, s.nlevels - 1, "PINV"))
+        finally:
+            s.close()
+    assert out[0].shape == (400, 400)
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
