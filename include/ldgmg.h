@@ -56,11 +56,21 @@ enum { LDGMG_SMOOTH_JACOBI = 0, LDGMG_SMOOTH_GS = 1, LDGMG_SMOOTH_SAI = 2 };
  * O = forward (eq:B1 / colours in order), I = reverse (eq:BT / colours reversed) */
 enum { LDGMG_ORDER_OO = 0, LDGMG_ORDER_OI = 1, LDGMG_ORDER_IO = 2, LDGMG_ORDER_II = 3 };
 /* storage precision of the V-cycle's matrices (A on every level, the smoother
- * matrix B or D^-1): FP64 or FP32.  V-cycle vectors, transfers and all
- * arithmetic are FP64 in both modes (FP32 blocks are widened as they are
- * read); the outer Krylov iteration, its FP64 operator and inner products are
- * FP64. */
-enum { LDGMG_FP64 = 0, LDGMG_FP32 = 1 };
+ * matrix B or D^-1): FP64, FP32, or LDGMG_BF16S = FP32 operators with the SAI
+ * matrices B and B^T in BF16 (round to nearest even via FP32; SAI smoothers
+ * only, EINVAL otherwise).  V-cycle vectors, transfers and all arithmetic are
+ * FP64 in every mode (stored blocks are widened exactly as they are read); the
+ * outer Krylov iteration, its FP64 operator and inner products are FP64. */
+enum { LDGMG_FP64 = 0, LDGMG_FP32 = 1, LDGMG_BF16S = 2 };
+/* device storage of the block-sparse matrices.  EXPANDED: every slot holds its
+ * block.  POOLED: the distinct blocks of a matrix are stored once and every
+ * slot holds a 4-byte block id; the setup builds each matrix as such a pool
+ * (identical blocks are computed once), so both storages hold the same values.
+ * AUTO: per matrix and level, POOLED when its distinct blocks take at most
+ * 64 MiB and at most a quarter of the expanded bytes, else EXPANDED.  Pooled
+ * storage needs a block size with a wave-mapped kernel (4, 8, 9, 12, 16, 25,
+ * 27, 32, 36, 48, 64); other sizes are always expanded. */
+enum { LDGMG_STORE_AUTO = 0, LDGMG_STORE_EXPANDED = 1, LDGMG_STORE_POOLED = 2 };
 enum { LDGMG_CG = 0, LDGMG_GMRES = 1 };
 
 typedef struct ldgmg_hier* ldgmg_handle;
@@ -84,9 +94,10 @@ typedef struct {
   int nu1, nu2;       /* pre/post smoothing steps (paper: 3, 3)                   */
   double omega;       /* damping (Jacobi 0.8, coloured GS 1.0); <= 0 -> default   */
   double zeta;        /* Stokes balancing weight (tab:zeta); <= 0 -> tab:zeta     */
-  int precision;      /* LDGMG_FP64 | LDGMG_FP32 (block storage of the V-cycle)  */
+  int precision;      /* LDGMG_FP64 | LDGMG_FP32 | LDGMG_BF16S (block storage)   */
   int nthreads;       /* host threads for the setup; <= 0 -> hardware count      */
   size_t hbm_budget;  /* refuse ldgmg_upload above this many bytes; 0 = no limit */
+  int storage;        /* LDGMG_STORE_* (default AUTO)                            */
 } ldgmg_problem;
 
 typedef struct {
@@ -135,6 +146,15 @@ int ldgmg_unload(ldgmg_handle h);
  * ldgmg_upload allocated plus the batch workspace once a batched call made it. */
 int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes);
 
+/* Device storage chosen for one level (needs device data): number of distinct
+ * blocks stored for A and for the smoother matrix when pooled, 0 when that
+ * matrix is expanded (every slot holds its block). */
+int ldgmg_level_storage(ldgmg_handle h, int level, int* pool_A, int* pool_S);
+
+/* Device bytes ldgmg_upload will allocate for this host hierarchy (exact for
+ * its storage choices; the batch workspace of the batched calls not included). */
+int ldgmg_upload_bytes(ldgmg_handle h, size_t* bytes);
+
 /* Sizes: fine-level unknowns, unknowns per element, number of levels. */
 int ldgmg_sizes(ldgmg_handle h, long long* ndofs, int* bs, int* nlevels);
 
@@ -158,8 +178,10 @@ int ldgmg_vcycle(ldgmg_handle h, const double* b_dev, double* x_dev, void* strea
  * (krylov = LDGMG_CG; needs a symmetric V) or of left-preconditioned GMRES
  * (LDGMG_GMRES, no restart, at most min(maxit, 200) iterations).  Stops when
  * ||r||_2 <= rtol ||b||_2 (CG, FP64 recursive residual) or
- * ||V r||_2 <= rtol ||V b||_2 (GMRES).  Returns LDGMG_ENOCONV if maxit is hit.
- * info may be NULL. */
+ * ||V r||_2 <= rtol ||V b||_2 (GMRES).  Returns LDGMG_ENOCONV if maxit is hit
+ * or, for CG, at a breakdown: r^T V r <= 0 or p^T A p <= 0 (a preconditioner
+ * that is not positive definite), where CG stops at once; info then holds the
+ * iterations done and the residual reached.  info may be NULL. */
 int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov,
                 double rtol, int maxit, ldgmg_info* info, void* stream);
 

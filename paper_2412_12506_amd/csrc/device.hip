@@ -53,6 +53,9 @@ struct DevLevel {
   int* tposS = nullptr;
   void* valS = nullptr;
   void* valST = nullptr;            // transposed copy: block (i,j) holds (S_ji)^T (fast kernels only)
+  int* bidA = nullptr;              // pooled storage: block id per slot (null when expanded)
+  int* bidS = nullptr;
+  int* bidST = nullptr;
   std::vector<int*> colour_rows;    // device lists per colour
   std::vector<int> colour_count;
   double* x = nullptr;              // level vectors are FP64 in both precisions
@@ -67,9 +70,11 @@ struct DevLevel {
 
 struct DevHier {
   int prec = LDGMG_FP32;
+  int storage = LDGMG_STORE_AUTO;
   int device = 0;
   std::vector<DevLevel> L;
   double* val64 = nullptr;          // fine-level FP64 A values (own copy only in FP32 mode)
+  int* bid64 = nullptr;             // its block ids when pooled
   bool own64 = false;
   double *kx = nullptr, *kr = nullptr, *kp = nullptr, *kq = nullptr, *kz = nullptr;
   double* scal = nullptr;           // scalar table
@@ -128,17 +133,36 @@ namespace {
 
 enum { S_BB = 0, S_RZ = 1, S_ALPHA = 2, S_RR = 3, S_BETA = 4, S_PQ = 5, S_TMP = 6, S_W = 7 };
 
-size_t elem_bytes(int prec) { return prec == LDGMG_FP64 ? 8 : 4; }
+// bytes per stored entry of the operators A and of the smoother S
+size_t elem_bytes_A(int prec) { return prec == LDGMG_FP64 ? 8 : 4; }
+size_t elem_bytes_S(int prec) { return prec == LDGMG_FP64 ? 8 : prec == LDGMG_BF16S ? 2 : 4; }
 
-// bytes one level needs on the device in precision prec
+// pooled storage of one matrix with elements of `elem` bytes (LDGMG_STORE_*)
+bool use_pool(const PMat& P, int bs, size_t elem, int storage) {
+  if (!fast_bs(bs) || storage == LDGMG_STORE_EXPANDED) return false;
+  if (storage == LDGMG_STORE_POOLED) return true;
+  const size_t bb = static_cast<size_t>(bs) * bs * elem;
+  const size_t pool = static_cast<size_t>(P.pool.size()) * bb;
+  return pool <= (static_cast<size_t>(64) << 20) && 4 * pool <= static_cast<size_t>(P.nnzb()) * bb;
+}
+
+// device bytes of one matrix's blocks (and block ids when pooled)
+size_t matrix_bytes(const PMat& P, int bs, size_t elem, int storage) {
+  const size_t bb = static_cast<size_t>(bs) * bs * elem;
+  if (use_pool(P, bs, elem, storage)) return static_cast<size_t>(P.pool.size()) * bb + P.nnzb() * sizeof(int);
+  return static_cast<size_t>(P.nnzb()) * bb;
+}
+
+// bytes one level needs on the device in precision prec (expanded storage;
+// used before the setup, from the stencil sizes)
 size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long nnzS, bool bottom,
                    bool gs, int prec) {
-  const size_t eb = elem_bytes(prec);
+  const size_t ea = elem_bytes_A(prec), es = elem_bytes_S(prec);
   const size_t N = static_cast<size_t>(ne) * bs;
   size_t b = 0;
-  b += (ne + 1) * 4 + nnzA * 4 + nnzA * static_cast<size_t>(bs) * bs * eb;
+  b += (ne + 1) * 4 + nnzA * 4 + nnzA * static_cast<size_t>(bs) * bs * ea;
   if (!bottom) {
-    b += (ne + 1) * 4 + nnzS * 8 + nnzS * static_cast<size_t>(bs) * bs * eb * (fast_bs(bs) ? 2 : 1);
+    b += (ne + 1) * 4 + nnzS * 8 + nnzS * static_cast<size_t>(bs) * bs * es * (fast_bs(bs) ? 2 : 1);
     if (gs) b += ne * 4;
   } else {
     b += N * N * 8;
@@ -148,7 +172,7 @@ size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long n
   return b;
 }
 
-template <typename T>   // T: element type of the stored blocks
+template <typename TA, typename TS>   // element types of the stored operator and smoother blocks
 void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hipStream_t st) {
   dl.n = hl.n;
   dl.ne = hl.ne;
@@ -162,31 +186,44 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
     HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
     return p;
   };
-  // expand a pooled matrix into device blocks of type T (staging the pool and ids)
-  auto expand = [&](const PMat& P, bool transpose) {
-    T* out = static_cast<T*>(D.alloc(static_cast<size_t>(P.nnzb()) * bb * sizeof(T)));
+  const int storage = D.storage;
+  // device blocks of type T for a pooled host matrix (transposed blocks if
+  // asked): every slot's block (expanded), or the distinct blocks once with
+  // the block id of every slot in `bid` (pooled; bid stays null otherwise)
+  auto place = [&](auto tag, const PMat& P, bool transpose, int*& bid) {
+    using T = decltype(tag);
+    const bool pooled = use_pool(P, hl.bs, sizeof(T), storage);
+    const int nd = P.pool.size();
+    std::vector<int> order;
+    if (pooled) {
+      order.resize(nd);
+      for (int i = 0; i < nd; ++i) order[i] = i;
+    }
+    const std::vector<int>& ids_h = pooled ? order : P.id;
+    T* out = static_cast<T*>(D.alloc(ids_h.size() * bb * sizeof(T)));
     double* pool = nullptr;
     int* ids = nullptr;
     HIPCHK(hipMalloc(&pool, std::max<size_t>(16, P.pool.data.size() * sizeof(double))));
-    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, P.id.size() * sizeof(int))));
+    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, ids_h.size() * sizeof(int))));
     HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ids, P.id.data(), P.id.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    expand_blocks<T>(P.nnzb(), hl.bs, ids, pool, out, transpose, st);
+    HIPCHK(hipMemcpyAsync(ids, ids_h.data(), ids_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    expand_blocks<T>(static_cast<long long>(ids_h.size()), hl.bs, ids, pool, out, transpose, st);
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipFree(pool));
     HIPCHK(hipFree(ids));
+    bid = pooled ? up_ints(P.id) : nullptr;
     return out;
   };
   dl.nnzA = hl.A.nnzb();
   dl.rpA = up_ints(hl.A.rp);
   dl.ciA = up_ints(hl.A.ci);
-  dl.valA = expand(hl.A, false);
+  dl.valA = place(TA{}, hl.A, false, dl.bidA);
   if (!bottom) {
     dl.nnzS = hl.S.nnzb();
     dl.rpS = up_ints(hl.S.rp);
     dl.ciS = up_ints(hl.S.ci);
     dl.tposS = up_ints(hl.tpos);
-    dl.valS = expand(hl.S, false);
+    dl.valS = place(TS{}, hl.S, false, dl.bidS);
     if (fast_bs(hl.bs)) {   // S^T applies stream a transposed copy through the forward kernel
       PMat st;
       st.nbr = hl.S.nbr;
@@ -198,7 +235,7 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
       st.pool.r = hl.S.pool.r;
       st.pool.c = hl.S.pool.c;
       st.pool.data = hl.S.pool.data;
-      dl.valST = expand(st, true);
+      dl.valST = place(TS{}, st, true, dl.bidST);
     }
     for (const auto& rows : hl.colour_rows) {
       dl.colour_rows.push_back(up_ints(rows));
@@ -231,17 +268,34 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
   HIPCHK(hipStreamSynchronize(st));
 }
 
+// exact device bytes of ldgmg_upload for a host hierarchy (batch workspace excluded)
 size_t estimate_from_host(const HostHierarchy& H, int prec) {
+  const int storage = H.prob.storage;
+  const size_t ea = elem_bytes_A(prec), es = elem_bytes_S(prec);
   size_t b = 0;
   const int nl = static_cast<int>(H.levels.size());
   for (int l = 0; l < nl; ++l) {
     const HostLevel& L = H.levels[l];
-    b += level_bytes(L.ne, L.bs, L.bss, L.em.dim, L.A.nnzb(), L.S.nnzb(), l == nl - 1,
-                     H.prob.smoother == LDGMG_SMOOTH_GS, prec);
+    const size_t N = static_cast<size_t>(L.ne) * L.bs;
+    const bool bottom = l == nl - 1;
+    b += (L.ne + 1) * 4 + L.A.nnzb() * 4 + matrix_bytes(L.A, L.bs, ea, storage);
+    if (!bottom) {
+      b += (L.ne + 1) * 4 + L.S.nnzb() * 4 + L.tpos.size() * 4 + matrix_bytes(L.S, L.bs, es, storage);
+      if (fast_bs(L.bs)) b += matrix_bytes(L.S, L.bs, es, storage);   // transposed copy
+      for (const auto& rows : L.colour_rows) b += std::max<size_t>(16, rows.size() * 4);
+    } else {
+      b += N * N * 8;
+    }
+    b += 4 * N * 8;
+    b += (static_cast<size_t>(1) << L.em.dim) * L.bss * L.bss * 8 + 2 * L.em.q1 * L.em.q1 * 8;
   }
   const HostLevel& F = H.levels[0];
   const size_t N = static_cast<size_t>(F.ne) * F.bs;
-  if (prec != LDGMG_FP64) b += static_cast<size_t>(F.A.nnzb()) * F.bs * F.bs * 8;
+  if (prec != LDGMG_FP64) {
+    const size_t bb8 = static_cast<size_t>(F.bs) * F.bs * 8;
+    b += use_pool(F.A, F.bs, ea, storage) ? static_cast<size_t>(F.A.pool.size()) * bb8
+                                          : static_cast<size_t>(F.A.nnzb()) * bb8;
+  }
   b += 5 * N * 8 + 64 * 8 + kRedBlocks * 8 * 2;
   return b;
 }
@@ -254,30 +308,43 @@ void upload(ldgmg_hier* h, hipStream_t st) {
                       std::to_string(H.prob.hbm_budget));
   auto D = std::make_unique<DevHier>();
   D->prec = H.prob.precision;
+  D->storage = H.prob.storage;
   HIPCHK(hipGetDevice(&D->device));
   const int nl = static_cast<int>(H.levels.size());
   D->L.resize(nl);
   for (int l = 0; l < nl; ++l) {
     D->L[l].index = l;
     if (D->prec == LDGMG_FP64)
-      upload_level<double>(*D, D->L[l], H.levels[l], l == nl - 1, st);
+      upload_level<double, double>(*D, D->L[l], H.levels[l], l == nl - 1, st);
+    else if (D->prec == LDGMG_BF16S)
+      upload_level<float, bf16s>(*D, D->L[l], H.levels[l], l == nl - 1, st);
     else
-      upload_level<float>(*D, D->L[l], H.levels[l], l == nl - 1, st);
+      upload_level<float, float>(*D, D->L[l], H.levels[l], l == nl - 1, st);
   }
   const HostLevel& F = H.levels[0];
   DevLevel& f = D->L[0];
   if (D->prec == LDGMG_FP64) {
     D->val64 = static_cast<double*>(f.valA);
+    D->bid64 = f.bidA;
   } else {
+    // the FP64 operator of the Krylov iteration follows the storage of A: the
+    // distinct blocks (sharing A's block ids) when A is pooled
     const size_t bb = static_cast<size_t>(F.bs) * F.bs;
-    D->val64 = static_cast<double*>(D->alloc(static_cast<size_t>(F.A.nnzb()) * bb * sizeof(double)));
+    std::vector<int> order;
+    if (f.bidA) {
+      order.resize(F.A.pool.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+    }
+    const std::vector<int>& ids_h = f.bidA ? order : F.A.id;
+    D->val64 = static_cast<double*>(D->alloc(ids_h.size() * bb * sizeof(double)));
+    D->bid64 = f.bidA;
     double* pool = nullptr;
     int* ids = nullptr;
     HIPCHK(hipMalloc(&pool, std::max<size_t>(16, F.A.pool.data.size() * sizeof(double))));
-    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, F.A.id.size() * sizeof(int))));
+    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, ids_h.size() * sizeof(int))));
     HIPCHK(hipMemcpyAsync(pool, F.A.pool.data.data(), F.A.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ids, F.A.id.data(), F.A.id.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    expand_blocks<double>(F.A.nnzb(), F.bs, ids, pool, D->val64, false, st);
+    HIPCHK(hipMemcpyAsync(ids, ids_h.data(), ids_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    expand_blocks<double>(static_cast<long long>(ids_h.size()), F.bs, ids, pool, D->val64, false, st);
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipFree(pool));
     HIPCHK(hipFree(ids));
@@ -334,6 +401,7 @@ BsrArgs<T, Vd> argsA(const DevLevel& L) {
   a.bs = L.bs;
   a.rp = L.rpA;
   a.ci = L.ciA;
+  a.bid = L.bidA;
   a.blk = static_cast<const T*>(L.valA);
   return a;
 }
@@ -345,6 +413,7 @@ BsrArgs<T, Vd> argsS(const DevLevel& L) {
   a.rp = L.rpS;
   a.ci = L.ciS;
   a.tpos = L.tposS;
+  a.bid = L.bidS;
   a.blk = static_cast<const T*>(L.valS);
   return a;
 }
@@ -379,6 +448,7 @@ void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* o
   a.beta = beta;
   if (transposed && L.valST) {
     a.blk = static_cast<const T*>(L.valST);
+    a.bid = L.bidST;
     bsr_forward<T, Vd>(a, st);
   } else if (transposed) {
     bsr_transposed<T, Vd>(a, st);
@@ -396,7 +466,9 @@ void apply_S(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, const 
 
 // one smoothing step on level L with x (in/out), b.  `zero_x`: x is known to be 0.
 // Uses L.r / L.t as scratch.  Returns the buffer holding the result (x or t).
-template <typename T>
+// T: operator blocks, TS: smoother blocks (the block inverses of Jacobi and
+// Gauss-Seidel share the operator's type)
+template <typename T, typename TS>
 Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, bool zero_x) {
   const int sm = c.H.prob.smoother;
   const Vd omega = c.H.omega;
@@ -404,11 +476,11 @@ Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, boo
   Vd* t = L.t;
   if (sm == LDGMG_SMOOTH_SAI) {
     if (zero_x) {             // x = S b  (eq:B1) or S^T b (eq:BT) from x = 0
-      apply_S<T>(c.D, L, !forward, b, nullptr, x, 1.0, 0.0, c.st);
+      apply_S<TS>(c.D, L, !forward, b, nullptr, x, 1.0, 0.0, c.st);
       return x;
     }
     residual<T>(c.D, L, x, b, r, c.st);
-    apply_S<T>(c.D, L, !forward, r, x, x, 1.0, 1.0, c.st);
+    apply_S<TS>(c.D, L, !forward, r, x, x, 1.0, 1.0, c.st);
     return x;
   }
   if (sm == LDGMG_SMOOTH_JACOBI) {
@@ -422,6 +494,7 @@ Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, boo
       a.z = b;
       a.out = t;
       a.dinv = static_cast<const T*>(L.valS);
+      a.dbid = L.bidS;        // D^-1 is block diagonal: slot = row
       a.omega = omega;
       ProfScope ps(c.D, L, c.st, K_FUSED);
       bsr_forward<T, Vd>(a, c.st);
@@ -444,6 +517,7 @@ Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, boo
       a.z = b;
       a.out = x;              // in place: rows of one colour are not coupled
       a.dinv = static_cast<const T*>(L.valS);
+      a.dbid = L.bidS;
       a.omega = omega;
       ProfScope ps(c.D, L, c.st, K_FUSED);
       bsr_forward<T, Vd>(a, c.st);
@@ -475,7 +549,7 @@ int order_pre_forward(int order) { return order == LDGMG_ORDER_OO || order == LD
 int order_post_forward(int order) { return order == LDGMG_ORDER_OO || order == LDGMG_ORDER_IO; }
 
 // x_l = V(E_l, 0, b_l) with b_l in L[l].b, result in L[l].x   (Algorithm 1)
-template <typename T>
+template <typename T, typename TS>
 void vcycle_level(const Ctx& c, int l) {
   DevLevel& L = c.D.L[l];
   const int nl = static_cast<int>(c.D.L.size());
@@ -494,21 +568,22 @@ void vcycle_level(const Ctx& c, int l) {
     }
   };
   if (P.nu1 == 0) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(Vd), c.st));
-  for (int s = 0; s < P.nu1; ++s) keep(smooth_step<T>(c, L, x, b, pre_fwd, s == 0));
+  for (int s = 0; s < P.nu1; ++s) keep(smooth_step<T, TS>(c, L, x, b, pre_fwd, s == 0));
   residual<T>(c.D, L, x, b, L.r, c.st);
   DevLevel& Lc = c.D.L[l + 1];
   restrict_op<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, L.r, Lc.b, c.st);
-  vcycle_level<T>(c, l + 1);
+  vcycle_level<T, TS>(c, l + 1);
   prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, Lc.x, x, c.st);
-  for (int s = 0; s < P.nu2; ++s) keep(smooth_step<T>(c, L, x, b, post_fwd, false));
+  for (int s = 0; s < P.nu2; ++s) keep(smooth_step<T, TS>(c, L, x, b, post_fwd, false));
 }
 
 // z = V r (FP64 vectors in and out; the stored blocks are FP32 or FP64)
 void vcycle64(const Ctx& c, const double* r, double* z) {
   DevLevel& L = c.D.L[0];
   HIPCHK(hipMemcpyAsync(L.b, r, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
-  if (c.D.prec == LDGMG_FP64) vcycle_level<double>(c, 0);
-  else vcycle_level<float>(c, 0);
+  if (c.D.prec == LDGMG_FP64) vcycle_level<double, double>(c, 0);
+  else if (c.D.prec == LDGMG_BF16S) vcycle_level<float, bf16s>(c, 0);
+  else vcycle_level<float, float>(c, 0);
   HIPCHK(hipMemcpyAsync(z, L.x, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
 }
 
@@ -520,6 +595,7 @@ void apply_A64(const Ctx& c, const double* x, double* y) {
   a.rp = L.rpA;
   a.ci = L.ciA;
   a.blk = c.D.val64;
+  a.bid = c.D.bid64;
   a.x = x;
   a.out = y;
   ProfScope ps(c.D, L, c.st, K_A64);
@@ -610,6 +686,9 @@ int solve_cg(const Ctx& c, const double* b, double* x, double rtol, int maxit, l
       conv = true;
       break;
     }
+    // r^T V r <= 0 or p^T A p <= 0: the preconditioner (or A) is not positive
+    // definite on the Krylov space and CG cannot continue; stop unconverged
+    if (!(D.hscal[S_RZ] > 0.0) || !(D.hscal[S_ALPHA] > 0.0)) break;
     vcycle64(c, D.kr, D.kz);
     ++vcycles;
     dot_partial(N, D.kr, D.kz, D.partial, c.st);
@@ -760,7 +839,10 @@ void apply_S_multi(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, 
   }
   ProfScope ps(D, L, st, transposed ? K_ST : K_SF);
   BsrArgs<T, Vd> a = argsS<T>(L);
-  if (transposed) a.blk = static_cast<const T*>(L.valST);
+  if (transposed) {
+    a.blk = static_cast<const T*>(L.valST);
+    a.bid = L.bidST;
+  }
   if (rows) {
     a.nrows = nrows;
     a.rows = rows;
@@ -773,18 +855,18 @@ void apply_S_multi(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, 
   bsr_forward_multi<T, Vd>(a, L.N, nk, st);
 }
 
-template <typename T>
+template <typename T, typename TS>
 void smooth_step_multi(const Ctx& c, DevLevel& L, DevHier::BatchLevel& B, bool forward, bool zero_x, int nk) {
   const int sm = c.H.prob.smoother;
   const Vd omega = c.H.omega;
   const size_t vb = static_cast<size_t>(L.N) * nk * sizeof(Vd);
   if (sm == LDGMG_SMOOTH_SAI) {
     if (zero_x) {
-      apply_S_multi<T>(c.D, L, !forward, B.b, nullptr, B.x, 1.0, 0.0, nk, c.st);
+      apply_S_multi<TS>(c.D, L, !forward, B.b, nullptr, B.x, 1.0, 0.0, nk, c.st);
       return;
     }
     residual_multi<T>(c.D, L, B.x, B.b, B.r, nk, c.st);
-    apply_S_multi<T>(c.D, L, !forward, B.r, B.x, B.x, 1.0, 1.0, nk, c.st);
+    apply_S_multi<TS>(c.D, L, !forward, B.r, B.x, B.x, 1.0, 1.0, nk, c.st);
     return;
   }
   if (sm == LDGMG_SMOOTH_JACOBI) {
@@ -805,7 +887,7 @@ void smooth_step_multi(const Ctx& c, DevLevel& L, DevHier::BatchLevel& B, bool f
   }
 }
 
-template <typename T>
+template <typename T, typename TS>
 void vcycle_level_multi(const Ctx& c, int l, int nk) {
   DevLevel& L = c.D.L[l];
   DevHier::BatchLevel& B = c.D.BL[l];
@@ -818,16 +900,16 @@ void vcycle_level_multi(const Ctx& c, int l, int nk) {
   const ldgmg_problem& P = c.H.prob;
   const bool pre_fwd = order_pre_forward(P.order), post_fwd = order_post_forward(P.order);
   if (P.nu1 == 0) HIPCHK(hipMemsetAsync(B.x, 0, static_cast<size_t>(L.N) * nk * sizeof(Vd), c.st));
-  for (int s = 0; s < P.nu1; ++s) smooth_step_multi<T>(c, L, B, pre_fwd, s == 0, nk);
+  for (int s = 0; s < P.nu1; ++s) smooth_step_multi<T, TS>(c, L, B, pre_fwd, s == 0, nk);
   residual_multi<T>(c.D, L, B.x, B.b, B.r, nk, c.st);
   DevLevel& Lc = c.D.L[l + 1];
   DevHier::BatchLevel& Bc = c.D.BL[l + 1];
   for (int q = 0; q < nk; ++q)
     restrict_op<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, B.r + q * L.N, Bc.b + q * Lc.N, c.st);
-  vcycle_level_multi<T>(c, l + 1, nk);
+  vcycle_level_multi<T, TS>(c, l + 1, nk);
   for (int q = 0; q < nk; ++q)
     prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, Bc.x + q * Lc.N, B.x + q * L.N, c.st);
-  for (int s = 0; s < P.nu2; ++s) smooth_step_multi<T>(c, L, B, post_fwd, false, nk);
+  for (int s = 0; s < P.nu2; ++s) smooth_step_multi<T, TS>(c, L, B, post_fwd, false, nk);
 }
 
 // z_q = V r_q for the nk vectors at r and z (stride N)
@@ -836,8 +918,9 @@ void vcycle64_multi(const Ctx& c, const double* r, double* z, int nk) {
   DevHier::BatchLevel& B = c.D.BL[0];
   const size_t vb = static_cast<size_t>(L.N) * nk * 8;
   HIPCHK(hipMemcpyAsync(B.b, r, vb, hipMemcpyDeviceToDevice, c.st));
-  if (c.D.prec == LDGMG_FP64) vcycle_level_multi<double>(c, 0, nk);
-  else vcycle_level_multi<float>(c, 0, nk);
+  if (c.D.prec == LDGMG_FP64) vcycle_level_multi<double, double>(c, 0, nk);
+  else if (c.D.prec == LDGMG_BF16S) vcycle_level_multi<float, bf16s>(c, 0, nk);
+  else vcycle_level_multi<float, float>(c, 0, nk);
   HIPCHK(hipMemcpyAsync(z, B.x, vb, hipMemcpyDeviceToDevice, c.st));
 }
 
@@ -849,6 +932,7 @@ void apply_A64_multi(const Ctx& c, const double* x, double* y, int nk) {
   a.rp = L.rpA;
   a.ci = L.ciA;
   a.blk = c.D.val64;
+  a.bid = c.D.bid64;
   a.x = x;
   a.out = y;
   ProfScope ps(c.D, L, c.st, K_A64);
@@ -912,6 +996,7 @@ int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int n
       rr[q] = D.hbscal[slot(q, RR)];
       if (!std::isfinite(rr[q])) throw std::runtime_error("CG breakdown (non-finite residual)");
       if (rr[q] <= rtol * rtol * bb[q]) done[q] = 1;
+      else if (!(D.hbscal[slot(q, RZ)] > 0.0) || !(D.hbscal[slot(q, AL)] > 0.0)) done[q] = 2;   // breakdown
       else more = true;
     }
     if (!more) break;
@@ -927,9 +1012,9 @@ int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int n
   bool all_conv = true;
   for (int q = 0; q < nk; ++q) {
     HIPCHK(hipMemcpyAsync(x[q], D.bx + q * N, N * 8, hipMemcpyDeviceToDevice, c.st));
-    all_conv = all_conv && done[q];
+    all_conv = all_conv && done[q] == 1;
     if (infos) {
-      finish_info(c, b[q], x[q], bb[q], hist[q], iters[q], done[q] != 0,
+      finish_info(c, b[q], x[q], bb[q], hist[q], iters[q], done[q] == 1,
                   bb[q] > 0 ? std::sqrt(std::fabs(rr[q]) / bb[q]) : 0.0, vcycles, &infos[q]);
     }
   }
@@ -937,7 +1022,7 @@ int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int n
   return all_conv ? LDGMG_OK : LDGMG_ENOCONV;
 }
 
-template <typename T>
+template <typename T, typename TS>
 void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, void* out) {
   DevLevel& L = c.D.L[l];
   const int nl = static_cast<int>(c.D.L.size());
@@ -959,13 +1044,13 @@ void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, v
     case LDGMG_OP_APPLY_S:
     case LDGMG_OP_APPLY_ST:
       if (bottom) throw std::invalid_argument("no smoother on the bottom level");
-      apply_S<T>(c.D, L, op == LDGMG_OP_APPLY_ST, a, nullptr, o, 1.0, 0.0, c.st);
+      apply_S<TS>(c.D, L, op == LDGMG_OP_APPLY_ST, a, nullptr, o, 1.0, 0.0, c.st);
       return;
     case LDGMG_OP_SMOOTH_FWD:
     case LDGMG_OP_SMOOTH_REV: {
       if (bottom) throw std::invalid_argument("no smoother on the bottom level");
       HIPCHK(hipMemcpyAsync(o, a, static_cast<size_t>(L.N) * sizeof(Vd), hipMemcpyDeviceToDevice, c.st));
-      Vd* res = smooth_step<T>(c, L, o, b, op == LDGMG_OP_SMOOTH_FWD, false);
+      Vd* res = smooth_step<T, TS>(c, L, o, b, op == LDGMG_OP_SMOOTH_FWD, false);
       if (res != o)
         HIPCHK(hipMemcpyAsync(o, res, static_cast<size_t>(L.N) * sizeof(Vd), hipMemcpyDeviceToDevice, c.st));
       return;
@@ -1061,6 +1146,7 @@ int ldgmg_problem_default(ldgmg_problem* p) {
   p->precision = LDGMG_FP32;
   p->nthreads = 0;
   p->hbm_budget = 0;
+  p->storage = LDGMG_STORE_AUTO;
   return LDGMG_OK;
 }
 
@@ -1131,6 +1217,26 @@ int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes) {
   return guarded([&] {
     if (!h || !h->host || !bytes) throw std::invalid_argument("null argument");
     *bytes = h->dev ? h->dev->bytes : 0;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_level_storage(ldgmg_handle h, int level, int* pool_A, int* pool_S) {
+  return guarded([&] {
+    need_dev(h);
+    check_level(h, level);
+    const HostLevel& H = h->host->levels[level];
+    const DevLevel& D = h->dev->L[level];
+    if (pool_A) *pool_A = D.bidA ? H.A.pool.size() : 0;
+    if (pool_S) *pool_S = D.bidS ? H.S.pool.size() : 0;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_upload_bytes(ldgmg_handle h, size_t* bytes) {
+  return guarded([&] {
+    if (!h || !h->host || !bytes) throw std::invalid_argument("null argument");
+    *bytes = estimate_from_host(*h->host, h->host->prob.precision);
     return LDGMG_OK;
   });
 }
@@ -1282,8 +1388,9 @@ int ldgmg_level_op(ldgmg_handle h, int level, int op, const void* in1, const voi
       apply_A64(c, static_cast<const double*>(in1), static_cast<double*>(out));
       return LDGMG_OK;
     }
-    if (h->dev->prec == LDGMG_FP64) level_op_t<double>(c, level, op, in1, in2, out);
-    else level_op_t<float>(c, level, op, in1, in2, out);
+    if (h->dev->prec == LDGMG_FP64) level_op_t<double, double>(c, level, op, in1, in2, out);
+    else if (h->dev->prec == LDGMG_BF16S) level_op_t<float, bf16s>(c, level, op, in1, in2, out);
+    else level_op_t<float, float>(c, level, op, in1, in2, out);
     return LDGMG_OK;
   });
 }

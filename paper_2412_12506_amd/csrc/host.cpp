@@ -322,7 +322,11 @@ void validate_problem(const ldgmg_problem& p) {
   if (p.sai_level < 0 || p.sai_level > 2) throw std::invalid_argument("sai_level must be 0..2");
   if (p.order < 0 || p.order > 3) throw std::invalid_argument("unknown order");
   if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 > 16 || p.nu2 > 16) throw std::invalid_argument("nu out of range");
-  if (p.precision != LDGMG_FP64 && p.precision != LDGMG_FP32) throw std::invalid_argument("unknown precision");
+  if (p.precision != LDGMG_FP64 && p.precision != LDGMG_FP32 && p.precision != LDGMG_BF16S)
+    throw std::invalid_argument("unknown precision");
+  if (p.storage < LDGMG_STORE_AUTO || p.storage > LDGMG_STORE_POOLED) throw std::invalid_argument("unknown storage");
+  if (p.precision == LDGMG_BF16S && p.smoother != LDGMG_SMOOTH_SAI)
+    throw std::invalid_argument("BF16 smoother storage is for the SAI smoothers only");
   if (!(p.tau0 > 0) || !(p.cp >= 0)) throw std::invalid_argument("penalty constants must be positive");
   for (int k = 0; k < p.dim; ++k) {
     const int a = p.bc[2 * k], b = p.bc[2 * k + 1];

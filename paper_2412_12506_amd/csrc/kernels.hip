@@ -17,11 +17,52 @@ template <> struct VecT<float, 1> { using type = float; };
 template <> struct VecT<double, 2> { using type = double2; };
 template <> struct VecT<double, 1> { using type = double; };
 
+// packed BF16 entries (two per 32-bit word, the lower half first)
+struct bf16x2 {
+  unsigned int w;
+};
+struct bf16x4 {
+  uint2 w;
+};
+struct bf16x8 {
+  uint4 w;
+};
+template <> struct VecT<bf16s, 8> { using type = bf16x8; };
+template <> struct VecT<bf16s, 4> { using type = bf16x4; };
+template <> struct VecT<bf16s, 2> { using type = bf16x2; };
+template <> struct VecT<bf16s, 1> { using type = bf16s; };
+
+__device__ __forceinline__ float half_of(unsigned int w, int h) {
+  return __uint_as_float(h ? (w & 0xffff0000u) : (w << 16));
+}
+
 template <typename T> __device__ __forceinline__ T elem(const T& a, int) { return a; }
 __device__ __forceinline__ float elem(const float4& a, int v) {
   return v == 0 ? a.x : v == 1 ? a.y : v == 2 ? a.z : a.w;
 }
 __device__ __forceinline__ double elem(const double2& a, int v) { return v == 0 ? a.x : a.y; }
+__device__ __forceinline__ float elem(const bf16s& a, int) { return __uint_as_float(static_cast<unsigned int>(a.u) << 16); }
+__device__ __forceinline__ float elem(const bf16x2& a, int v) { return half_of(a.w, v); }
+__device__ __forceinline__ float elem(const bf16x4& a, int v) { return half_of(v < 2 ? a.w.x : a.w.y, v & 1); }
+__device__ __forceinline__ float elem(const bf16x8& a, int v) {
+  const unsigned int w = v < 2 ? a.w.x : v < 4 ? a.w.y : v < 6 ? a.w.z : a.w.w;
+  return half_of(w, v & 1);
+}
+
+// stored entry -> arithmetic value (exact)
+__device__ __forceinline__ float widen(float a) { return a; }
+__device__ __forceinline__ double widen(double a) { return a; }
+__device__ __forceinline__ float widen(bf16s a) { return elem(a, 0); }
+
+// FP64 pool value -> stored entry: round to nearest even to FP32, and for BF16
+// once more from FP32 to the upper 16 bits
+template <typename T> __device__ __forceinline__ T narrow(double v) { return static_cast<T>(v); }
+template <> __device__ __forceinline__ bf16s narrow<bf16s>(double v) {
+  const unsigned int u = __float_as_uint(static_cast<float>(v));
+  bf16s b;
+  b.u = static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  return b;
+}
 
 template <typename VT> __device__ __forceinline__ VT vzero() { return VT{}; }
 
@@ -52,14 +93,19 @@ constexpr int kThreads = 64 * kWaves;
 //   MODE 1: out_i = x_i + omega Dinv_i (z_i - (M x)_i)  (fused block-inverse smoothing;
 //           out may alias x when the rows of one launch are not coupled)
 // rows (optional) lists the block rows to process (nrows entries).
+// POOL: blk holds the distinct blocks only and bid[slot] names the block of a
+// slot (pooled storage); otherwise slot s owns block s.  dbid (optional) names
+// the block inverse of a row in the same way.
 // ---------------------------------------------------------------------------
-template <typename TM, typename T, int BS, int MODE>
+template <typename TM, typename T, int BS, int MODE, bool POOL>
 __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __restrict__ rows,
                                                       const int* __restrict__ rp,
                                                       const int* __restrict__ ci,
+                                                      const int* __restrict__ bid,
                                                       const TM* __restrict__ blk, const T* x,
                                                       const T* z, T* out, T alpha, T beta,
-                                                      const TM* __restrict__ dinv, T omega) {
+                                                      const TM* __restrict__ dinv,
+                                                      const int* __restrict__ dbid, T omega) {
   using C = BlkCfg<TM, BS>;
   constexpr int V = C::V, G = C::G, NV = C::NV;
   constexpr int CH = BS < 8 ? BS : 8;   // slots whose column index and x entry are fetched together
@@ -91,8 +137,11 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
     // then fetches its entries of those CH neighbour vectors, so the block
     // loads below wait for one memory latency only
     const bool own = r < CH && k0 + r < cnt;
-    const int cl = ci[own ? s0 + k0 + r : 0];
+    const int so = own ? s0 + k0 + r : 0;
+    const int cl = ci[so];
     const int cidx = own ? cl : -1;
+    int pid = 0;                            // pooled: block of slot k0 + r (slot 0's if none)
+    if constexpr (POOL) pid = bid[so];
     T xv[CH];
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
@@ -103,8 +152,14 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
       if (k0 + t >= mc) break;                // wave-uniform
-      const int sl = k0 + t < cnt ? s0 + k0 + t : 0;
-      const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(sl) * (BS * BS)) + r;
+      size_t boff;
+      if constexpr (POOL) {
+        boff = static_cast<size_t>(group_bcast<int, BS>(pid, g, t)) * (BS * BS);
+      } else {
+        const int sl = k0 + t < cnt ? s0 + k0 + t : 0;
+        boff = static_cast<size_t>(sl) * (BS * BS);
+      }
+      const VT* bp = reinterpret_cast<const VT*>(blk + boff) + r;
       VT a[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) a[q] = bp[q * BS];
@@ -127,7 +182,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
     const T zo = z[o];
     const T res = active ? zo - sum : T(0);
     VT d[NV];
-    const VT* dp = reinterpret_cast<const VT*>(dinv + static_cast<size_t>(row) * (BS * BS)) + r;
+    const int drow = dbid ? dbid[row] : row;
+    const VT* dp = reinterpret_cast<const VT*>(dinv + static_cast<size_t>(drow) * (BS * BS)) + r;
 #pragma unroll
     for (int q = 0; q < NV; ++q) d[q] = dp[q * BS];
     T y[NA];
@@ -167,6 +223,7 @@ template <typename TM, typename T, int BS>
 __global__ __launch_bounds__(kThreads) void k_bsr_fwd_multi(int nrows, const int* __restrict__ rows,
                                                             const int* __restrict__ rp,
                                                             const int* __restrict__ ci,
+                                                            const int* __restrict__ bid,
                                                             const TM* __restrict__ blk, const T* x,
                                                             const T* z, T* out, long long stride, int nk,
                                                             T alpha, T beta) {
@@ -207,7 +264,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd_multi(int nrows, const int
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(sl) * (BS * BS)) + r;
+    const int pb = bid ? bid[sl] : sl;          // pooled storage: block of the slot
+    const VT* bp = reinterpret_cast<const VT*>(blk + static_cast<size_t>(pb) * (BS * BS)) + r;
     VT a[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) a[q] = bp[q * BS];
@@ -345,10 +403,10 @@ __global__ __launch_bounds__(256) void k_bsr_generic(int nrows, int bs, const in
     const T* xj = x + static_cast<size_t>(j) * bs;
     if (tpos) {   // (M_ji)^T[r][c] = M_ji[c][r], stored at r * bs + c
       const TM* b = blk + static_cast<size_t>(tpos[s]) * bb + static_cast<size_t>(r) * bs;
-      for (int c = 0; c < bs; ++c) acc += static_cast<T>(b[c]) * xj[c];
+      for (int c = 0; c < bs; ++c) acc += static_cast<T>(widen(b[c])) * xj[c];
     } else {
       const TM* b = blk + static_cast<size_t>(s) * bb + r;
-      for (int c = 0; c < bs; ++c) acc += static_cast<T>(b[static_cast<size_t>(c) * bs]) * xj[c];
+      for (int c = 0; c < bs; ++c) acc += static_cast<T>(widen(b[static_cast<size_t>(c) * bs])) * xj[c];
     }
   }
   const size_t o = static_cast<size_t>(row) * bs + r;
@@ -369,7 +427,7 @@ __global__ void k_expand(long long nslots, int bs, int V, const int* __restrict_
     const double v = transpose ? pool[ids[s] * bb + static_cast<long long>(c) * bs + r]
                                : pool[ids[s] * bb + e];
     const size_t dst = (static_cast<size_t>(c / V) * bs + r) * V + (c % V);
-    out[s * bb + dst] = static_cast<T>(v);
+    out[s * bb + dst] = narrow<T>(v);
   }
 }
 
@@ -700,12 +758,22 @@ void launch_fwd_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
   const long long waves = (a.nrows + G - 1) / G;
   const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
   if (blocks == 0) return;
-  if (a.dinv)
-    k_bsr_fwd<TM, T, BS, 1><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
-                                                     a.alpha, a.beta, a.dinv, a.omega);
+  if (a.dinv && a.bid)
+    k_bsr_fwd<TM, T, BS, 1, true><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.bid, a.blk, a.x,
+                                                               a.z, a.out, a.alpha, a.beta, a.dinv, a.dbid,
+                                                               a.omega);
+  else if (a.dinv)
+    k_bsr_fwd<TM, T, BS, 1, false><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, nullptr, a.blk,
+                                                                a.x, a.z, a.out, a.alpha, a.beta, a.dinv,
+                                                                a.dbid, a.omega);
+  else if (a.bid)
+    k_bsr_fwd<TM, T, BS, 0, true><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.bid, a.blk, a.x,
+                                                               a.z, a.out, a.alpha, a.beta, nullptr, nullptr,
+                                                               T(0));
   else
-    k_bsr_fwd<TM, T, BS, 0><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
-                                                     a.alpha, a.beta, nullptr, T(0));
+    k_bsr_fwd<TM, T, BS, 0, false><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, nullptr, a.blk,
+                                                                a.x, a.z, a.out, a.alpha, a.beta, nullptr,
+                                                                nullptr, T(0));
   check_launch("bsr_fwd");
 }
 
@@ -726,8 +794,8 @@ void launch_fwd_multi_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipS
   const long long waves = (a.nrows + G - 1) / G;
   const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
   if (blocks == 0) return;
-  k_bsr_fwd_multi<TM, T, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.blk, a.x, a.z, a.out,
-                                                          stride, nk, a.alpha, a.beta);
+  k_bsr_fwd_multi<TM, T, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.bid, a.blk, a.x, a.z,
+                                                          a.out, stride, nk, a.alpha, a.beta);
   check_launch("bsr_fwd_multi");
 }
 
@@ -759,6 +827,7 @@ void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st) {
       break;
   }
   if (a.dinv) throw std::runtime_error("fused smoothing needs a block size <= 64");
+  if (a.bid) throw std::runtime_error("pooled storage needs a block size with a wave-mapped kernel");
   const long long n = static_cast<long long>(a.nrows) * a.bs;
   if (n == 0) return;
   k_bsr_generic<TM, T><<<static_cast<int>((n + 255) / 256), 256, 0, st>>>(a.nrows, a.bs, a.rows, a.rp, a.ci,
@@ -792,6 +861,7 @@ void bsr_forward_multi(const BsrArgs<TM, T>& a, long long stride, int nk, hipStr
 
 template <typename TM, typename T>
 void bsr_transposed(const BsrArgs<TM, T>& a, hipStream_t st) {
+  if (a.bid) throw std::runtime_error("pooled storage: transposed applies use the transposed copy");
   switch (a.bs) {
 #define CASE(B) \
   case B:       \
@@ -915,6 +985,10 @@ template void bsr_transposed<float, double>(const BsrArgs<float, double>&, hipSt
 template void bsr_forward_multi<float, double>(const BsrArgs<float, double>&, long long, int, hipStream_t);
 template void bsr_forward_multi<double, double>(const BsrArgs<double, double>&, long long, int, hipStream_t);
 template void bsr_transposed<double, double>(const BsrArgs<double, double>&, hipStream_t);
+template void bsr_forward<bf16s, double>(const BsrArgs<bf16s, double>&, hipStream_t);
+template void bsr_transposed<bf16s, double>(const BsrArgs<bf16s, double>&, hipStream_t);
+template void bsr_forward_multi<bf16s, double>(const BsrArgs<bf16s, double>&, long long, int, hipStream_t);
+template void expand_blocks<bf16s>(long long, int, const int*, const double*, bf16s*, bool, hipStream_t);
 template void expand_blocks<float>(long long, int, const int*, const double*, float*, bool, hipStream_t);
 template void expand_blocks<double>(long long, int, const int*, const double*, double*, bool, hipStream_t);
 template void restrict_op<double>(int, int, int, int, int, const double*, const double*, const double*, double*,

@@ -19,9 +19,18 @@
 
 namespace ldgmg {
 
+// BF16 storage of a block entry: the upper 16 bits of the FP32 value (rounded
+// to nearest even from FP32), widened back to FP32 exactly by a shift.
+struct bf16s {
+  uint16_t u;
+};
+
+// V: entries per vector load (16 bytes where bs allows it)
 template <typename T, int BS>
 struct BlkCfg {
-  static constexpr int V = sizeof(T) == 4 ? (BS % 4 == 0 ? 4 : 1) : (BS % 2 == 0 ? 2 : 1);
+  static constexpr int V = sizeof(T) == 8   ? (BS % 2 == 0 ? 2 : 1)
+                           : sizeof(T) == 4 ? (BS % 4 == 0 ? 4 : 1)
+                                            : (BS % 8 == 0 ? 8 : BS % 4 == 0 ? 4 : BS % 2 == 0 ? 2 : 1);
   static constexpr int G = 64 / BS;      // block rows per wavefront
   static constexpr int NV = BS / V;      // vector loads per lane per block
 };

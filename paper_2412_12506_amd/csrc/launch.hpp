@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "kernels.hpp"   // storage types (bf16s)
+
 namespace ldgmg {
 
 constexpr int kRedBlocks = 1024;   // partial sums per dot product
@@ -19,8 +21,9 @@ bool fast_bs(int bs);
 // elements per vector load in the device block layout for block size bs
 inline int device_vec_width(int bs, int elem_bytes) {
   if (!fast_bs(bs)) return 1;
+  if (elem_bytes == 8) return bs % 2 == 0 ? 2 : 1;
   if (elem_bytes == 4) return bs % 4 == 0 ? 4 : 1;
-  return bs % 2 == 0 ? 2 : 1;
+  return bs % 8 == 0 ? 8 : bs % 4 == 0 ? 4 : bs % 2 == 0 ? 2 : 1;
 }
 
 // TM: element type of the stored blocks; T: vectors and arithmetic
@@ -32,12 +35,14 @@ struct BsrArgs {
   const int* rp = nullptr;    // row pointer [nblockrows + 1]
   const int* ci = nullptr;    // block columns [nnzb]
   const int* tpos = nullptr;  // transposed kernel: slot of (j,i) for slot (i,j)
-  const TM* blk = nullptr;    // blocks [nnzb][bs*bs], device layout
+  const int* bid = nullptr;   // pooled storage: block of each slot [nnzb] (null: slot s owns block s)
+  const TM* blk = nullptr;    // blocks [nnzb or pool size][bs*bs], device layout
   const T* x = nullptr;       // input vector
   const T* z = nullptr;       // added vector (MODE 0) / right-hand side (fused smoothing)
   T* out = nullptr;
   T alpha = T(1), beta = T(0);
   const TM* dinv = nullptr;   // fused smoothing: block inverses indexed by block row
+  const int* dbid = nullptr;  // pooled block inverses: block of each row (null: row r owns block r)
   T omega = T(1);
 };
 

@@ -24,7 +24,8 @@ BASIS = {"legendre": 0, "gl_nodal": 1}
 BC = {"D": 0, "N": 1, "P": 2}
 SMOOTHER = {"jacobi": 0, "gs": 1, "sai": 2}
 ORDER = {"OO": 0, "OI": 1, "IO": 2, "II": 3}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16s": 2}
+STORAGE = {"auto": 0, "expanded": 1, "pooled": 2}
 KRYLOV = {"cg": 0, "gmres": 1}
 OP = {"residual": 0, "apply_a": 1, "apply_s": 2, "apply_st": 3, "smooth_fwd": 4,
       "smooth_rev": 5, "restrict": 6, "prolong_add": 7, "bottom": 8, "apply_a64": 9}
@@ -37,7 +38,8 @@ class Problem(C.Structure):
                 ("mu", C.POINTER(C.c_double)), ("tau0", C.c_double), ("cp", C.c_double),
                 ("smoother", C.c_int), ("sai_level", C.c_int), ("order", C.c_int),
                 ("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("zeta", C.c_double),
-                ("precision", C.c_int), ("nthreads", C.c_int), ("hbm_budget", C.c_size_t)]
+                ("precision", C.c_int), ("nthreads", C.c_int), ("hbm_budget", C.c_size_t),
+                ("storage", C.c_int)]
 
 
 class Info(C.Structure):
@@ -58,7 +60,7 @@ _lib = None
 SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
-           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_device_bytes", "ldgmg_destroy",
+           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -94,6 +96,8 @@ def lib():
     L.ldgmg_profile_read.argtypes = [H, C.c_int, ip, dp]
     L.ldgmg_unload.argtypes = [H]
     L.ldgmg_device_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
+    L.ldgmg_upload_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
+    L.ldgmg_level_storage.argtypes = [H, C.c_int, ip, ip]
     L.ldgmg_destroy.argtypes = [H]
     L.ldgmg_last_error.argtypes = []
     L.ldgmg_last_error.restype = C.c_char_p
@@ -135,7 +139,7 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
                  gamma: int = 1, bc=None, mu=None, tau0: float = 1.0, cp: float = 0.1,
                  smoother: str = "sai", sai_level: int = 1, order: str = "OI", nu1: int = 3,
                  nu2: int = 3, omega: float = 0.0, zeta: float = 0.0, precision: str = "fp32",
-                 nthreads: int = 0, hbm_budget: int = 0):
+                 nthreads: int = 0, hbm_budget: int = 0, storage: str = "auto"):
     """Problem struct plus the numpy array that backs `mu` (keep both alive)."""
     pr = ldgmg_problem_default()
     pr.dim, pr.n, pr.p = dim, n, p
@@ -160,6 +164,7 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
     pr.precision = PRECISION[precision]
     pr.nthreads = nthreads
     pr.hbm_budget = hbm_budget
+    pr.storage = STORAGE[storage]
     return pr, mu_arr
 
 
@@ -318,6 +323,18 @@ def ldgmg_device_bytes(h: int) -> int:
     return out.value
 
 
+def ldgmg_upload_bytes(h: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().ldgmg_upload_bytes(h, C.byref(out)))
+    return out.value
+
+
+def ldgmg_level_storage(h: int, level: int) -> dict:
+    a, b = C.c_int(0), C.c_int(0)
+    _check(lib().ldgmg_level_storage(h, level, C.byref(a), C.byref(b)))
+    return {"pool_A": a.value, "pool_S": b.value}
+
+
 def ldgmg_destroy(h: int):
     if h:
         lib().ldgmg_destroy(h)
@@ -353,6 +370,10 @@ class Solver:
     @property
     def device_bytes(self) -> int:
         return ldgmg_device_bytes(self.handle)
+
+    @property
+    def upload_bytes(self) -> int:
+        return ldgmg_upload_bytes(self.handle)
 
     def vcycle(self, b, x, stream=None):
         ldgmg_vcycle(self.handle, b, x, stream)

@@ -2,8 +2,9 @@
 
 Requests (one Poisson or elliptic-interface problem each: dim, n, p, viscosity
 contrast, right-hand-side seed) arrive over time.  Each request is solved to
-the same relative residual by CG preconditioned with one V-cycle (FP32 block
-storage, FP64 vectors and Krylov), exactly as a lone ldgmg_solve would.
+the same relative residual by CG preconditioned with one V-cycle (FP32
+operator blocks, BF16 SAI blocks by default, FP64 vectors and Krylov), exactly
+as a lone ldgmg_solve would.
 
 Hierarchy cache, two tiers, keyed by the problem:
   * host tier: the hierarchy built by ldgmg_setup_host (block pools, indices,
@@ -11,10 +12,17 @@ Hierarchy cache, two tiers, keyed by the problem:
     distinct block is stored once.
   * device tier (HBM): hierarchies uploaded with ldgmg_upload.  A hierarchy is
     admitted only while the device bytes of all resident hierarchies stay
-    within the budget (ldgmg_estimate_bytes plus the batched-solve workspace
-    before the upload, the measured ldgmg_device_bytes after it); idle ones are
+    within the budget (ldgmg_upload_bytes of the built host tier plus the
+    batched-solve workspace, the measured ldgmg_device_bytes once it is larger);
+    idle ones are
     evicted least recently used with ldgmg_unload, keeping their host tier.
     Requests whose hierarchy does not fit wait until a running batch ends.
+
+Robustness: when a batch's CG solves with the SAI V-cycle do not converge (the
+library stops CG at once when the preconditioner shows it is not positive
+definite), the hierarchy of that problem is rebuilt with the coloured
+Gauss-Seidel smoother (the paper's second-ranked smoother) and the affected
+requests are queued again at the front; later requests of the key use it.
 
 Scheduling: several workers, each with its own HIP stream, take the key whose
 oldest waiting request is oldest among the keys not in use, and solve up to 8
@@ -49,6 +57,8 @@ def problem_kwargs(key, precision="fp32", smoother="sai"):
     from ldg_inputs import mu_box
     dim, n, p, contrast = key
     mu = None if contrast == 1.0 else mu_box(dim, n, contrast)
+    if smoother != "sai" and precision == "bf16s":     # BF16 storage is for the SAI matrices
+        precision = "fp32"
     return dict(dim=dim, n=n, p=p, mu=mu, smoother=smoother, sai_level=1, order="OI",
                 precision=precision)
 
@@ -72,12 +82,14 @@ class Pending:
 @dataclass
 class Entry:
     key: tuple
+    smoother: str = "sai"
     solver: Optional["L.Solver"] = None      # host tier (None until built)
     building: bool = False
     resident: bool = False                   # device tier
     bytes: int = 0
     busy: bool = False
     uploads: int = 0
+    fallbacks: int = 0
 
 
 @dataclass
@@ -95,6 +107,7 @@ class Result:
     upload_s: float = 0.0
     x: Optional[np.ndarray] = None
     error: str = ""
+    smoother: str = "sai"
 
     @property
     def latency(self):
@@ -102,7 +115,7 @@ class Result:
 
 
 class ServingEngine:
-    def __init__(self, hbm_budget: int, workers: int = 4, max_batch: int = 8, precision: str = "fp32",
+    def __init__(self, hbm_budget: int, workers: int = 4, max_batch: int = 8, precision: str = "bf16s",
                  smoother: str = "sai", rtol: float = 1e-10, maxit: int = 200, keep_solutions: bool = False,
                  setup_threads: int = 0):
         import torch
@@ -124,6 +137,7 @@ class ServingEngine:
         self.errors: List[str] = []
         self.evictions: List[tuple] = []     # (key, time)
         self.admissions: List[tuple] = []    # (key, time)
+        self.fallback_keys: List[tuple] = []
         self.t0 = time.perf_counter()
 
     def _now(self):
@@ -133,13 +147,15 @@ class ServingEngine:
     def _entry(self, key) -> Entry:
         e = self.entries.get(key)
         if e is None:
-            e = self.entries[key] = Entry(key)
+            e = self.entries[key] = Entry(key, smoother=self.smoother)
         return e
 
     def _build_host(self, key) -> float:
         """Host setup of `key` (outside the lock); returns seconds."""
         ts = time.perf_counter()
-        kw = problem_kwargs(key, self.precision, self.smoother)
+        with self.cv:
+            smoother = self._entry(key).smoother
+        kw = problem_kwargs(key, self.precision, smoother)
         solver = L.Solver(host_only=True, nthreads=self.setup_threads, **kw)
         with self.cv:
             e = self._entry(key)
@@ -162,9 +178,14 @@ class ServingEngine:
 
     # -- device tier -------------------------------------------------------------
     def _need_bytes(self, key) -> int:
-        pr, _ = L.make_problem(**problem_kwargs(key, self.precision, self.smoother))
+        """Device bytes of the key's hierarchy with the batch workspace: exact
+        from the host tier when it is built, else the expanded-storage bound."""
         dim, n, p, _c = key
         ndofs = n ** dim * (p + 1) ** dim
+        e = self.entries.get(key)
+        if e is not None and e.solver is not None:
+            return e.solver.upload_bytes + batch_workspace_bytes(ndofs, dim)
+        pr, _ = L.make_problem(**problem_kwargs(key, self.precision, self.smoother))
         return L.ldgmg_estimate_bytes(pr) + batch_workspace_bytes(ndofs, dim)
 
     def _reserve(self, e: Entry, need: int) -> bool:
@@ -254,7 +275,19 @@ class ServingEngine:
                     upload_s = time.perf_counter() - tu
                     e.resident = True
                     e.uploads += 1
-                self._solve_batch(e, batch, stream, setup_s, upload_s)
+                failed = self._solve_batch(e, batch, stream, setup_s, upload_s)
+                if failed:                         # SAI did not converge: switch the key to GS
+                    with self.cv:
+                        old = e.solver
+                        old.unload()
+                        e.resident = False
+                        self.used -= e.bytes
+                        e.bytes = 0
+                        e.solver, e.smoother = None, "gs"
+                        e.fallbacks += 1
+                        self.fallback_keys.append(key)
+                        self.waiting[key].extendleft(reversed(failed))
+                    old.close()
             except Exception as ex:  # keep serving; report the failure
                 with self.cv:
                     self._reject(key, batch, str(ex))
@@ -265,6 +298,8 @@ class ServingEngine:
                     self.cv.notify_all()
 
     def _solve_batch(self, e: Entry, batch, stream, setup_s, upload_s):
+        """Solve `batch` on e's hierarchy and record the results; returns the
+        requests to retry (not converged with the SAI smoother)."""
         from ldg_inputs import rhs_normal
         torch = self.torch
         n = e.solver.ndofs
@@ -277,15 +312,21 @@ class ServingEngine:
         stream.synchronize()
         end = self._now()
         actual = e.solver.device_bytes
+        failed = []
         with self.cv:
             if actual > e.bytes:           # measured bytes replace the estimate
                 self.used += actual - e.bytes
                 e.bytes = actual
                 self.peak_used = max(self.peak_used, self.used)
             for r, info, x in zip(batch, infos, xs):
+                if not info["converged"] and e.smoother == "sai":
+                    failed.append(r)
+                    continue
                 self.results.append(Result(r.rid, e.key, r.arrival, start, end, info["iters"],
                                            info["converged"], info["rel_res_true"], len(batch), setup_s,
-                                           upload_s, x.cpu().numpy() if self.keep else None))
+                                           upload_s, x.cpu().numpy() if self.keep else None,
+                                           smoother=e.smoother))
+        return failed
 
     def run(self, requests, time_scale: float = 1.0) -> List[Result]:
         """Replay `requests` (objects with rid, arrival in seconds, dim, n, p,

@@ -40,3 +40,38 @@ def smoother_matrix(vc, level):
 def rel_err_bound(y, ref, absref):
     """max |y - ref| / max |absref| (absref = |A||x| style magnitude)."""
     return float(np.max(np.abs(y - ref)) / max(np.max(np.abs(absref)), 1e-300))
+
+
+def round_fp32(M):
+    """Entries of a sparse matrix rounded to FP32 (nearest even), kept in FP64."""
+    M = sp.csr_matrix(M, copy=True)
+    M.data = M.data.astype(np.float32).astype(np.float64)
+    return M
+
+
+def round_bf16(M):
+    """Entries rounded as the library stores BF16 blocks: to nearest even in
+    FP32, then to nearest even on the upper 16 bits of the FP32 word."""
+    M = sp.csr_matrix(M, copy=True)
+    u = M.data.astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    M.data = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return M
+
+
+def stored_vcycle(vc, prec):
+    """The oracle's V-cycle with its matrices rounded as a precision mode stores
+    them ("bf16s": operators in FP32, SAI matrices in BF16; the bottom
+    pseudo-inverse stays FP64).  Arithmetic stays FP64, as in the library."""
+    from oracle.vcycle import MGLevel, SmootherData, VCycle
+    assert prec == "bf16s"
+    levels = []
+    for lv in vc.levels:
+        A = round_fp32(lv.A)
+        if lv.sm is None:
+            levels.append(MGLevel(A, lv.bs, None, None, pinv=lv.pinv))
+            continue
+        assert lv.sm.kind == "sai"
+        sd = SmootherData("sai", B=round_bf16(lv.sm.B))
+        levels.append(MGLevel(A, lv.bs, lv.I, sd))
+    return VCycle(levels, vc.order, vc.nu1, vc.nu2)

@@ -20,7 +20,11 @@ CASES = [
 ]
 
 
-@pytest.fixture(scope="module", params=[(c, pr) for c in CASES for pr in ("fp64", "fp32")],
+def _precisions(case):
+    return ("fp64", "fp32", "bf16s") if case["smoother"] == "sai" else ("fp64", "fp32")
+
+
+@pytest.fixture(scope="module", params=[(c, pr) for c in CASES for pr in _precisions(c)],
                 ids=lambda cp: f"{cp[0]['id']}-{cp[1]}")
 def built(request):
     from paper_2412_12506_amd import ldgmg as L

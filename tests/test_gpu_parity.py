@@ -9,6 +9,10 @@ Tolerances (derived from the arithmetic, not tuned):
   * FP32 block storage (vectors and accumulation stay FP64): the only new
     error is the rounding of each stored entry, |fl(a) - a| <= u32 |a|, so
     |y - y_ref| <= 4 u32 |A||x| (u32 = 2^-24, with slack for the FP64 sums).
+  * BF16 SAI storage ("bf16s": FP32 operators, BF16 B): the SAI applies, the
+    smoothing steps and the V-cycle are compared with the oracle's own code
+    run on its matrices rounded exactly as stored (tests/gpu_common), so the
+    FP32 bounds above apply; the solve is compared with the unrounded oracle.
   * smoothing steps: the first-order bound |dx| <= u |S| (|b| + |A||x|) of
     one step (u = unit roundoff of the stored entries; once per colour for
     Gauss-Seidel), with a factor 64 of slack for the FP64 sums.
@@ -28,7 +32,7 @@ import pytest
 import scipy.sparse as sp
 
 from ldg_inputs import rhs_normal, stokes_body_force
-from tests.gpu_common import lib_kwargs, oracle_build, smoother_matrix
+from tests.gpu_common import lib_kwargs, oracle_build, smoother_matrix, stored_vcycle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -54,15 +58,33 @@ def _dev():
     return torch.device("cuda:0")
 
 
+def _variants(case):
+    """(precision, device storage) pairs: every kernel instantiation the case reaches."""
+    v = [("fp64", "auto"), ("fp32", "expanded"), ("fp32", "pooled")]
+    if case["smoother"] == "sai":
+        v += [("bf16s", "expanded"), ("bf16s", "pooled")]
+    return v
+
+
+_ORACLE = {}
+
+
+def _oracle(case):
+    if case["id"] not in _ORACLE:
+        _ORACLE.clear()                    # cases come in order: keep one
+        _ORACLE[case["id"]] = oracle_build(case)
+    return _ORACLE[case["id"]]
+
+
 @pytest.fixture(scope="module",
-                params=[(c, pr) for c in CASES for pr in ("fp64", "fp32")],
-                ids=lambda cp: f"{cp[0]['id']}-{cp[1]}")
+                params=[(c, pr, st) for c in CASES for pr, st in _variants(c)],
+                ids=lambda cp: f"{cp[0]['id']}-{cp[1]}-{cp[2]}")
 def built(request):
     from paper_2412_12506_amd import ldgmg as L
-    case, prec = request.param
-    print(f"\n[case {case['id']} {prec}]", flush=True)
-    s = L.Solver(**lib_kwargs(case, prec))
-    lv, vc = oracle_build(case)
+    case, prec, storage = request.param
+    print(f"\n[case {case['id']} {prec} {storage}]", flush=True)
+    s = L.Solver(storage=storage, **lib_kwargs(case, prec))
+    lv, vc = _oracle(case)
     yield case, prec, s, lv, vc
     s.close()
 
@@ -90,6 +112,7 @@ def _tol_op(prec, A):
 def test_level_operations(built):
     from paper_2412_12506_amd import ldgmg as L
     case, prec, s, lv, vc = built
+    vs = stored_vcycle(vc, prec) if prec == "bf16s" else vc    # references for S and smoothing
     rng = np.random.default_rng(1234)
     nl = len(lv)
     assert s.nlevels == nl
@@ -117,7 +140,7 @@ def test_level_operations(built):
             continue
         # smoother matrix forward / transposed (a2, a3).  Block inverses are
         # computed independently by both setups: they agree to ~kappa(A_ii) eps64.
-        S = smoother_matrix(vc, l)
+        S = smoother_matrix(vs, l)
         stol = _tol_op(prec, S)
         if vc.levels[l].sm.kind != "sai":
             kd = max(np.linalg.cond(D) for D in np.linalg.inv(vc.levels[l].sm.Dinv))
@@ -138,7 +161,7 @@ def test_level_operations(built):
         for op, fwd in (("smooth_fwd", True), ("smooth_rev", False)):
             L.ldgmg_level_op(s.handle, l, op, xt, bt, out)
             torch.cuda.synchronize()
-            ref = vc.smooth(vc.levels[l], x, b, fwd)
+            ref = vs.smooth(vs.levels[l], x, b, fwd)
             err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(mag)
             assert err <= 4 * ncol * u * 16, (l, op, err)
         # transfers (a5, a6)
@@ -183,7 +206,7 @@ def test_vcycle(built):
     xt = torch.empty_like(bt)
     L.ldgmg_vcycle(s.handle, bt, xt)
     torch.cuda.synchronize()
-    ref = vc.apply(b)
+    ref = (stored_vcycle(vc, prec) if prec == "bf16s" else vc).apply(b)
     err = np.linalg.norm(xt.cpu().numpy() - ref) / np.linalg.norm(ref)
     tol = (1e-10 if prec == "fp64" else 1e-5) + 100 * _kappa_bottom(vc) * EPS64
     assert err <= tol, (err, tol)

@@ -22,15 +22,15 @@ pytestmark = pytest.mark.gpu
 GIB = 1 << 30
 
 
-def _alone(results):
+def _alone(results, precision):
     from paper_2412_12506_amd import ldgmg as L
     from paper_2412_12506_amd.serving import problem_kwargs
     by_key = {}
     for r in results:
-        by_key.setdefault(r.key, []).append(r)
+        by_key.setdefault((r.key, r.smoother), []).append(r)
     worst = 0.0
-    for key, rs in by_key.items():
-        s = L.Solver(**problem_kwargs(key))
+    for (key, smoother), rs in by_key.items():
+        s = L.Solver(**problem_kwargs(key, precision, smoother))
         try:
             for r in rs:
                 b = torch.from_numpy(rhs_normal(s.ndofs, r.seed_used)).cuda()
@@ -70,7 +70,7 @@ def test_mix_equals_alone():
         assert all(r.rel_res_true <= 2e-10 for r in res)
         assert max(r.batch for r in res) >= 2          # requests were batched
         assert eng.peak_used <= eng.budget
-        worst = _alone(res)
+        worst = _alone(res, eng.precision)
         print(f"[serving mix] alone vs mix worst relative difference {worst:.2e}", flush=True)
     finally:
         eng.close()
@@ -82,6 +82,7 @@ def test_admission_waits_for_memory():
     small = [Request(10 + i, 0.001, "poisson", 2, 32, 2, 1.0, 950 + i) for i in range(3)]
     eng = ServingEngine(hbm_budget=1, workers=2, keep_solutions=True)
     ka, kb = problem_key(big[0]), problem_key(small[0])
+    eng.prebuild([ka, kb], threads=2)                  # exact device bytes from the host tier
     na, nb = eng._need_bytes(ka), eng._need_bytes(kb)
     eng.budget = max(na, nb) + min(na, nb) // 2       # one fits, not both
     try:
@@ -100,7 +101,7 @@ def test_admission_waits_for_memory():
         assert first[ky] >= x_end, (first, x_end)
         assert eng.evictions and eng.evictions[0][0] == kx
         print(f"\n[serving memory] admissions {eng.admissions} evictions {eng.evictions}", flush=True)
-        _alone(res)
+        _alone(res, eng.precision)
     finally:
         eng.close()
 
@@ -108,7 +109,7 @@ def test_admission_waits_for_memory():
 def test_refuses_problem_over_budget():
     from paper_2412_12506_amd.serving import ServingEngine
     reqs = [Request(0, 0.0, "poisson", 2, 16, 1, 1.0, 5), Request(1, 0.0, "poisson", 2, 16, 1, 1.0, 6)]
-    eng = ServingEngine(hbm_budget=1 << 20, workers=1)
+    eng = ServingEngine(hbm_budget=1 << 16, workers=1)
     try:
         res = eng.run(reqs)
         assert len(res) == 2 and all(r.error and not r.converged for r in res)

@@ -78,7 +78,9 @@ def test_invalid_problems_are_rejected():
     from paper_2412_12506_amd import ldgmg as L
     for bad in (dict(dim=4, n=8, p=2), dict(dim=2, n=8, p=0), dict(dim=2, n=1, p=2),
                 dict(dim=2, n=8, p=2, bc=["P", "D", "D", "D"]),
-                dict(dim=2, n=4, p=2, mu=np.array([1.0] * 15 + [np.nan]))):
+                dict(dim=2, n=4, p=2, mu=np.array([1.0] * 15 + [np.nan])),
+                dict(dim=2, n=8, p=2, smoother="jacobi", precision="bf16s"),   # BF16 is for SAI only
+                dict(dim=2, n=8, p=2, smoother="gs", precision="bf16s")):
         with pytest.raises((L.LdgmgError, ValueError)) as ei:
             s = L.Solver(host_only=True, **bad)
             s.close()
@@ -98,3 +100,20 @@ def test_bottom_independent_of_thread_count():
             s.close()
     assert out[0].shape == (400, 400)
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_upload_bytes_by_storage():
+    """Pooled storage keeps the distinct blocks once plus a block id per slot."""
+    from paper_2412_12506_amd import ldgmg as L
+    got = {}
+    for st in ("expanded", "pooled", "auto"):
+        s = L.Solver(host_only=True, dim=3, n=8, p=3, smoother="sai", storage=st)
+        try:
+            got[st] = s.upload_bytes
+            nnz_a = L.ldgmg_level_info(s.handle, 0)["nnzb_A"]
+        finally:
+            s.close()
+    # the fine A alone: 8^3 rows of 7 (interior) FP32 64x64 blocks when expanded
+    assert got["expanded"] > nnz_a * 64 * 64 * 4
+    assert got["pooled"] < got["expanded"] / 4
+    assert got["pooled"] <= got["auto"] <= got["expanded"]
