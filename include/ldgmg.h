@@ -142,6 +142,15 @@ int ldgmg_setup(const ldgmg_problem* p, void* stream, ldgmg_handle* out);
  * no device data is left as it is. */
 int ldgmg_unload(ldgmg_handle h);
 
+/* CG guard for the solves of this handle (single and batched): when enabled,
+ * CG stops at once, unconverged (LDGMG_ENOCONV), as soon as r^T V r <= 0 or
+ * p^T A p <= 0, i.e. the V-cycle (or A) shows it is not positive definite on
+ * the Krylov space; info holds the iterations done and the residual reached.
+ * Off by default: plain preconditioned CG (Section 2.2), which can still
+ * converge with such a preconditioner.  For callers that switch smoothers on
+ * failure (serving).  Kept across ldgmg_unload / ldgmg_upload. */
+int ldgmg_cg_guard(ldgmg_handle h, int enable);
+
 /* Device bytes the handle holds now (0 when it holds no device data): what
  * ldgmg_upload allocated plus the batch workspace once a batched call made it. */
 int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes);
@@ -179,9 +188,7 @@ int ldgmg_vcycle(ldgmg_handle h, const double* b_dev, double* x_dev, void* strea
  * (LDGMG_GMRES, no restart, at most min(maxit, 200) iterations).  Stops when
  * ||r||_2 <= rtol ||b||_2 (CG, FP64 recursive residual) or
  * ||V r||_2 <= rtol ||V b||_2 (GMRES).  Returns LDGMG_ENOCONV if maxit is hit
- * or, for CG, at a breakdown: r^T V r <= 0 or p^T A p <= 0 (a preconditioner
- * that is not positive definite), where CG stops at once; info then holds the
- * iterations done and the residual reached.  info may be NULL. */
+ * or, with ldgmg_cg_guard enabled, at a CG breakdown.  info may be NULL. */
 int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov,
                 double rtol, int maxit, ldgmg_info* info, void* stream);
 

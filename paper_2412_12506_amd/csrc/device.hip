@@ -126,6 +126,7 @@ struct DevHier {
 struct ldgmg_hier {
   std::unique_ptr<ldgmg::HostHierarchy> host;
   std::unique_ptr<ldgmg::DevHier> dev;
+  bool cg_guard = false;            // ldgmg_cg_guard
 };
 
 namespace ldgmg {
@@ -371,6 +372,7 @@ struct Ctx {
   const HostHierarchy& H;
   DevHier& D;
   hipStream_t st;
+  bool guard = false;               // CG stops at a breakdown (ldgmg_cg_guard)
 };
 
 // brackets one launch on level 0 with events when profiling is enabled
@@ -686,9 +688,9 @@ int solve_cg(const Ctx& c, const double* b, double* x, double rtol, int maxit, l
       conv = true;
       break;
     }
-    // r^T V r <= 0 or p^T A p <= 0: the preconditioner (or A) is not positive
-    // definite on the Krylov space and CG cannot continue; stop unconverged
-    if (!(D.hscal[S_RZ] > 0.0) || !(D.hscal[S_ALPHA] > 0.0)) break;
+    // guarded: r^T V r <= 0 or p^T A p <= 0 shows that the preconditioner (or A)
+    // is not positive definite on the Krylov space; stop unconverged
+    if (c.guard && (!(D.hscal[S_RZ] > 0.0) || !(D.hscal[S_ALPHA] > 0.0))) break;
     vcycle64(c, D.kr, D.kz);
     ++vcycles;
     dot_partial(N, D.kr, D.kz, D.partial, c.st);
@@ -996,7 +998,8 @@ int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int n
       rr[q] = D.hbscal[slot(q, RR)];
       if (!std::isfinite(rr[q])) throw std::runtime_error("CG breakdown (non-finite residual)");
       if (rr[q] <= rtol * rtol * bb[q]) done[q] = 1;
-      else if (!(D.hbscal[slot(q, RZ)] > 0.0) || !(D.hbscal[slot(q, AL)] > 0.0)) done[q] = 2;   // breakdown
+      else if (c.guard && (!(D.hbscal[slot(q, RZ)] > 0.0) || !(D.hbscal[slot(q, AL)] > 0.0)))
+        done[q] = 2;                                     // guarded breakdown
       else more = true;
     }
     if (!more) break;
@@ -1213,6 +1216,14 @@ int ldgmg_unload(ldgmg_handle h) {
   });
 }
 
+int ldgmg_cg_guard(ldgmg_handle h, int enable) {
+  return guarded([&] {
+    if (!h || !h->host) throw std::invalid_argument("null handle");
+    h->cg_guard = enable != 0;
+    return LDGMG_OK;
+  });
+}
+
 int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes) {
   return guarded([&] {
     if (!h || !h->host || !bytes) throw std::invalid_argument("null argument");
@@ -1337,7 +1348,7 @@ int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov, 
     need_dev(h);
     if (!b_dev || !x_dev) throw std::invalid_argument("null vector");
     if (!(rtol > 0) || maxit < 1) throw std::invalid_argument("rtol must be > 0 and maxit >= 1");
-    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream), h->cg_guard};
     if (krylov == LDGMG_CG) return solve_cg(c, b_dev, x_dev, rtol, maxit, info);
     if (krylov == LDGMG_GMRES) return solve_gmres(c, b_dev, x_dev, rtol, maxit, info);
     throw std::invalid_argument("unknown krylov method");
@@ -1370,7 +1381,7 @@ int ldgmg_solve_batch(ldgmg_handle h, const double* const* b_dev, double* const*
     if (!(rtol > 0) || maxit < 1) throw std::invalid_argument("rtol must be > 0 and maxit >= 1");
     for (int q = 0; q < k; ++q)
       if (!b_dev[q] || !x_dev[q]) throw std::invalid_argument("null vector in batch");
-    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream), h->cg_guard};
     return solve_cg_batch(c, b_dev, x_dev, k, rtol, maxit, infos);
   });
 }

@@ -60,7 +60,7 @@ _lib = None
 SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
-           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage", "ldgmg_destroy",
+           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -95,6 +95,7 @@ def lib():
     L.ldgmg_profile.argtypes = [H, C.c_int]
     L.ldgmg_profile_read.argtypes = [H, C.c_int, ip, dp]
     L.ldgmg_unload.argtypes = [H]
+    L.ldgmg_cg_guard.argtypes = [H, C.c_int]
     L.ldgmg_device_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.ldgmg_upload_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.ldgmg_level_storage.argtypes = [H, C.c_int, ip, ip]
@@ -315,6 +316,10 @@ def ldgmg_profile_read(h: int, kind: str):
 
 def ldgmg_unload(h: int):
     _check(lib().ldgmg_unload(h))
+
+
+def ldgmg_cg_guard(h: int, enable: bool = True):
+    _check(lib().ldgmg_cg_guard(h, 1 if enable else 0))
 
 
 def ldgmg_device_bytes(h: int) -> int:

@@ -19,8 +19,9 @@ Hierarchy cache, two tiers, keyed by the problem:
     Requests whose hierarchy does not fit wait until a running batch ends.
 
 Robustness: when a batch's CG solves with the SAI V-cycle do not converge (the
-library stops CG at once when the preconditioner shows it is not positive
-definite), the hierarchy of that problem is rebuilt with the coloured
+engine enables the library's CG guard, which stops CG at once when the
+preconditioner shows it is not positive definite), the hierarchy of that
+problem is rebuilt with the coloured
 Gauss-Seidel smoother (the paper's second-ranked smoother) and the affected
 requests are queued again at the front; later requests of the key use it.
 
@@ -157,6 +158,7 @@ class ServingEngine:
             smoother = self._entry(key).smoother
         kw = problem_kwargs(key, self.precision, smoother)
         solver = L.Solver(host_only=True, nthreads=self.setup_threads, **kw)
+        L.ldgmg_cg_guard(solver.handle, True)     # fail fast when the V-cycle is not SPD
         with self.cv:
             e = self._entry(key)
             e.solver, e.building = solver, False
