@@ -65,12 +65,17 @@ enum { LDGMG_FP64 = 0, LDGMG_FP32 = 1, LDGMG_BF16S = 2 };
 /* device storage of the block-sparse matrices.  EXPANDED: every slot holds its
  * block.  POOLED: the distinct blocks of a matrix are stored once and every
  * slot holds a 4-byte block id; the setup builds each matrix as such a pool
- * (identical blocks are computed once), so both storages hold the same values.
- * AUTO: per matrix and level, POOLED when its distinct blocks take at most
- * 64 MiB and at most a quarter of the expanded bytes, else EXPANDED.  Pooled
- * storage needs a block size with a wave-mapped kernel (4, 8, 9, 12, 16, 25,
- * 27, 32, 36, 48, 64); other sizes are always expanded. */
-enum { LDGMG_STORE_AUTO = 0, LDGMG_STORE_EXPANDED = 1, LDGMG_STORE_POOLED = 2 };
+ * (identical blocks are computed once), so both storages hold the same values
+ * and give bitwise-equal results.  TILED: POOLED plus, for matrices with at
+ * most 64 distinct column offsets (column - row), a [row][offset] table of
+ * block ids and a copy of the pool in the operand layout of the FP64 matrix
+ * cores: forward products then run as 16-row tiles of FP64 MFMA (same values,
+ * FP64 products and sums, a different summation order).  AUTO: per matrix and
+ * level, TILED (or POOLED beyond 64 offsets) when its distinct blocks take at
+ * most 64 MiB and at most a quarter of the expanded bytes, else EXPANDED.
+ * Pooled and tiled storage need a block size with a wave-mapped kernel (4, 8,
+ * 9, 12, 16, 25, 27, 32, 36, 48, 64); other sizes are always expanded. */
+enum { LDGMG_STORE_AUTO = 0, LDGMG_STORE_EXPANDED = 1, LDGMG_STORE_POOLED = 2, LDGMG_STORE_TILED = 3 };
 enum { LDGMG_CG = 0, LDGMG_GMRES = 1 };
 
 typedef struct ldgmg_hier* ldgmg_handle;
@@ -157,8 +162,9 @@ int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes);
 
 /* Device storage chosen for one level (needs device data): number of distinct
  * blocks stored for A and for the smoother matrix when pooled, 0 when that
- * matrix is expanded (every slot holds its block). */
-int ldgmg_level_storage(ldgmg_handle h, int level, int* pool_A, int* pool_S);
+ * matrix is expanded (every slot holds its block); *tiled: bit 0 A, bit 1 the
+ * smoother matrix, set when tiled.  Any output may be NULL. */
+int ldgmg_level_storage(ldgmg_handle h, int level, int* pool_A, int* pool_S, int* tiled);
 
 /* Device bytes ldgmg_upload will allocate for this host hierarchy (exact for
  * its storage choices; the batch workspace of the batched calls not included). */

@@ -40,6 +40,14 @@ struct StateError : std::runtime_error {
     if (e_ != hipSuccess) throw HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// tiled storage of one matrix (forward products on the matrix cores)
+struct Tiled {
+  const void* blk = nullptr;        // pool in the operand layout of the tiled kernel
+  int* tab = nullptr;               // [rows][noff] pool ids, -1 where no block
+  int* off = nullptr;               // column offsets
+  int noff = 0;
+};
+
 struct DevLevel {
   int index = 0;
   int n = 0, ne = 0, bs = 0, bss = 0, ncomp = 1;
@@ -56,6 +64,7 @@ struct DevLevel {
   int* bidA = nullptr;              // pooled storage: block id per slot (null when expanded)
   int* bidS = nullptr;
   int* bidST = nullptr;
+  Tiled tA, tS, tST;                // tiled storage (tab null when not tiled)
   std::vector<int*> colour_rows;    // device lists per colour
   std::vector<int> colour_count;
   double* x = nullptr;              // level vectors are FP64 in both precisions
@@ -75,6 +84,7 @@ struct DevHier {
   std::vector<DevLevel> L;
   double* val64 = nullptr;          // fine-level FP64 A values (own copy only in FP32 mode)
   int* bid64 = nullptr;             // its block ids when pooled
+  Tiled t64;                        // and its tiled form
   bool own64 = false;
   double *kx = nullptr, *kr = nullptr, *kp = nullptr, *kq = nullptr, *kz = nullptr;
   double* scal = nullptr;           // scalar table
@@ -141,17 +151,43 @@ size_t elem_bytes_S(int prec) { return prec == LDGMG_FP64 ? 8 : prec == LDGMG_BF
 // pooled storage of one matrix with elements of `elem` bytes (LDGMG_STORE_*)
 bool use_pool(const PMat& P, int bs, size_t elem, int storage) {
   if (!fast_bs(bs) || storage == LDGMG_STORE_EXPANDED) return false;
-  if (storage == LDGMG_STORE_POOLED) return true;
+  if (storage == LDGMG_STORE_POOLED || storage == LDGMG_STORE_TILED) return true;
   const size_t bb = static_cast<size_t>(bs) * bs * elem;
   const size_t pool = static_cast<size_t>(P.pool.size()) * bb;
   return pool <= (static_cast<size_t>(64) << 20) && 4 * pool <= static_cast<size_t>(P.nnzb()) * bb;
 }
 
-// device bytes of one matrix's blocks (and block ids when pooled)
+// distinct column offsets (column - row) of a block-sparse matrix, ascending
+std::vector<int> column_offsets(const PMat& P) {
+  std::vector<int> o;
+  for (int i = 0; i + 1 < static_cast<int>(P.rp.size()); ++i)
+    for (int s2 = P.rp[i]; s2 < P.rp[i + 1]; ++s2) o.push_back(P.ci[s2] - i);
+  std::sort(o.begin(), o.end());
+  o.erase(std::unique(o.begin(), o.end()), o.end());
+  return o;
+}
+
+constexpr int kMaxTiledOffsets = 64;
+
+// tiled storage (on top of pooled) for a matrix: TILED, or AUTO when pooled
+bool use_tiled(const PMat& P, int bs, size_t elem, int storage) {
+  if (storage != LDGMG_STORE_TILED && storage != LDGMG_STORE_AUTO) return false;
+  if (!use_pool(P, bs, elem, storage)) return false;
+  return static_cast<int>(column_offsets(P).size()) <= kMaxTiledOffsets;
+}
+
+// device bytes of one matrix's blocks (and block ids when pooled, and the
+// operand-layout pool and offset table when tiled)
 size_t matrix_bytes(const PMat& P, int bs, size_t elem, int storage) {
   const size_t bb = static_cast<size_t>(bs) * bs * elem;
-  if (use_pool(P, bs, elem, storage)) return static_cast<size_t>(P.pool.size()) * bb + P.nnzb() * sizeof(int);
-  return static_cast<size_t>(P.nnzb()) * bb;
+  if (!use_pool(P, bs, elem, storage)) return static_cast<size_t>(P.nnzb()) * bb;
+  size_t b = static_cast<size_t>(P.pool.size()) * bb + P.nnzb() * sizeof(int);
+  if (use_tiled(P, bs, elem, storage)) {
+    const size_t noff = column_offsets(P).size();
+    b += static_cast<size_t>(P.pool.size()) * tiled_block_elems(bs) * elem;
+    b += static_cast<size_t>(P.nbr) * noff * sizeof(int) + std::max<size_t>(16, noff * sizeof(int));
+  }
+  return b;
 }
 
 // bytes one level needs on the device in precision prec (expanded storage;
@@ -173,6 +209,34 @@ size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long n
   return b;
 }
 
+// tiled form of a pooled matrix: the pool in the tiled kernel's operand layout
+// (transposed blocks if asked), the column offsets and the pool-id table
+template <typename T>
+void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, Tiled& t, hipStream_t st) {
+  const std::vector<int> off = column_offsets(P);
+  const int noff = static_cast<int>(off.size());
+  std::vector<int> tab(static_cast<size_t>(P.nbr) * noff, -1);
+  for (int i = 0; i < P.nbr; ++i)
+    for (int s2 = P.rp[i]; s2 < P.rp[i + 1]; ++s2) {
+      const int d = static_cast<int>(std::lower_bound(off.begin(), off.end(), P.ci[s2] - i) - off.begin());
+      tab[static_cast<size_t>(i) * noff + d] = P.id[s2];
+    }
+  const long long nd = P.pool.size();
+  T* blk = static_cast<T*>(D.alloc(static_cast<size_t>(nd) * tiled_block_elems(bs) * sizeof(T)));
+  t.tab = static_cast<int*>(D.alloc(tab.size() * sizeof(int)));
+  t.off = static_cast<int*>(D.alloc(std::max<size_t>(16, off.size() * sizeof(int))));
+  HIPCHK(hipMemcpyAsync(t.tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(t.off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  double* pool = nullptr;
+  HIPCHK(hipMalloc(&pool, std::max<size_t>(16, P.pool.data.size() * sizeof(double))));
+  HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  expand_tiled<T>(nd, bs, pool, blk, transpose, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipFree(pool));
+  t.blk = blk;
+  t.noff = noff;
+}
+
 template <typename TA, typename TS>   // element types of the stored operator and smoother blocks
 void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hipStream_t st) {
   dl.n = hl.n;
@@ -191,9 +255,10 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
   // device blocks of type T for a pooled host matrix (transposed blocks if
   // asked): every slot's block (expanded), or the distinct blocks once with
   // the block id of every slot in `bid` (pooled; bid stays null otherwise)
-  auto place = [&](auto tag, const PMat& P, bool transpose, int*& bid) {
+  auto place = [&](auto tag, const PMat& P, bool transpose, int*& bid, Tiled& tiled) {
     using T = decltype(tag);
     const bool pooled = use_pool(P, hl.bs, sizeof(T), storage);
+    if (use_tiled(P, hl.bs, sizeof(T), storage)) make_tiled<T>(D, P, hl.bs, transpose, tiled, st);
     const int nd = P.pool.size();
     std::vector<int> order;
     if (pooled) {
@@ -218,13 +283,13 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
   dl.nnzA = hl.A.nnzb();
   dl.rpA = up_ints(hl.A.rp);
   dl.ciA = up_ints(hl.A.ci);
-  dl.valA = place(TA{}, hl.A, false, dl.bidA);
+  dl.valA = place(TA{}, hl.A, false, dl.bidA, dl.tA);
   if (!bottom) {
     dl.nnzS = hl.S.nnzb();
     dl.rpS = up_ints(hl.S.rp);
     dl.ciS = up_ints(hl.S.ci);
     dl.tposS = up_ints(hl.tpos);
-    dl.valS = place(TS{}, hl.S, false, dl.bidS);
+    dl.valS = place(TS{}, hl.S, false, dl.bidS, dl.tS);
     if (fast_bs(hl.bs)) {   // S^T applies stream a transposed copy through the forward kernel
       PMat st;
       st.nbr = hl.S.nbr;
@@ -236,7 +301,7 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
       st.pool.r = hl.S.pool.r;
       st.pool.c = hl.S.pool.c;
       st.pool.data = hl.S.pool.data;
-      dl.valST = place(TS{}, st, true, dl.bidST);
+      dl.valST = place(TS{}, st, true, dl.bidST, dl.tST);
     }
     for (const auto& rows : hl.colour_rows) {
       dl.colour_rows.push_back(up_ints(rows));
@@ -296,6 +361,8 @@ size_t estimate_from_host(const HostHierarchy& H, int prec) {
     const size_t bb8 = static_cast<size_t>(F.bs) * F.bs * 8;
     b += use_pool(F.A, F.bs, ea, storage) ? static_cast<size_t>(F.A.pool.size()) * bb8
                                           : static_cast<size_t>(F.A.nnzb()) * bb8;
+    if (use_tiled(F.A, F.bs, ea, storage))   // operand-layout pool of the FP64 copy
+      b += static_cast<size_t>(F.A.pool.size()) * tiled_block_elems(F.bs) * 8;
   }
   b += 5 * N * 8 + 64 * 8 + kRedBlocks * 8 * 2;
   return b;
@@ -327,6 +394,7 @@ void upload(ldgmg_hier* h, hipStream_t st) {
   if (D->prec == LDGMG_FP64) {
     D->val64 = static_cast<double*>(f.valA);
     D->bid64 = f.bidA;
+    D->t64 = f.tA;
   } else {
     // the FP64 operator of the Krylov iteration follows the storage of A: the
     // distinct blocks (sharing A's block ids) when A is pooled
@@ -346,6 +414,13 @@ void upload(ldgmg_hier* h, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(pool, F.A.pool.data.data(), F.A.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ids, ids_h.data(), ids_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
     expand_blocks<double>(static_cast<long long>(ids_h.size()), F.bs, ids, pool, D->val64, false, st);
+    if (f.tA.tab) {                         // tiled A: the FP64 copy gets its own operand-layout pool
+      const long long nd = F.A.pool.size();
+      double* tb = static_cast<double*>(D->alloc(static_cast<size_t>(nd) * tiled_block_elems(F.bs) * sizeof(double)));
+      expand_tiled<double>(nd, F.bs, pool, tb, false, st);
+      D->t64 = f.tA;
+      D->t64.blk = tb;
+    }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipFree(pool));
     HIPCHK(hipFree(ids));
@@ -397,6 +472,14 @@ enum { K_A = 0, K_SF = 1, K_ST = 2, K_A64 = 3, K_FUSED = 4 };
 using Vd = double;   // vector / arithmetic type of the V-cycle
 
 template <typename T>
+void set_tiled(BsrArgs<T, Vd>& a, const Tiled& t) {
+  a.tblk = static_cast<const T*>(t.blk);
+  a.tab = t.tab;
+  a.toff = t.off;
+  a.noff = t.noff;
+}
+
+template <typename T>
 BsrArgs<T, Vd> argsA(const DevLevel& L) {
   BsrArgs<T, Vd> a;
   a.nrows = L.ne;
@@ -405,6 +488,7 @@ BsrArgs<T, Vd> argsA(const DevLevel& L) {
   a.ci = L.ciA;
   a.bid = L.bidA;
   a.blk = static_cast<const T*>(L.valA);
+  set_tiled(a, L.tA);
   return a;
 }
 template <typename T>
@@ -417,6 +501,7 @@ BsrArgs<T, Vd> argsS(const DevLevel& L) {
   a.tpos = L.tposS;
   a.bid = L.bidS;
   a.blk = static_cast<const T*>(L.valS);
+  set_tiled(a, L.tS);
   return a;
 }
 
@@ -451,6 +536,7 @@ void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* o
   if (transposed && L.valST) {
     a.blk = static_cast<const T*>(L.valST);
     a.bid = L.bidST;
+    set_tiled(a, L.tST);
     bsr_forward<T, Vd>(a, st);
   } else if (transposed) {
     bsr_transposed<T, Vd>(a, st);
@@ -598,6 +684,7 @@ void apply_A64(const Ctx& c, const double* x, double* y) {
   a.ci = L.ciA;
   a.blk = c.D.val64;
   a.bid = c.D.bid64;
+  set_tiled(a, c.D.t64);
   a.x = x;
   a.out = y;
   ProfScope ps(c.D, L, c.st, K_A64);
@@ -935,6 +1022,7 @@ void apply_A64_multi(const Ctx& c, const double* x, double* y, int nk) {
   a.ci = L.ciA;
   a.blk = c.D.val64;
   a.bid = c.D.bid64;
+  set_tiled(a, c.D.t64);
   a.x = x;
   a.out = y;
   ProfScope ps(c.D, L, c.st, K_A64);
@@ -1232,7 +1320,7 @@ int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes) {
   });
 }
 
-int ldgmg_level_storage(ldgmg_handle h, int level, int* pool_A, int* pool_S) {
+int ldgmg_level_storage(ldgmg_handle h, int level, int* pool_A, int* pool_S, int* tiled) {
   return guarded([&] {
     need_dev(h);
     check_level(h, level);
@@ -1240,6 +1328,7 @@ int ldgmg_level_storage(ldgmg_handle h, int level, int* pool_A, int* pool_S) {
     const DevLevel& D = h->dev->L[level];
     if (pool_A) *pool_A = D.bidA ? H.A.pool.size() : 0;
     if (pool_S) *pool_S = D.bidS ? H.S.pool.size() : 0;
+    if (tiled) *tiled = (D.tA.tab ? 1 : 0) | (D.tS.tab ? 2 : 0);
     return LDGMG_OK;
   });
 }

@@ -324,7 +324,7 @@ void validate_problem(const ldgmg_problem& p) {
   if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 > 16 || p.nu2 > 16) throw std::invalid_argument("nu out of range");
   if (p.precision != LDGMG_FP64 && p.precision != LDGMG_FP32 && p.precision != LDGMG_BF16S)
     throw std::invalid_argument("unknown precision");
-  if (p.storage < LDGMG_STORE_AUTO || p.storage > LDGMG_STORE_POOLED) throw std::invalid_argument("unknown storage");
+  if (p.storage < LDGMG_STORE_AUTO || p.storage > LDGMG_STORE_TILED) throw std::invalid_argument("unknown storage");
   if (p.precision == LDGMG_BF16S && p.smoother != LDGMG_SMOOTH_SAI)
     throw std::invalid_argument("BF16 smoother storage is for the SAI smoothers only");
   if (!(p.tau0 > 0) || !(p.cp >= 0)) throw std::invalid_argument("penalty constants must be positive");

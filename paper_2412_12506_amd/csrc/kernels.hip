@@ -5,6 +5,7 @@
 #include "launch.hpp"
 
 #include <stdexcept>
+#include <type_traits>
 #include <string>
 
 namespace ldgmg {
@@ -379,6 +380,104 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
   if (active) {
     const size_t o = static_cast<size_t>(row) * BS + r;
     out[o] = beta != T(0) ? alpha * y + beta * z[o] : alpha * y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tiled forward BSR kernel on the FP64 matrix cores: out = alpha M x + beta z
+// for a pooled matrix addressed by column offset.  tab[row * noff + d] is the
+// pool id of block (row, row + off[d]) or -1.  A wavefront takes the 16 block
+// rows e0 .. e0 + 15 as the columns of an MFMA tile; for each offset it groups
+// them by block id and accumulates Y(bs x 16) += B(bs x bs) X(bs x 16), column
+// c of X being the x block of row e0 + c + off[d] (zero for rows outside the
+// group), with v_mfma_f64_16x16x4f64: products and sums in FP64.
+// Pool layout (MT = ceil(bs/16) row tiles, KS = ceil(bs/4) k steps): entry
+// [block][m][lane][s] = B(16 m + lane % 16, (lane / 16) KS + s), zero outside
+// the block, so that lane l reads the KS operands of its k range contiguously.
+// MFMA operands: A lane l = (row l % 16, k l / 16), B lane l = (k l / 16,
+// column l % 16); result lane l = rows l / 16 + 4 i (i < 4) of column l % 16.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename TM, int BS>
+__global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
+                                                        const int* __restrict__ tab,
+                                                        const TM* __restrict__ blk, const double* x,
+                                                        const double* z, double* out, double alpha,
+                                                        double beta) {
+  constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int e0 = tile * 16;
+  if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
+  const int col = lane & 15, kq = lane >> 4;
+  const int row = e0 + col;
+  const bool rv = row < nrows;
+  const int rowc = rv ? row : e0;
+  v4d acc[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int d = 0; d < noff; ++d) {
+    const int o = off[d];
+    const int t = tab[static_cast<size_t>(rowc) * noff + d];
+    const int myid = rv ? t : -1;
+    unsigned long long rem = __ballot(myid >= 0) & 0xFFFFull;
+    while (rem) {                           // one MFMA pass per distinct block of this offset
+      const int c0 = __ffsll(static_cast<long long>(rem)) - 1;
+      const int id = __shfl(myid, c0);
+      const unsigned long long sel = __ballot(myid == id) & 0xFFFFull;
+      const bool use = (sel >> col) & 1ull;
+      const double* xp = x + static_cast<size_t>(use ? row + o : 0) * BS;
+      double xb[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int c = kq * KS + s;
+        const double v = xp[c < BS ? c : 0];
+        xb[s] = (use && c < BS) ? v : 0.0;
+      }
+      const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(lane) * KS;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        TM a[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[s] = bp[m * 64 * KS + s];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+          acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(widen(a[s])), xb[s], acc[m], 0, 0, 0);
+      }
+      rem &= ~sel;
+    }
+  }
+  if (!rv) return;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * m + kq + 4 * i;      // result layout of the MFMA
+      if (r < BS) {
+        const size_t o = static_cast<size_t>(row) * BS + r;
+        out[o] = beta != 0.0 ? alpha * acc[m][i] + beta * z[o] : alpha * acc[m][i];
+      }
+    }
+}
+
+// pooled blocks (row-major FP64) -> the operand layout of k_bsr_tiled
+template <typename T>
+__global__ void k_expand_tiled(long long nblk, int bs, int MT, int KS, const double* __restrict__ pool,
+                               T* __restrict__ out, int transpose) {
+  const long long per = static_cast<long long>(MT) * 64 * KS;
+  const long long bb = static_cast<long long>(bs) * bs;
+  for (long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; t < nblk * per;
+       t += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const long long b = t / per;
+    const int rem = static_cast<int>(t - b * per);
+    const int m = rem / (64 * KS);
+    const int l = (rem / KS) % 64;
+    const int s = rem % KS;
+    const int r = 16 * m + l % 16, c = (l / 16) * KS + s;
+    double v = 0.0;
+    if (r < bs && c < bs) v = transpose ? pool[b * bb + static_cast<long long>(c) * bs + r] : pool[b * bb + static_cast<long long>(r) * bs + c];
+    out[t] = narrow<T>(v);
   }
 }
 
@@ -778,6 +877,16 @@ void launch_fwd_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
 }
 
 template <typename TM, typename T, int BS>
+void launch_tiled_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
+  const long long tiles = (a.nrows + 15) / 16;
+  const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
+  if (blocks == 0) return;
+  k_bsr_tiled<TM, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tblk, a.x, a.z, a.out,
+                                                   a.alpha, a.beta);
+  check_launch("bsr_tiled");
+}
+
+template <typename TM, typename T, int BS>
 void launch_tr_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
   constexpr int G = 64 / BS;
   const long long waves = (a.nrows + G - 1) / G;
@@ -816,6 +925,20 @@ bool fast_bs(int bs) {
 
 template <typename TM, typename T>
 void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (a.tab && !a.dinv && !a.rows) {     // tiled storage: matrix cores
+      switch (a.bs) {
+#define CASE(B) \
+  case B:       \
+    launch_tiled_bs<TM, T, B>(a, st); \
+    return;
+        LDGMG_FOR_BS(CASE)
+#undef CASE
+        default:
+          throw std::runtime_error("tiled storage needs a block size with a wave-mapped kernel");
+      }
+    }
+  }
   switch (a.bs) {
 #define CASE(B) \
   case B:       \
@@ -888,6 +1011,15 @@ void expand_blocks(long long nslots, int bs, const int* ids, const double* pool,
   const long long total = nslots * bs * bs;
   k_expand<T><<<grid_for(total, 256, 65536), 256, 0, st>>>(nslots, bs, V, ids, pool, out, transpose ? 1 : 0);
   check_launch("expand");
+}
+
+template <typename T>
+void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool transpose, hipStream_t st) {
+  if (nblk == 0) return;
+  const int MT = (bs + 15) / 16, KS = (bs + 3) / 4;
+  const long long total = nblk * MT * 64 * KS;
+  k_expand_tiled<T><<<grid_for(total, 256, 65536), 256, 0, st>>>(nblk, bs, MT, KS, pool, out, transpose ? 1 : 0);
+  check_launch("expand_tiled");
 }
 
 template <typename T>
@@ -989,6 +1121,9 @@ template void bsr_forward<bf16s, double>(const BsrArgs<bf16s, double>&, hipStrea
 template void bsr_transposed<bf16s, double>(const BsrArgs<bf16s, double>&, hipStream_t);
 template void bsr_forward_multi<bf16s, double>(const BsrArgs<bf16s, double>&, long long, int, hipStream_t);
 template void expand_blocks<bf16s>(long long, int, const int*, const double*, bf16s*, bool, hipStream_t);
+template void expand_tiled<float>(long long, int, const double*, float*, bool, hipStream_t);
+template void expand_tiled<double>(long long, int, const double*, double*, bool, hipStream_t);
+template void expand_tiled<bf16s>(long long, int, const double*, bf16s*, bool, hipStream_t);
 template void expand_blocks<float>(long long, int, const int*, const double*, float*, bool, hipStream_t);
 template void expand_blocks<double>(long long, int, const int*, const double*, double*, bool, hipStream_t);
 template void restrict_op<double>(int, int, int, int, int, const double*, const double*, const double*, double*,

@@ -43,8 +43,21 @@ struct BsrArgs {
   T alpha = T(1), beta = T(0);
   const TM* dinv = nullptr;   // fused smoothing: block inverses indexed by block row
   const int* dbid = nullptr;  // pooled block inverses: block of each row (null: row r owns block r)
+  // tiled storage (forward products on the matrix cores; used when tab is set,
+  // without dinv and rows): pool in the operand layout of k_bsr_tiled, the
+  // column offsets and the [nrows][noff] table of pool ids (-1: no block)
+  const TM* tblk = nullptr;
+  const int* tab = nullptr;
+  const int* toff = nullptr;
+  int noff = 0;
   T omega = T(1);
 };
+
+// expand pooled FP64 blocks (row-major) into the operand layout of the tiled kernel
+template <typename T>
+void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool transpose, hipStream_t st);
+// elements per pooled block in that layout
+inline long long tiled_block_elems(int bs) { return static_cast<long long>((bs + 15) / 16) * 64 * ((bs + 3) / 4); }
 
 // out = alpha M x + beta z, or (dinv != null) out = x + omega Dinv (z - M x)
 template <typename TM, typename T> void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st);

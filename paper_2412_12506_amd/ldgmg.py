@@ -25,7 +25,7 @@ BC = {"D": 0, "N": 1, "P": 2}
 SMOOTHER = {"jacobi": 0, "gs": 1, "sai": 2}
 ORDER = {"OO": 0, "OI": 1, "IO": 2, "II": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16s": 2}
-STORAGE = {"auto": 0, "expanded": 1, "pooled": 2}
+STORAGE = {"auto": 0, "expanded": 1, "pooled": 2, "tiled": 3}
 KRYLOV = {"cg": 0, "gmres": 1}
 OP = {"residual": 0, "apply_a": 1, "apply_s": 2, "apply_st": 3, "smooth_fwd": 4,
       "smooth_rev": 5, "restrict": 6, "prolong_add": 7, "bottom": 8, "apply_a64": 9}
@@ -98,7 +98,7 @@ def lib():
     L.ldgmg_cg_guard.argtypes = [H, C.c_int]
     L.ldgmg_device_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.ldgmg_upload_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
-    L.ldgmg_level_storage.argtypes = [H, C.c_int, ip, ip]
+    L.ldgmg_level_storage.argtypes = [H, C.c_int, ip, ip, ip]
     L.ldgmg_destroy.argtypes = [H]
     L.ldgmg_last_error.argtypes = []
     L.ldgmg_last_error.restype = C.c_char_p
@@ -335,9 +335,9 @@ def ldgmg_upload_bytes(h: int) -> int:
 
 
 def ldgmg_level_storage(h: int, level: int) -> dict:
-    a, b = C.c_int(0), C.c_int(0)
-    _check(lib().ldgmg_level_storage(h, level, C.byref(a), C.byref(b)))
-    return {"pool_A": a.value, "pool_S": b.value}
+    a, b, t = C.c_int(0), C.c_int(0), C.c_int(0)
+    _check(lib().ldgmg_level_storage(h, level, C.byref(a), C.byref(b), C.byref(t)))
+    return {"pool_A": a.value, "pool_S": b.value, "tiled_A": bool(t.value & 1), "tiled_S": bool(t.value & 2)}
 
 
 def ldgmg_destroy(h: int):

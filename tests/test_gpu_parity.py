@@ -60,9 +60,9 @@ def _dev():
 
 def _variants(case):
     """(precision, device storage) pairs: every kernel instantiation the case reaches."""
-    v = [("fp64", "auto"), ("fp32", "expanded"), ("fp32", "pooled")]
+    v = [("fp64", "auto"), ("fp32", "expanded"), ("fp32", "pooled"), ("fp32", "tiled")]
     if case["smoother"] == "sai":
-        v += [("bf16s", "expanded"), ("bf16s", "pooled")]
+        v += [("bf16s", "expanded"), ("bf16s", "pooled"), ("bf16s", "tiled")]
     return v
 
 

@@ -1,11 +1,14 @@
-"""Pooled against expanded device storage (GPU).
+"""Pooled and tiled against expanded device storage (GPU).
 
 Both storages hold the same block values (the setup builds every matrix as a
 pool of distinct blocks; pooled storage keeps the pool and a block id per slot,
 expanded storage copies each slot's block), and the kernels do the same
 arithmetic in the same order, so every result must be bitwise equal: level
 operations, the V-cycle, single and batched solves.  The bytes ldgmg_upload
-allocates equal ldgmg_upload_bytes exactly in both storages.
+allocates equal ldgmg_upload_bytes exactly in every storage.  Tiled storage
+applies the same blocks on the FP64 matrix cores: its products and sums are
+FP64 in another order, so it agrees with pooled storage to a few FP64 units
+per row sum (1e-13 of |M||x|) and gives the same CG iterations.
 """
 import numpy as np
 import pytest
@@ -34,7 +37,7 @@ def pair(request):
     case, prec = request.param
     print(f"\n[storage {case['id']} {prec}]", flush=True)
     out = {}
-    for st in ("expanded", "pooled"):
+    for st in ("expanded", "pooled", "tiled"):
         s = L.Solver(storage=st, **lib_kwargs(case, prec))
         torch.cuda.synchronize()
         out[st] = s
@@ -44,10 +47,13 @@ def pair(request):
 
 
 def test_upload_bytes_exact(pair):
+    from paper_2412_12506_amd import ldgmg as L
     case, prec, sv = pair
     for st, s in sv.items():
         assert s.device_bytes == s.upload_bytes, (st, s.device_bytes, s.upload_bytes)
     assert sv["pooled"].upload_bytes < sv["expanded"].upload_bytes
+    st = L.ldgmg_level_storage(sv["tiled"].handle, 0)
+    assert st["tiled_A"] and st["pool_A"] > 0
 
 
 def _rhs(case, s, seed):
@@ -125,3 +131,42 @@ def test_batch_bitwise(pair):
     for q in range(3):
         assert outs[0][0][q]["iters"] == outs[1][0][q]["iters"]
         assert torch.equal(outs[0][1][q], outs[1][1][q])
+
+
+def test_tiled_close_to_pooled(pair):
+    from paper_2412_12506_amd import ldgmg as L
+    case, prec, sv = pair
+    p, t = sv["pooled"], sv["tiled"]
+    rng = np.random.default_rng(4)
+    for l in range(p.nlevels):
+        info = L.ldgmg_level_info(p.handle, l)
+        N = info["nelem"] * p.bs
+        xn = rng.standard_normal(N)
+        x = torch.from_numpy(xn).cuda()
+        bottom = l == p.nlevels - 1
+        A = abs(L.export_bsr(p.handle, l, "A").tocsr())
+        S = None if bottom else abs(L.export_bsr(p.handle, l, "S").tocsr())
+        for op, M in [("apply_a", A)] + ([] if bottom else [("apply_s", S), ("apply_st", S.T.tocsr())]):
+            outs = []
+            for s in (p, t):
+                o = torch.empty_like(x)
+                L.ldgmg_level_op(s.handle, l, op, x, None, o)
+                torch.cuda.synchronize()
+                outs.append(o.cpu().numpy())
+            # the same FP64 products summed in another order: a few hundred
+            # terms per row, each sum within (terms) u64 of |M||x|
+            mag = np.max(M @ np.abs(xn))
+            err = np.max(np.abs(outs[0] - outs[1]))
+            assert err <= 1e-13 * mag, (l, op, err, mag)
+    b = torch.from_numpy(_rhs(case, p, 22)).cuda()
+    krylov = case.get("krylov", "cg")
+    res = []
+    for s in (p, t):
+        x = torch.empty_like(b)
+        info = L.ldgmg_solve(s.handle, b, x, krylov, 1e-10, 200)
+        torch.cuda.synchronize()
+        res.append((info, x))
+    assert res[0][0]["converged"] and res[1][0]["converged"]
+    assert abs(res[0][0]["iters"] - res[1][0]["iters"]) <= 1
+    rel = float(torch.linalg.norm(res[0][1] - res[1][1]) / torch.linalg.norm(res[0][1]))
+    assert rel <= 1e-8, rel
