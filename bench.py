@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 METRIC = "V-cycle DOF/s & solves/s to 1e-10 rel. residual (FP32 vs FP64); p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TF = 78.6      # MI355X FP64 vector (FMA) peak
+FP64_MFMA_PEAK_TF = 78.6        # MI355X dense FP64 matrix-core peak
 
 
 def log(*a):
@@ -110,6 +111,7 @@ def run_path(L, torch, args, precision, rhs, prof, storage="auto"):
             nnzb = info0["nnzb_A"] if kind in ("A", "A64") else info0["nnzb_S"]
             ebk = 8 if kind == "A64" else eb_a if kind == "A" else eb_s
             pool = storage["pool_A"] if kind in ("A", "A64") else storage["pool_S"]
+            tiled = storage["tiled_A"] if kind in ("A", "A64") else storage["tiled_S"]
             # algorithmic HBM bytes per launch: the stored blocks (expanded: every
             # slot's block; pooled: the distinct blocks once plus a 4-byte block
             # id per slot) + block indices + vectors (FP64 input read, FP64 added
@@ -121,7 +123,7 @@ def run_path(L, torch, args, precision, rhs, prof, storage="auto"):
             flops = 2 * nnzb * bs * bs          # one FP64 FMA per stored entry
             mean_s = ms / cnt / 1e3 if cnt else None
             kinds[kind] = {"count": cnt, "ms_total": ms, "bytes_per_launch": byts, "flops_per_launch": flops,
-                           "pooled": bool(pool), "mean_ms": ms / cnt if cnt else None,
+                           "pooled": bool(pool), "tiled": bool(tiled), "mean_ms": ms / cnt if cnt else None,
                            "gbs": byts / mean_s / 1e9 if cnt else None,
                            "tflops": flops / mean_s / 1e12 if cnt else None}
         out["kernels"] = kinds
@@ -132,20 +134,33 @@ def run_path(L, torch, args, precision, rhs, prof, storage="auto"):
     return out
 
 
-def counter_traffic(pooled=False):
+def kernel_source(kernel):
+    """Source text of a kernel family in kernels.hip (what the counter
+    summaries are keyed on): the forward kernels (k_bsr_fwd and its
+    multi-right-hand-side form) or the tiled kernel with its layout helpers."""
+    src = open(os.path.join(ROOT, "paper_2412_12506_amd", "csrc", "kernels.hip")).read()
+    sep = "// ---------------------------------------------------------------------------\n"
+    if kernel == "tiled":
+        a = src.index(sep + "// tiled forward BSR kernel")
+        b = src.index("// generic BSR kernel for any block size")
+    else:
+        a = src.rindex("template <", 0, src.index("void k_bsr_fwd("))
+        b = src.index(sep + "// transposed BSR kernel")
+    return src[a:b]
+
+
+def counter_traffic(storage="expanded"):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, if that summary was taken with the current kernel source
     (None otherwise)."""
     import hashlib
-    name = "bsr_fwd_fp32_pooled_bs64" if pooled else "bsr_fwd_fp32_bs64"
+    name = {"expanded": "bsr_fwd_fp32_bs64", "pooled": "bsr_fwd_fp32_pooled_bs64",
+            "tiled": "bsr_tiled_fp32_bs64"}[storage]
     prof = os.path.join(ROOT, "profiles", f"{name}_poisson3d_n64_counters.json")
-    src_path = os.path.join(ROOT, "paper_2412_12506_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(prof))
-        src = open(src_path).read()
-        a = src.rindex("template <", 0, src.index("void k_bsr_fwd("))
-        b = src.index("// ---------------------------------------------------------------------------\n// transposed BSR kernel")
-        if hashlib.sha256(src[a:b].encode()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
+        text = kernel_source("tiled" if storage == "tiled" else "fwd")
+        if hashlib.sha256(text.encode()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
             return None
         return rec["traffic_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
@@ -322,29 +337,39 @@ def main():
     k = hp["kernels"]
     # dominant kernel: the fine-level forward BSR apply of A with FP32 blocks
     # (with FP32 smoother storage the B applies run the same instantiation)
-    dom = ("A", "S") if head == "fp32" and k["A"]["pooled"] == k["S"]["pooled"] else ("A",)
+    dom = ("A", "S") if head == "fp32" and (k["A"]["pooled"], k["A"]["tiled"]) == (k["S"]["pooled"], k["S"]["tiled"]) \
+        else ("A",)
     cnt = sum(k[d]["count"] for d in dom)
     ms = sum(k[d]["ms_total"] for d in dom)
     byts = sum(k[d]["bytes_per_launch"] * k[d]["count"] for d in dom) / max(cnt, 1)
     flops = sum(k[d]["flops_per_launch"] * k[d]["count"] for d in dom) / max(cnt, 1)
     mean_s = ms / max(cnt, 1) / 1000.0
-    pooled = k["A"]["pooled"]
+    pooled, tiled = k["A"]["pooled"], k["A"]["tiled"]
     name = f"k_bsr_fwd<fp32 blocks, fp64 vectors, bs=64, {'pooled' if pooled else 'expanded'}> (fine level)"
-    if pooled:
+    if tiled:
+        # pooled blocks applied on the FP64 matrix cores: priced against the
+        # FP64 MFMA peak (2 flops per stored entry and row)
+        name = "k_bsr_tiled<fp32 blocks, bs=64> (fine level, v_mfma_f64_16x16x4f64)"
+        achieved = flops / mean_s / 1e12 if cnt else None
+        roof = {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": FP64_MFMA_PEAK_TF,
+                "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TF if achieved else None,
+                "traffic": counter_traffic("tiled"), "hbm_gbs": byts / mean_s / 1e9 if cnt else None,
+                "flops_per_launch": flops}
+    elif pooled:
         # blocks come from the caches; each stored entry costs a widening and an
         # FP64 FMA on the vector ALUs: priced against the FP64 vector peak
         achieved = flops / mean_s / 1e12 if cnt else None
         roof = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": FP64_VECTOR_PEAK_TF,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TF if achieved else None,
-                "traffic": counter_traffic(pooled=True), "hbm_gbs": byts / mean_s / 1e9 if cnt else None,
+                "traffic": counter_traffic("pooled"), "hbm_gbs": byts / mean_s / 1e9 if cnt else None,
                 "flops_per_launch": flops}
     else:
         achieved = byts / mean_s / 1e9 if cnt else None
         roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": counter_traffic(pooled=False)}
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": counter_traffic("expanded")}
     roof.update({"launches": cnt, "mean_ms": ms / max(cnt, 1), "bytes_per_launch": byts,
                  "other_kernels": {kk: {"mean_ms": v["mean_ms"], "gbs": v["gbs"], "tflops": v["tflops"],
-                                        "count": v["count"], "pooled": v["pooled"],
+                                        "count": v["count"], "pooled": v["pooled"], "tiled": v["tiled"],
                                         "bytes_per_launch": v["bytes_per_launch"]}
                                    for kk, v in k.items() if kk not in dom}})
     summary = ("vcycle_dof_per_s", "solves_per_s", "ms_per_solve", "p50_ms", "p99_ms", "iters",
@@ -362,7 +387,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "block_storage": ("A f32, SAI B bf16" if head == "bf16s" else "f32")
-                         + (", pooled" if k["A"]["pooled"] else ", expanded"),
+                         + (", tiled" if k["A"]["tiled"] else ", pooled" if k["A"]["pooled"] else ", expanded"),
         "data": "synthetic",
         "config": {"workload": f"poisson3d_p{args.p}_n{args.n}_sai1_oi_cg",
                    "fine_dofs": ndofs, "rtol": 1e-10, "rhs": "N(0,1) seeded",

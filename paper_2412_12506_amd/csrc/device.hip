@@ -44,6 +44,7 @@ struct StateError : std::runtime_error {
 struct Tiled {
   const void* blk = nullptr;        // pool in the operand layout of the tiled kernel
   int* tab = nullptr;               // [rows][noff] pool ids, -1 where no block
+  int* perm = nullptr;              // rows ordered by their row of tab
   int* off = nullptr;               // column offsets
   int noff = 0;
 };
@@ -168,16 +169,66 @@ std::vector<int> column_offsets(const PMat& P) {
 }
 
 constexpr int kMaxTiledOffsets = 64;
+constexpr int kMinTiledRows = 16384;      // 1024 tiles: enough to fill the device
+constexpr double kMaxTiledPasses = 1.5;   // mean MFMA passes per tile and offset
 
-// tiled storage (on top of pooled) for a matrix: TILED, or AUTO when pooled
+// pool-id table [row][offset] of a matrix and its rows ordered by table row
+// (stable, so that rows with equal blocks at every offset are side by side)
+void tiled_table(const PMat& P, const std::vector<int>& off, std::vector<int>& tab, std::vector<int>& perm) {
+  const int noff = static_cast<int>(off.size());
+  tab.assign(static_cast<size_t>(P.nbr) * noff, -1);
+  for (int i = 0; i < P.nbr; ++i)
+    for (int s2 = P.rp[i]; s2 < P.rp[i + 1]; ++s2) {
+      const int d = static_cast<int>(std::lower_bound(off.begin(), off.end(), P.ci[s2] - i) - off.begin());
+      tab[static_cast<size_t>(i) * noff + d] = P.id[s2];
+    }
+  perm.resize(P.nbr);
+  for (int i = 0; i < P.nbr; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+    return std::lexicographical_compare(tab.begin() + static_cast<size_t>(a) * noff,
+                                        tab.begin() + static_cast<size_t>(a + 1) * noff,
+                                        tab.begin() + static_cast<size_t>(b) * noff,
+                                        tab.begin() + static_cast<size_t>(b + 1) * noff);
+  });
+}
+
+// mean number of MFMA passes (distinct blocks) per 16-row tile and offset
+double tiled_passes(const PMat& P) {
+  if (P.tile_passes >= 0.0) return P.tile_passes;
+  const std::vector<int> off = column_offsets(P);
+  std::vector<int> tab, perm;
+  tiled_table(P, off, tab, perm);
+  const int noff = static_cast<int>(off.size());
+  long long passes = 0, slots = 0;
+  std::vector<int> ids;
+  for (int t0 = 0; t0 < P.nbr; t0 += 16)
+    for (int d = 0; d < noff; ++d) {
+      ids.clear();
+      for (int c = t0; c < std::min(P.nbr, t0 + 16); ++c) {
+        const int v = tab[static_cast<size_t>(perm[c]) * noff + d];
+        if (v >= 0) ids.push_back(v);
+      }
+      std::sort(ids.begin(), ids.end());
+      passes += std::unique(ids.begin(), ids.end()) - ids.begin();
+      slots += 1;
+    }
+  P.tile_passes = slots ? static_cast<double>(passes) / slots : 0.0;
+  return P.tile_passes;
+}
+
+// tiled storage (on top of pooled) for a matrix: TILED; or AUTO when pooled,
+// large enough to fill the device and with few distinct blocks per tile
 bool use_tiled(const PMat& P, int bs, size_t elem, int storage) {
   if (storage != LDGMG_STORE_TILED && storage != LDGMG_STORE_AUTO) return false;
   if (!use_pool(P, bs, elem, storage)) return false;
-  return static_cast<int>(column_offsets(P).size()) <= kMaxTiledOffsets;
+  if (static_cast<int>(column_offsets(P).size()) > kMaxTiledOffsets) return false;
+  if (storage == LDGMG_STORE_TILED) return true;
+  return P.nbr >= kMinTiledRows && tiled_passes(P) <= kMaxTiledPasses;
 }
 
 // device bytes of one matrix's blocks (and block ids when pooled, and the
-// operand-layout pool and offset table when tiled)
+// operand-layout pool and offset table when tiled).  The transposed copy of a
+// smoother matrix follows the smoother matrix's choices.
 size_t matrix_bytes(const PMat& P, int bs, size_t elem, int storage) {
   const size_t bb = static_cast<size_t>(bs) * bs * elem;
   if (!use_pool(P, bs, elem, storage)) return static_cast<size_t>(P.nnzb()) * bb;
@@ -186,6 +237,7 @@ size_t matrix_bytes(const PMat& P, int bs, size_t elem, int storage) {
     const size_t noff = column_offsets(P).size();
     b += static_cast<size_t>(P.pool.size()) * tiled_block_elems(bs) * elem;
     b += static_cast<size_t>(P.nbr) * noff * sizeof(int) + std::max<size_t>(16, noff * sizeof(int));
+    b += std::max<size_t>(16, static_cast<size_t>(P.nbr) * sizeof(int));            // row order
   }
   return b;
 }
@@ -215,14 +267,14 @@ template <typename T>
 void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, Tiled& t, hipStream_t st) {
   const std::vector<int> off = column_offsets(P);
   const int noff = static_cast<int>(off.size());
-  std::vector<int> tab(static_cast<size_t>(P.nbr) * noff, -1);
-  for (int i = 0; i < P.nbr; ++i)
-    for (int s2 = P.rp[i]; s2 < P.rp[i + 1]; ++s2) {
-      const int d = static_cast<int>(std::lower_bound(off.begin(), off.end(), P.ci[s2] - i) - off.begin());
-      tab[static_cast<size_t>(i) * noff + d] = P.id[s2];
-    }
+  // rows with equal blocks at every offset side by side (stable: interior rows
+  // keep their grid order), so that a 16-row tile needs one pass per offset
+  std::vector<int> tab, perm;
+  tiled_table(P, off, tab, perm);
   const long long nd = P.pool.size();
   T* blk = static_cast<T*>(D.alloc(static_cast<size_t>(nd) * tiled_block_elems(bs) * sizeof(T)));
+  t.perm = static_cast<int*>(D.alloc(std::max<size_t>(16, perm.size() * sizeof(int))));
+  HIPCHK(hipMemcpyAsync(t.perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, st));
   t.tab = static_cast<int*>(D.alloc(tab.size() * sizeof(int)));
   t.off = static_cast<int*>(D.alloc(std::max<size_t>(16, off.size() * sizeof(int))));
   HIPCHK(hipMemcpyAsync(t.tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, st));
@@ -255,10 +307,10 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
   // device blocks of type T for a pooled host matrix (transposed blocks if
   // asked): every slot's block (expanded), or the distinct blocks once with
   // the block id of every slot in `bid` (pooled; bid stays null otherwise)
-  auto place = [&](auto tag, const PMat& P, bool transpose, int*& bid, Tiled& tiled) {
+  auto place = [&](auto tag, const PMat& P, bool transpose, int*& bid, Tiled& tiled, bool want_tiled) {
     using T = decltype(tag);
     const bool pooled = use_pool(P, hl.bs, sizeof(T), storage);
-    if (use_tiled(P, hl.bs, sizeof(T), storage)) make_tiled<T>(D, P, hl.bs, transpose, tiled, st);
+    if (want_tiled) make_tiled<T>(D, P, hl.bs, transpose, tiled, st);
     const int nd = P.pool.size();
     std::vector<int> order;
     if (pooled) {
@@ -283,13 +335,14 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
   dl.nnzA = hl.A.nnzb();
   dl.rpA = up_ints(hl.A.rp);
   dl.ciA = up_ints(hl.A.ci);
-  dl.valA = place(TA{}, hl.A, false, dl.bidA, dl.tA);
+  dl.valA = place(TA{}, hl.A, false, dl.bidA, dl.tA, use_tiled(hl.A, hl.bs, sizeof(TA), storage));
   if (!bottom) {
     dl.nnzS = hl.S.nnzb();
     dl.rpS = up_ints(hl.S.rp);
     dl.ciS = up_ints(hl.S.ci);
     dl.tposS = up_ints(hl.tpos);
-    dl.valS = place(TS{}, hl.S, false, dl.bidS, dl.tS);
+    const bool tiled_S = use_tiled(hl.S, hl.bs, sizeof(TS), storage);
+    dl.valS = place(TS{}, hl.S, false, dl.bidS, dl.tS, tiled_S);
     if (fast_bs(hl.bs)) {   // S^T applies stream a transposed copy through the forward kernel
       PMat st;
       st.nbr = hl.S.nbr;
@@ -301,7 +354,7 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
       st.pool.r = hl.S.pool.r;
       st.pool.c = hl.S.pool.c;
       st.pool.data = hl.S.pool.data;
-      dl.valST = place(TS{}, st, true, dl.bidST, dl.tST);
+      dl.valST = place(TS{}, st, true, dl.bidST, dl.tST, tiled_S);
     }
     for (const auto& rows : hl.colour_rows) {
       dl.colour_rows.push_back(up_ints(rows));
@@ -475,6 +528,7 @@ template <typename T>
 void set_tiled(BsrArgs<T, Vd>& a, const Tiled& t) {
   a.tblk = static_cast<const T*>(t.blk);
   a.tab = t.tab;
+  a.tperm = t.perm;
   a.toff = t.off;
   a.noff = t.noff;
 }

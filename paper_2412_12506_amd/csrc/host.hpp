@@ -49,6 +49,7 @@ struct PMat {
   int nbr = 0, nbc = 0;
   std::vector<int> rp, ci, id;
   Pool pool;
+  mutable double tile_passes = -1.0;   // cache of the device's tiling estimate (< 0: not computed)
   int nnzb() const { return static_cast<int>(ci.size()); }
   int slot(int i, int j) const;     // -1 if (i, j) is not stored
   const double* block(int s) const { return pool.at(id[s]); }

@@ -386,11 +386,13 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 // ---------------------------------------------------------------------------
 // tiled forward BSR kernel on the FP64 matrix cores: out = alpha M x + beta z
 // for a pooled matrix addressed by column offset.  tab[row * noff + d] is the
-// pool id of block (row, row + off[d]) or -1.  A wavefront takes the 16 block
-// rows e0 .. e0 + 15 as the columns of an MFMA tile; for each offset it groups
-// them by block id and accumulates Y(bs x 16) += B(bs x bs) X(bs x 16), column
-// c of X being the x block of row e0 + c + off[d] (zero for rows outside the
-// group), with v_mfma_f64_16x16x4f64: products and sums in FP64.
+// pool id of block (row, row + off[d]) or -1; perm lists the block rows ordered
+// by their row of tab (rows with the same blocks are adjacent).  A wavefront
+// takes the 16 block rows perm[e0 .. e0 + 15] as the columns of an MFMA tile;
+// for each offset it groups them by block id and accumulates
+// Y(bs x 16) += B(bs x bs) X(bs x 16), column c of X being the x block of the
+// column's row + off[d] (zero for rows outside the group), with
+// v_mfma_f64_16x16x4f64: products and sums in FP64.
 // Pool layout (MT = ceil(bs/16) row tiles, KS = ceil(bs/4) k steps): entry
 // [block][m][lane][s] = B(16 m + lane % 16, (lane / 16) KS + s), zero outside
 // the block, so that lane l reads the KS operands of its k range contiguously.
@@ -399,9 +401,30 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// KS consecutive stored entries, widened to FP64: 16-byte loads when KS fills
+// whole vectors (the tiled pool keeps each lane's run 16-byte aligned)
+template <typename TM, int KS>
+__device__ __forceinline__ void load_widen(const TM* p, double (&out)[KS]) {
+  constexpr int E = 16 / static_cast<int>(sizeof(TM));
+  if constexpr (KS % E == 0) {
+    using VT = typename VecT<TM, E>::type;
+    const VT* v = reinterpret_cast<const VT*>(p);
+#pragma unroll
+    for (int q = 0; q < KS / E; ++q) {
+      const VT w = v[q];
+#pragma unroll
+      for (int e = 0; e < E; ++e) out[q * E + e] = static_cast<double>(elem(w, e));
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) out[s] = static_cast<double>(widen(p[s]));
+  }
+}
+
 template <typename TM, int BS>
 __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
                                                         const int* __restrict__ tab,
+                                                        const int* __restrict__ perm,
                                                         const TM* __restrict__ blk, const double* x,
                                                         const double* z, double* out, double alpha,
                                                         double beta) {
@@ -411,9 +434,9 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   const int e0 = tile * 16;
   if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
   const int col = lane & 15, kq = lane >> 4;
-  const int row = e0 + col;
-  const bool rv = row < nrows;
-  const int rowc = rv ? row : e0;
+  const bool rv = e0 + col < nrows;
+  const int row = perm[rv ? e0 + col : e0];
+  const int rowc = row;
   v4d acc[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) acc[m] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -429,21 +452,30 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const bool use = (sel >> col) & 1ull;
       const double* xp = x + static_cast<size_t>(use ? row + o : 0) * BS;
       double xb[KS];
+      if constexpr (4 * KS == BS && KS % 2 == 0) {    // no padding: 16-byte loads
+        const double2* x2 = reinterpret_cast<const double2*>(xp + kq * KS);
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int c = kq * KS + s;
-        const double v = xp[c < BS ? c : 0];
-        xb[s] = (use && c < BS) ? v : 0.0;
+        for (int q = 0; q < KS / 2; ++q) {
+          const double2 v = x2[q];
+          xb[2 * q] = use ? v.x : 0.0;
+          xb[2 * q + 1] = use ? v.y : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int c = kq * KS + s;
+          const double v = xp[c < BS ? c : 0];
+          xb[s] = (use && c < BS) ? v : 0.0;
+        }
       }
       const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(lane) * KS;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        TM a[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) a[s] = bp[m * 64 * KS + s];
+        double a[KS];
+        load_widen<TM, KS>(bp + m * 64 * KS, a);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
-          acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(widen(a[s])), xb[s], acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xb[s], acc[m], 0, 0, 0);
       }
       rem &= ~sel;
     }
@@ -881,8 +913,8 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
   const long long tiles = (a.nrows + 15) / 16;
   const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
   if (blocks == 0) return;
-  k_bsr_tiled<TM, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tblk, a.x, a.z, a.out,
-                                                   a.alpha, a.beta);
+  k_bsr_tiled<TM, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z,
+                                                   a.out, a.alpha, a.beta);
   check_launch("bsr_tiled");
 }
 

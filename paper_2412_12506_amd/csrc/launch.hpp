@@ -48,6 +48,7 @@ struct BsrArgs {
   // column offsets and the [nrows][noff] table of pool ids (-1: no block)
   const TM* tblk = nullptr;
   const int* tab = nullptr;
+  const int* tperm = nullptr; // block rows ordered by their row of tab
   const int* toff = nullptr;
   int noff = 0;
   T omega = T(1);
