@@ -429,6 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
                                                         const double* z, double* out, double alpha,
                                                         double beta) {
   constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
+  constexpr int MG = sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
   const int lane = threadIdx.x & 63;
   const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int e0 = tile * 16;
@@ -469,13 +470,19 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
         }
       }
       const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(lane) * KS;
+      // MG row tiles at a time: their operands are loaded first and their
+      // independent accumulations interleaved, so no MFMA waits on the last
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        double a[KS];
-        load_widen<TM, KS>(bp + m * 64 * KS, a);
+      for (int m0 = 0; m0 < MT; m0 += MG) {
+        double a[MG][KS];
+#pragma unroll
+        for (int g = 0; g < MG; ++g)
+          if (m0 + g < MT) load_widen<TM, KS>(bp + (m0 + g) * 64 * KS, a[g]);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
-          acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xb[s], acc[m], 0, 0, 0);
+#pragma unroll
+          for (int g = 0; g < MG; ++g)
+            if (m0 + g < MT) acc[m0 + g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[g][s], xb[s], acc[m0 + g], 0, 0, 0);
       }
       rem &= ~sel;
     }
