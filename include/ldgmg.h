@@ -131,6 +131,16 @@ int ldgmg_estimate_bytes(const ldgmg_problem* p, size_t* bytes);
  * *out receives a new handle owning all host data. */
 int ldgmg_setup_host(const ldgmg_problem* p, ldgmg_handle* out);
 
+/* A new host hierarchy for problem p built from src: src's operators on every
+ * level, transfers and bottom pseudo-inverse are copied and only the smoother
+ * of p (smoother, sai_level, order, nu1, nu2, omega, zeta) is built; precision,
+ * storage, nthreads and hbm_budget are taken from p.  p must describe the same
+ * discrete problem as src (dim, n, p, basis, system, gamma, bc, tau0, cp and
+ * equal viscosity values), else LDGMG_EINVAL.  Needs no GPU; src is unchanged.
+ * For switching smoothers without repeating the assembly and the bottom
+ * eigendecomposition. */
+int ldgmg_rebuild_smoother(ldgmg_handle src, const ldgmg_problem* p, ldgmg_handle* out);
+
 /* Copy a host-built hierarchy to the current HIP device (allocating with
  * hipMalloc) in the handle's precision; fails with LDGMG_ENOMEM above the
  * problem's hbm_budget. */

@@ -280,11 +280,11 @@ void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, Tiled& t, hip
   HIPCHK(hipMemcpyAsync(t.tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(t.off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, st));
   double* pool = nullptr;
-  HIPCHK(hipMalloc(&pool, std::max<size_t>(16, P.pool.data.size() * sizeof(double))));
+  HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&pool), std::max<size_t>(16, P.pool.data.size() * sizeof(double)), st));
   HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
   expand_tiled<T>(nd, bs, pool, blk, transpose, st);
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(hipFree(pool));
+  HIPCHK(hipFreeAsync(pool, st));
+  HIPCHK(hipStreamSynchronize(st));   // the host tables above must outlive their copies
   t.blk = blk;
   t.noff = noff;
 }
@@ -321,14 +321,14 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
     T* out = static_cast<T*>(D.alloc(ids_h.size() * bb * sizeof(T)));
     double* pool = nullptr;
     int* ids = nullptr;
-    HIPCHK(hipMalloc(&pool, std::max<size_t>(16, P.pool.data.size() * sizeof(double))));
-    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, ids_h.size() * sizeof(int))));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&pool), std::max<size_t>(16, P.pool.data.size() * sizeof(double)), st));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&ids), std::max<size_t>(16, ids_h.size() * sizeof(int)), st));
     HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ids, ids_h.data(), ids_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
     expand_blocks<T>(static_cast<long long>(ids_h.size()), hl.bs, ids, pool, out, transpose, st);
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipFree(pool));
-    HIPCHK(hipFree(ids));
+    HIPCHK(hipFreeAsync(pool, st));   // stream-ordered: no device-wide synchronisation
+    HIPCHK(hipFreeAsync(ids, st));
+    HIPCHK(hipStreamSynchronize(st));  // the host id list must outlive its copy
     bid = pooled ? up_ints(P.id) : nullptr;
     return out;
   };
@@ -462,8 +462,8 @@ void upload(ldgmg_hier* h, hipStream_t st) {
     D->bid64 = f.bidA;
     double* pool = nullptr;
     int* ids = nullptr;
-    HIPCHK(hipMalloc(&pool, std::max<size_t>(16, F.A.pool.data.size() * sizeof(double))));
-    HIPCHK(hipMalloc(&ids, std::max<size_t>(16, ids_h.size() * sizeof(int))));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&pool), std::max<size_t>(16, F.A.pool.data.size() * sizeof(double)), st));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&ids), std::max<size_t>(16, ids_h.size() * sizeof(int)), st));
     HIPCHK(hipMemcpyAsync(pool, F.A.pool.data.data(), F.A.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ids, ids_h.data(), ids_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
     expand_blocks<double>(static_cast<long long>(ids_h.size()), F.bs, ids, pool, D->val64, false, st);
@@ -474,9 +474,9 @@ void upload(ldgmg_hier* h, hipStream_t st) {
       D->t64 = f.tA;
       D->t64.blk = tb;
     }
+    HIPCHK(hipFreeAsync(pool, st));   // stream-ordered: no device-wide synchronisation
+    HIPCHK(hipFreeAsync(ids, st));
     HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipFree(pool));
-    HIPCHK(hipFree(ids));
     D->own64 = true;
   }
   const size_t vb = static_cast<size_t>(f.N) * sizeof(double);
@@ -985,6 +985,7 @@ void apply_S_multi(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, 
   if (transposed) {
     a.blk = static_cast<const T*>(L.valST);
     a.bid = L.bidST;
+    set_tiled(a, L.tST);
   }
   if (rows) {
     a.nrows = nrows;
@@ -1336,6 +1337,17 @@ int ldgmg_setup_host(const ldgmg_problem* p, ldgmg_handle* out) {
     *out = nullptr;
     auto h = std::make_unique<ldgmg_hier>();
     h->host = build_host(*p);
+    *out = h.release();
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_rebuild_smoother(ldgmg_handle src, const ldgmg_problem* p, ldgmg_handle* out) {
+  return guarded([&] {
+    if (!src || !src->host || !p || !out) throw std::invalid_argument("null argument");
+    *out = nullptr;
+    auto h = std::make_unique<ldgmg_hier>();
+    h->host = rebuild_smoother(*src->host, *p);
     *out = h.release();
     return LDGMG_OK;
   });

@@ -1016,6 +1016,67 @@ void build_bottom(HostLevel& L) {
 
 }  // namespace
 
+namespace {
+
+// smoother of one non-bottom level from its assembled A (Sections 2.3, 3.3)
+void build_smoother(HostLevel& L, const ldgmg_problem& pr, double zeta) {
+  if (pr.smoother == LDGMG_SMOOTH_SAI) {
+    build_sai(L, pr.sai_level, pr.system, zeta);
+  } else {
+    build_block_inverse(L);
+    if (pr.smoother == LDGMG_SMOOTH_GS) build_colours(L);
+  }
+}
+
+double default_omega(const ldgmg_problem& pr) {
+  return pr.omega > 0 ? pr.omega : (pr.smoother == LDGMG_SMOOTH_JACOBI ? 0.8 : 1.0);
+}
+
+double default_zeta(const ldgmg_problem& pr) {
+  if (pr.zeta > 0) return pr.zeta;
+  static const double tz[2][2][5] = {{{0.0382, 0.131, 0.0990, 0.153, 0.142}, {0.0462, 0.107, 0.113, 0.113, 0.113}},
+                                     {{0.118, 0.131, 0.0814, 0.123, 0.0745}, {0.0384, 0.0928, 0.0930, 0.0930, 0.0930}}};
+  return tz[pr.gamma ? 1 : 0][pr.dim - 2][pr.p - 1];
+}
+
+}  // namespace
+
+std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const ldgmg_problem& pr) {
+  validate_problem(pr);
+  const ldgmg_problem& q = src.prob;
+  bool same = pr.dim == q.dim && pr.n == q.n && pr.p == q.p && pr.basis == q.basis && pr.system == q.system &&
+              pr.gamma == q.gamma && pr.tau0 == q.tau0 && pr.cp == q.cp;
+  for (int f = 0; f < 6; ++f) same = same && pr.bc[f] == q.bc[f];
+  if (same) {
+    for (size_t e = 0; e < src.mu.size(); ++e)
+      if ((pr.mu ? pr.mu[e] : 1.0) != src.mu[e]) {
+        same = false;
+        break;
+      }
+  }
+  if (!same) throw std::invalid_argument("rebuild_smoother: the problem differs from the source hierarchy's");
+  const auto t0 = std::chrono::steady_clock::now();
+  g_threads = pr.nthreads > 0 ? pr.nthreads : std::max(1u, std::thread::hardware_concurrency());
+  auto H = std::make_unique<HostHierarchy>(src);   // operators, transfers, bottom pseudo-inverse
+  H->prob = pr;
+  H->prob.mu = nullptr;
+  H->omega = default_omega(pr);
+  H->zeta = default_zeta(pr);
+  for (size_t l = 0; l + 1 < H->levels.size(); ++l) {
+    HostLevel& L = H->levels[l];
+    const auto tl = std::chrono::steady_clock::now();
+    L.S = PMat{};
+    L.tpos.clear();
+    L.colour_rows.clear();
+    L.ncolours = 0;
+    L.sai_unique = L.sai_qr = 0;
+    build_smoother(L, pr, H->zeta);
+    L.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
+  }
+  H->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return H;
+}
+
 std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
   validate_problem(pr);
   const auto t0 = std::chrono::steady_clock::now();
@@ -1028,14 +1089,8 @@ std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
   for (int k = 0; k < d; ++k) ne0 *= pr.n;
   H->mu.assign(ne0, 1.0);
   if (pr.mu) std::copy(pr.mu, pr.mu + ne0, H->mu.begin());
-  H->omega = pr.omega > 0 ? pr.omega : (pr.smoother == LDGMG_SMOOTH_JACOBI ? 0.8 : 1.0);
-  if (pr.zeta > 0) {
-    H->zeta = pr.zeta;
-  } else {
-    static const double tz[2][2][5] = {{{0.0382, 0.131, 0.0990, 0.153, 0.142}, {0.0462, 0.107, 0.113, 0.113, 0.113}},
-                                       {{0.118, 0.131, 0.0814, 0.123, 0.0745}, {0.0384, 0.0928, 0.0930, 0.0930, 0.0930}}};
-    H->zeta = tz[pr.gamma ? 1 : 0][d - 2][pr.p - 1];
-  }
+  H->omega = default_omega(pr);
+  H->zeta = default_zeta(pr);
   const std::vector<int> sizes = level_sizes(pr.n);
   const int ncomp = pr.system == LDGMG_STOKES ? d + 1 : 1;
   std::vector<GridInfo> grids;
@@ -1078,11 +1133,8 @@ std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
     const bool bottom = l + 1 == sizes.size();
     if (bottom) {
       build_bottom(L);
-    } else if (pr.smoother == LDGMG_SMOOTH_SAI) {
-      build_sai(L, pr.sai_level, pr.system, H->zeta);
     } else {
-      build_block_inverse(L);
-      if (pr.smoother == LDGMG_SMOOTH_GS) build_colours(L);
+      build_smoother(L, pr, H->zeta);
     }
     L.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
   }

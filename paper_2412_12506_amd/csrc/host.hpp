@@ -97,6 +97,12 @@ struct HostHierarchy {
 // Throws std::runtime_error / std::invalid_argument on failure.
 std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& prob);
 
+// A hierarchy for prob that keeps src's operators, transfers and bottom
+// pseudo-inverse and builds only the smoother of prob; prob must describe the
+// same discrete problem as src (geometry, basis, system, penalties and the same
+// viscosity values), else std::invalid_argument.
+std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const ldgmg_problem& prob);
+
 // q-point Gauss-Legendre rule on [-1, 1] (ascending nodes)
 void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w);
 // values (v) and derivatives (dv) of the 1-D basis functions psi_0..psi_p at t

@@ -385,14 +385,17 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 
 // ---------------------------------------------------------------------------
 // tiled forward BSR kernel on the FP64 matrix cores: out = alpha M x + beta z
-// for a pooled matrix addressed by column offset.  tab[row * noff + d] is the
-// pool id of block (row, row + off[d]) or -1; perm lists the block rows ordered
-// by their row of tab (rows with the same blocks are adjacent).  A wavefront
-// takes the 16 block rows perm[e0 .. e0 + 15] as the columns of an MFMA tile;
-// for each offset it groups them by block id and accumulates
-// Y(bs x 16) += B(bs x bs) X(bs x 16), column c of X being the x block of the
-// column's row + off[d] (zero for rows outside the group), with
-// v_mfma_f64_16x16x4f64: products and sums in FP64.
+// for a pooled matrix addressed by column offset, for nk <= 8 right-hand sides
+// (vectors q at x + q stride, z + q stride, out + q stride).  tab[row * noff +
+// d] is the pool id of block (row, row + off[d]) or -1; perm lists the block
+// rows ordered by their row of tab (rows with the same blocks are adjacent).
+// The 16 columns of an MFMA tile are (row, right-hand side) pairs: with kp the
+// power of two >= nk, a wavefront takes the 16 / kp block rows
+// perm[e0 .. e0 + 16 / kp - 1] and column c = (row c / kp, vector c % kp).  For
+// each offset it groups the columns by block id and accumulates
+// Y(bs x 16) += B(bs x bs) X(bs x 16), column c of X being its vector's block at
+// the row + off[d] (zero outside the group), with v_mfma_f64_16x16x4f64:
+// products and sums in FP64.
 // Pool layout (MT = ceil(bs/16) row tiles, KS = ceil(bs/4) k steps): entry
 // [block][m][lane][s] = B(16 m + lane % 16, (lane / 16) KS + s), zero outside
 // the block, so that lane l reads the KS operands of its k range contiguously.
@@ -427,17 +430,19 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
                                                         const int* __restrict__ perm,
                                                         const TM* __restrict__ blk, const double* x,
                                                         const double* z, double* out, double alpha,
-                                                        double beta) {
+                                                        double beta, long long stride, int nk, int lkp) {
   constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
   constexpr int MG = sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
   const int lane = threadIdx.x & 63;
   const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int e0 = tile * 16;
+  const int e0 = tile * (16 >> lkp);        // 16 / kp block rows per tile
   if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
   const int col = lane & 15, kq = lane >> 4;
-  const bool rv = e0 + col < nrows;
-  const int row = perm[rv ? e0 + col : e0];
+  const int q = col & ((1 << lkp) - 1);     // right-hand side of this column
+  const bool rv = e0 + (col >> lkp) < nrows && q < nk;
+  const int row = perm[rv ? e0 + (col >> lkp) : e0];
   const int rowc = row;
+  const size_t qoff = static_cast<size_t>(rv ? q : 0) * stride;
   v4d acc[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) acc[m] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const int id = __shfl(myid, c0);
       const unsigned long long sel = __ballot(myid == id) & 0xFFFFull;
       const bool use = (sel >> col) & 1ull;
-      const double* xp = x + static_cast<size_t>(use ? row + o : 0) * BS;
+      const double* xp = x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0);
       double xb[KS];
       if constexpr (4 * KS == BS && KS % 2 == 0) {    // no padding: 16-byte loads
         const double2* x2 = reinterpret_cast<const double2*>(xp + kq * KS);
@@ -494,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
     for (int i = 0; i < 4; ++i) {
       const int r = 16 * m + kq + 4 * i;      // result layout of the MFMA
       if (r < BS) {
-        const size_t o = static_cast<size_t>(row) * BS + r;
+        const size_t o = qoff + static_cast<size_t>(row) * BS + r;
         out[o] = beta != 0.0 ? alpha * acc[m][i] + beta * z[o] : alpha * acc[m][i];
       }
     }
@@ -916,12 +921,15 @@ void launch_fwd_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
 }
 
 template <typename TM, typename T, int BS>
-void launch_tiled_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
-  const long long tiles = (a.nrows + 15) / 16;
+void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStream_t st) {
+  int lkp = 0;                              // log2 of the power of two >= nk
+  while ((1 << lkp) < nk) ++lkp;
+  const int rpt = 16 >> lkp;                // block rows per tile
+  const long long tiles = (a.nrows + rpt - 1) / rpt;
   const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
   if (blocks == 0) return;
   k_bsr_tiled<TM, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z,
-                                                   a.out, a.alpha, a.beta);
+                                                   a.out, a.alpha, a.beta, stride, nk, lkp);
   check_launch("bsr_tiled");
 }
 
@@ -969,7 +977,7 @@ void bsr_forward(const BsrArgs<TM, T>& a, hipStream_t st) {
       switch (a.bs) {
 #define CASE(B) \
   case B:       \
-    launch_tiled_bs<TM, T, B>(a, st); \
+    launch_tiled_bs<TM, T, B>(a, 0, 1, st); \
     return;
         LDGMG_FOR_BS(CASE)
 #undef CASE
@@ -1002,6 +1010,20 @@ template <typename TM, typename T>
 void bsr_forward_multi(const BsrArgs<TM, T>& a, long long stride, int nk, hipStream_t st) {
   if (nk < 1 || nk > kMaxRhs) throw std::invalid_argument("bsr_forward_multi: bad right-hand-side count");
   if (a.dinv) throw std::invalid_argument("bsr_forward_multi: no fused smoothing");
+  if constexpr (std::is_same<T, double>::value) {
+    if (a.tab && !a.rows) {                 // tiled storage: (row, vector) columns on the matrix cores
+      switch (a.bs) {
+#define CASE(B) \
+  case B:       \
+    launch_tiled_bs<TM, T, B>(a, stride, nk, st); \
+    return;
+        LDGMG_FOR_BS(CASE)
+#undef CASE
+        default:
+          throw std::runtime_error("tiled storage needs a block size with a wave-mapped kernel");
+      }
+    }
+  }
   switch (a.bs) {
 #define CASE(B) \
   case B:       \

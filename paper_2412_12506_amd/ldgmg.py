@@ -57,7 +57,8 @@ class LdgmgError(RuntimeError):
 
 _lib = None
 
-SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_upload",
+SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", "ldgmg_rebuild_smoother",
+           "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
            "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage", "ldgmg_destroy",
@@ -78,6 +79,7 @@ def lib():
     L.ldgmg_problem_default.argtypes = [C.POINTER(Problem)]
     L.ldgmg_estimate_bytes.argtypes = [C.POINTER(Problem), C.POINTER(C.c_size_t)]
     L.ldgmg_setup_host.argtypes = [C.POINTER(Problem), C.POINTER(H)]
+    L.ldgmg_rebuild_smoother.argtypes = [H, C.POINTER(Problem), C.POINTER(H)]
     L.ldgmg_upload.argtypes = [H, vp]
     L.ldgmg_setup.argtypes = [C.POINTER(Problem), vp, C.POINTER(H)]
     L.ldgmg_sizes.argtypes = [H, C.POINTER(C.c_longlong), ip, ip]
@@ -178,6 +180,12 @@ def ldgmg_estimate_bytes(problem: Problem) -> int:
 def ldgmg_setup_host(problem: Problem) -> int:
     h = C.c_void_p()
     _check(lib().ldgmg_setup_host(C.byref(problem), C.byref(h)))
+    return h.value
+
+
+def ldgmg_rebuild_smoother(src: int, problem: Problem) -> int:
+    h = C.c_void_p()
+    _check(lib().ldgmg_rebuild_smoother(src, C.byref(problem), C.byref(h)))
     return h.value
 
 
@@ -368,6 +376,15 @@ class Solver:
 
     def upload(self, stream=None):
         ldgmg_upload(self.handle, stream)
+
+    def resmoothed(self, **kw) -> "Solver":
+        """A host-only Solver for the same problem with another smoother (kw as
+        for the constructor), reusing this hierarchy's operators and bottom."""
+        new = Solver.__new__(Solver)
+        new.problem, new._mu = make_problem(**kw)
+        new.handle = ldgmg_rebuild_smoother(self.handle, new.problem)
+        new.ndofs, new.bs, new.nlevels = ldgmg_sizes(new.handle)
+        return new
 
     def unload(self):
         ldgmg_unload(self.handle)

@@ -21,12 +21,14 @@ Hierarchy cache, two tiers, keyed by the problem:
 Robustness: when a batch's CG solves with the SAI V-cycle do not converge (the
 engine enables the library's CG guard, which stops CG at once when the
 preconditioner shows it is not positive definite), the hierarchy of that
-problem is rebuilt with the coloured
-Gauss-Seidel smoother (the paper's second-ranked smoother) and the affected
-requests are queued again at the front; later requests of the key use it.
+problem is rebuilt with the coloured Gauss-Seidel smoother (the paper's
+second-ranked smoother; ldgmg_rebuild_smoother keeps the operators and the
+bottom) and the affected requests are queued again at the front; later
+requests of the key use it.
 
 Scheduling: several workers, each with its own HIP stream, take the key whose
-oldest waiting request is oldest among the keys not in use, and solve up to 8
+oldest waiting request is oldest among the keys not in use (ties: the most
+work first), and solve up to 8
 of its waiting requests together with ldgmg_solve_batch (each matrix block
 streamed once per V-cycle for the whole batch).  Requests that arrive while a
 batch runs join a later one, and batches of different hierarchies run on the
@@ -219,16 +221,21 @@ class ServingEngine:
     # -- scheduling ----------------------------------------------------------------
     def _pick(self):
         """Under the lock: the key (not in use, not being built) with the oldest
-        waiting request, and up to max_batch of its requests."""
-        best = None
+        waiting request (among equally old ones, the most work: unknowns times
+        waiting requests), and up to max_batch of its requests."""
+        def rank(key, q):
+            size = key[1] ** key[0] * (key[2] + 1) ** key[0] if isinstance(key, tuple) and len(key) == 4 else 1
+            return (q[0].arrival, -size * min(len(q), self.max_batch))
+        best, best_rank = None, None
         for key, q in self.waiting.items():
             if not q:
                 continue
             e = self.entries.get(key)
             if e is not None and (e.busy or e.building):
                 continue
-            if best is None or q[0].arrival < self.waiting[best][0].arrival:
-                best = key
+            r = rank(key, q)
+            if best is None or r < best_rank:
+                best, best_rank = key, r
         if best is None:
             return None, []
         q = self.waiting[best]
@@ -285,11 +292,17 @@ class ServingEngine:
                         e.resident = False
                         self.used -= e.bytes
                         e.bytes = 0
-                        e.solver, e.smoother = None, "gs"
+                        e.smoother = "gs"
                         e.fallbacks += 1
                         self.fallback_keys.append(key)
-                        self.waiting[key].extendleft(reversed(failed))
+                    # same operators and bottom, new smoother (the key stays busy meanwhile)
+                    new = old.resmoothed(nthreads=self.setup_threads,
+                                         **problem_kwargs(key, self.precision, "gs"))
+                    L.ldgmg_cg_guard(new.handle, True)
                     old.close()
+                    with self.cv:
+                        e.solver = new
+                        self.waiting[key].extendleft(reversed(failed))
             except Exception as ex:  # keep serving; report the failure
                 with self.cv:
                     self._reject(key, batch, str(ex))

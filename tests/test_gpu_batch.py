@@ -20,17 +20,22 @@ CASES = [
 ]
 
 
-def _precisions(case):
-    return ("fp64", "fp32", "bf16s") if case["smoother"] == "sai" else ("fp64", "fp32")
+def _variants(case):
+    """(precision, device storage): tiled storage runs the batched products on
+    the matrix cores, the others on the vector units."""
+    v = [("fp64", "auto"), ("fp32", "auto"), ("fp32", "tiled")]
+    if case["smoother"] == "sai":
+        v += [("bf16s", "auto"), ("bf16s", "tiled")]
+    return v
 
 
-@pytest.fixture(scope="module", params=[(c, pr) for c in CASES for pr in _precisions(c)],
-                ids=lambda cp: f"{cp[0]['id']}-{cp[1]}")
+@pytest.fixture(scope="module", params=[(c, pr, st) for c in CASES for pr, st in _variants(c)],
+                ids=lambda cp: f"{cp[0]['id']}-{cp[1]}-{cp[2]}")
 def built(request):
     from paper_2412_12506_amd import ldgmg as L
-    case, prec = request.param
-    print(f"\n[batch {case['id']} {prec}]", flush=True)
-    s = L.Solver(**lib_kwargs(case, prec))
+    case, prec, storage = request.param
+    print(f"\n[batch {case['id']} {prec} {storage}]", flush=True)
+    s = L.Solver(storage=storage, **lib_kwargs(case, prec))
     lv, vc = oracle_build(case)
     yield case, prec, s, lv, vc
     s.close()

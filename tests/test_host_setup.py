@@ -117,3 +117,30 @@ def test_upload_bytes_by_storage():
     assert got["expanded"] > nnz_a * 64 * 64 * 4
     assert got["pooled"] < got["expanded"] / 4
     assert got["pooled"] <= got["auto"] <= got["expanded"]
+
+
+def test_rebuild_smoother_matches_fresh_build():
+    """A GS hierarchy rebuilt from a SAI one (operators, transfers and bottom
+    kept) exports exactly what a fresh GS setup exports; another problem is
+    refused."""
+    from paper_2412_12506_amd import ldgmg as L
+    from ldg_inputs import mu_box
+    kw = dict(dim=2, n=8, p=2, mu=mu_box(2, 8, 1e4))
+    sai = L.Solver(host_only=True, smoother="sai", **kw)
+    fresh = L.Solver(host_only=True, smoother="gs", **kw)
+    rebuilt = sai.resmoothed(smoother="gs", **kw)
+    try:
+        assert rebuilt.nlevels == fresh.nlevels
+        for l in range(fresh.nlevels):
+            for what in ("A",) + (("S",) if l + 1 < fresh.nlevels else ()):
+                a, b = L.export_bsr(fresh.handle, l, what), L.export_bsr(rebuilt.handle, l, what)
+                assert (a != b).nnz == 0, (l, what)
+            if l + 1 < fresh.nlevels:
+                assert np.array_equal(L.ldgmg_export_colours(fresh.handle, l), L.ldgmg_export_colours(rebuilt.handle, l))
+        assert np.array_equal(L.ldgmg_export(fresh.handle, 0, "PINV"), L.ldgmg_export(rebuilt.handle, 0, "PINV"))
+        with pytest.raises(L.LdgmgError) as ei:
+            sai.resmoothed(smoother="gs", dim=2, n=8, p=2, mu=mu_box(2, 8, 1e3))
+        assert ei.value.code == L.EINVAL
+    finally:
+        for s in (sai, fresh, rebuilt):
+            s.close()
