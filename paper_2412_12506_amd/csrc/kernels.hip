@@ -424,23 +424,23 @@ __device__ __forceinline__ void load_widen(const TM* p, double (&out)[KS]) {
   }
 }
 
-template <typename TM, int BS>
+template <typename TM, int BS, int LKP>   // LKP = log2 of the power of two >= nk
 __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
                                                         const int* __restrict__ tab,
                                                         const int* __restrict__ perm,
                                                         const TM* __restrict__ blk, const double* x,
                                                         const double* z, double* out, double alpha,
-                                                        double beta, long long stride, int nk, int lkp) {
+                                                        double beta, long long stride, int nk) {
   constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
   constexpr int MG = sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
   const int lane = threadIdx.x & 63;
   const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int e0 = tile * (16 >> lkp);        // 16 / kp block rows per tile
+  const int e0 = tile * (16 >> LKP);        // 16 / kp block rows per tile
   if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
   const int col = lane & 15, kq = lane >> 4;
-  const int q = col & ((1 << lkp) - 1);     // right-hand side of this column
-  const bool rv = e0 + (col >> lkp) < nrows && q < nk;
-  const int row = perm[rv ? e0 + (col >> lkp) : e0];
+  const int q = col & ((1 << LKP) - 1);     // right-hand side of this column
+  const bool rv = e0 + (col >> LKP) < nrows && q < nk;
+  const int row = perm[rv ? e0 + (col >> LKP) : e0];
   const int rowc = row;
   const size_t qoff = static_cast<size_t>(rv ? q : 0) * stride;
   v4d acc[MT];
@@ -928,8 +928,17 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   const long long tiles = (a.nrows + rpt - 1) / rpt;
   const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
   if (blocks == 0) return;
-  k_bsr_tiled<TM, BS><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z,
-                                                   a.out, a.alpha, a.beta, stride, nk, lkp);
+  switch (lkp) {
+#define TILED(LK)                                                                                         \
+  case LK:                                                                                                \
+    k_bsr_tiled<TM, BS, LK><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, \
+                                                         a.x, a.z, a.out, a.alpha, a.beta, stride, nk);   \
+    break;
+    TILED(0) TILED(1) TILED(2) TILED(3)
+#undef TILED
+    default:
+      throw std::invalid_argument("bsr_tiled: at most 8 right-hand sides");
+  }
   check_launch("bsr_tiled");
 }
 
