@@ -628,104 +628,124 @@ __global__ void k_prolong_add(int dim, int nc, int ncomp, int bss, const T* __re
   xf[tid] += sum;
 }
 
-// Sum-factorised transfers (bss <= 64): one wavefront per (element,
-// component); lane = scalar coefficient (digit k of the lane index is the
-// degree in dimension k).  The tensor-product child matrix is applied one
-// dimension at a time through LDS: (p+1) products per lane and dimension
-// instead of bss.  P1 holds the 1-D child matrices, P1[c][i][j] = coefficient
-// i on child c of the coarse basis function j.
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_sf(int dim, int nc, int ncomp, int q1, int bss,
-                                                    const T* __restrict__ P1, const T* __restrict__ xc,
-                                                    T* __restrict__ xf, long long nwork) {
-  __shared__ T buf[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const long long work = static_cast<long long>(blockIdx.x) * 4 + w;
-  const bool valid = work < nwork;
-  const long long wk = valid ? work : 0;
-  const long long f = wk / ncomp;
-  const int comp = static_cast<int>(wk - f * ncomp);
-  const int nf = 2 * nc;
-  const int fx = static_cast<int>(f % nf), fy = static_cast<int>((f / nf) % nf);
-  const int fz = dim == 3 ? static_cast<int>(f / (static_cast<long long>(nf) * nf)) : 0;
-  const int cb[3] = {fx & 1, fy & 1, fz & 1};
-  const long long K = (fx >> 1) + static_cast<long long>(nc) * ((fy >> 1) + static_cast<long long>(nc) * (fz >> 1));
-  const bool act = lane < bss;
-  const int li = act ? lane : 0;
-  int dg[3] = {0, 0, 0};
-  {
-    int rem = li;
-    for (int k = 0; k < dim; ++k) {
-      dg[k] = rem % q1;
-      rem /= q1;
+// Sum-factorised transfers (bss = (p+1)^d <= 64), one lane per scalar
+// coefficient.  The tensor-product child matrix is applied one direction at a
+// time with lane shuffles: (p+1) products per lane and direction instead of
+// bss.  P1 holds the 1-D child matrices, P1[c][i][j] = coefficient i on child c
+// of the coarse basis function j.
+template <int Q1, int DIM>
+struct XferShape {
+  static constexpr int BSS = DIM == 3 ? Q1 * Q1 * Q1 : Q1 * Q1;   // nodes per element component
+  static constexpr int G = 64 / BSS;                              // coarse elements per wavefront
+  static constexpr int NCH = 1 << DIM;                            // children per coarse element
+};
+
+// Work unit of both transfer kernels: one (coarse element, component) pair per
+// group of BSS lanes, covering all 2^d children of the element.  Lane li holds
+// node li, whose degree index in direction k is digit k of li in base Q1.
+template <int Q1, int DIM>
+struct XferLane {
+  unsigned g;
+  bool valid;
+  int li, dg[3];
+  size_t coarse;                                  // offset of the lane's coarse value
+  size_t fine[XferShape<Q1, DIM>::NCH];           // offset of the lane's value in each child
+  __device__ XferLane(int nc, int ncomp, unsigned nwork) {
+    using S = XferShape<Q1, DIM>;
+    const unsigned lane = threadIdx.x & 63u;
+    g = lane / S::BSS;
+    const unsigned work = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * S::G + g;
+    valid = g < S::G && work < nwork;
+    const unsigned wk = valid ? work : 0u;
+    li = valid ? static_cast<int>(lane - g * S::BSS) : 0;
+    dg[0] = li % Q1;
+    dg[1] = (li / Q1) % Q1;
+    dg[2] = DIM == 3 ? li / (Q1 * Q1) : 0;
+    const unsigned K = wk / ncomp, comp = wk - K * ncomp;
+    const unsigned kx = K % nc, ky = (K / nc) % nc, kz = DIM == 3 ? K / (static_cast<unsigned>(nc) * nc) : 0u;
+    const size_t nf = 2u * nc;
+    coarse = (static_cast<size_t>(K) * ncomp + comp) * S::BSS + li;
+#pragma unroll
+    for (int cp = 0; cp < S::NCH; ++cp) {
+      const size_t f = (2 * kx + (cp & 1)) + nf * ((2 * ky + ((cp >> 1) & 1)) + nf * (DIM == 3 ? 2 * kz + (cp >> 2) : 0u));
+      fine[cp] = (f * ncomp + comp) * S::BSS + li;
     }
   }
-  const T xl = xc[(K * ncomp + comp) * bss + li];
-  T v = act ? xl : T(0);
+};
+
+// x_f += I x_c over the children of every coarse element (Section 3.2: the
+// prolongation is the injection of the coarse polynomial into the children).
+// The tensor-product child matrices are applied direction by direction as a
+// tree: the direction-k pass turns each of the 2^k partial results into one
+// per child index c_k in {0, 1}, and one shuffle of an input value serves both.
+template <typename T, int Q1, int DIM>
+__global__ __launch_bounds__(256) void k_prolong_tree(int nc, int ncomp, const T* __restrict__ P1,
+                                                      const T* __restrict__ xc, T* __restrict__ xf, unsigned nwork) {
+  using S = XferShape<Q1, DIM>;
+  const XferLane<Q1, DIM> L(nc, ncomp, nwork);
+  T old[S::NCH], v[S::NCH];
+#pragma unroll
+  for (int cp = 0; cp < S::NCH; ++cp) old[cp] = xf[L.fine[cp]];
+  v[0] = xc[L.coarse];
   int stride = 1;
-  for (int k = 0; k < dim; ++k) {
-    buf[w][lane] = v;
-    __syncthreads();
-    T sum = T(0);
-    const T* Pr = P1 + (cb[k] * q1 + dg[k]) * q1;
-    const int base = li - dg[k] * stride;
-    for (int j = 0; j < q1; ++j) sum += Pr[j] * buf[w][base + j * stride];
-    __syncthreads();
-    v = sum;
-    stride *= q1;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int base = static_cast<int>(L.g * S::BSS) + L.li - L.dg[k] * stride;
+    const T* P0 = P1 + L.dg[k] * Q1;            // row dg of the child-0 matrix
+    const T* Pc = P1 + (Q1 + L.dg[k]) * Q1;     // row dg of the child-1 matrix
+    T nv[S::NCH];
+#pragma unroll
+    for (int t = 0; t < (1 << k); ++t) {
+      T a0 = T(0), a1 = T(0);
+#pragma unroll
+      for (int j = 0; j < Q1; ++j) {
+        const T u = __shfl(v[t], base + j * stride);
+        a0 += P0[j] * u;
+        a1 += Pc[j] * u;
+      }
+      nv[t] = a0;
+      nv[t + (1 << k)] = a1;
+    }
+#pragma unroll
+    for (int t = 0; t < (2 << k); ++t) v[t] = nv[t];
+    stride *= Q1;
   }
-  const size_t o = static_cast<size_t>((f * ncomp + comp) * bss + li);
-  const T old = xf[o];
-  if (valid && act) xf[o] = old + v;
+#pragma unroll
+  for (int cp = 0; cp < S::NCH; ++cp)
+    if (L.valid) xf[L.fine[cp]] = old[cp] + v[cp];
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict_sf(int dim, int nc, int ncomp, int q1, int bss,
-                                                     const T* __restrict__ P1, const T* __restrict__ rf,
-                                                     T* __restrict__ rc, long long nwork) {
-  __shared__ T buf[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const long long work = static_cast<long long>(blockIdx.x) * 4 + w;
-  const bool valid = work < nwork;
-  const long long wk = valid ? work : 0;
-  const long long K = wk / ncomp;
-  const int comp = static_cast<int>(wk - K * ncomp);
-  const int kx = static_cast<int>(K % nc), ky = static_cast<int>((K / nc) % nc);
-  const int kz = dim == 3 ? static_cast<int>(K / (static_cast<long long>(nc) * nc)) : 0;
-  const int nf = 2 * nc;
-  const bool act = lane < bss;
-  const int li = act ? lane : 0;
-  int dg[3] = {0, 0, 0};
-  {
-    int rem = li;
-    for (int k = 0; k < dim; ++k) {
-      dg[k] = rem % q1;
-      rem /= q1;
+// r_c = I^T r_f (Section 3.2: restriction is the transpose of prolongation),
+// the tree of the prolongation run backwards: the direction-k pass pairs the
+// partial results of child index c_k = 0 and 1 and applies the transposed
+// child matrices.
+template <typename T, int Q1, int DIM>
+__global__ __launch_bounds__(256) void k_restrict_tree(int nc, int ncomp, const T* __restrict__ P1,
+                                                       const T* __restrict__ rf, T* __restrict__ rc, unsigned nwork) {
+  using S = XferShape<Q1, DIM>;
+  const XferLane<Q1, DIM> L(nc, ncomp, nwork);
+  T v[S::NCH];
+#pragma unroll
+  for (int cp = 0; cp < S::NCH; ++cp) v[cp] = rf[L.fine[cp]];
+  int stride = 1;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const int base = static_cast<int>(L.g * S::BSS) + L.li - L.dg[k] * stride;
+    const int half = S::NCH >> (k + 1);
+#pragma unroll
+    for (int t = 0; t < half; ++t) {
+      T a = T(0);
+#pragma unroll
+      for (int j = 0; j < Q1; ++j) {
+        // column dg of the child matrices: P1[c][j][dg]
+        a += P1[j * Q1 + L.dg[k]] * __shfl(v[2 * t], base + j * stride);
+        a += P1[(Q1 + j) * Q1 + L.dg[k]] * __shfl(v[2 * t + 1], base + j * stride);
+      }
+      v[t] = a;
     }
+    stride *= Q1;
   }
-  T acc = T(0);
-  const int nchild = 1 << dim;
-  for (int cp = 0; cp < nchild; ++cp) {
-    const int cb[3] = {cp & 1, (cp >> 1) & 1, (cp >> 2) & 1};
-    const long long f = (2 * kx + cb[0]) +
-                        static_cast<long long>(nf) * ((2 * ky + cb[1]) + static_cast<long long>(nf) * (dim == 3 ? 2 * kz + cb[2] : 0));
-    const T rl = rf[(f * ncomp + comp) * bss + li];
-    T v = act ? rl : T(0);
-    int stride = 1;
-    for (int k = 0; k < dim; ++k) {
-      buf[w][lane] = v;
-      __syncthreads();
-      T sum = T(0);
-      const int base = li - dg[k] * stride;
-      // transpose of the child matrix: sum over the child degree j of P1[c][j][a]
-      for (int j = 0; j < q1; ++j) sum += P1[(cb[k] * q1 + j) * q1 + dg[k]] * buf[w][base + j * stride];
-      __syncthreads();
-      v = sum;
-      stride *= q1;
-    }
-    acc += v;
-  }
-  if (valid && act) rc[(K * ncomp + comp) * bss + li] = acc;
+  if (L.valid) rc[L.coarse] = v[0];
 }
 
 // dense FP64 GEMV (bottom pseudo-inverse): one wavefront per row
@@ -1092,17 +1112,49 @@ void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool trans
   check_launch("expand_tiled");
 }
 
+template <typename T, int Q1, int DIM>
+void launch_xfer_tree(bool prolong, int nc, int ncomp, long long nwork, const T* P1, const T* in, T* out,
+                      hipStream_t st) {
+  constexpr int G = XferShape<Q1, DIM>::G;
+  const long long waves = (nwork + G - 1) / G;
+  const int blocks = static_cast<int>((waves + 3) / 4);
+  if (prolong)
+    k_prolong_tree<T, Q1, DIM><<<blocks, 256, 0, st>>>(nc, ncomp, P1, in, out, static_cast<unsigned>(nwork));
+  else
+    k_restrict_tree<T, Q1, DIM><<<blocks, 256, 0, st>>>(nc, ncomp, P1, in, out, static_cast<unsigned>(nwork));
+  check_launch(prolong ? "prolong_tree" : "restrict_tree");
+}
+
+// Transfers whose element component fits one wavefront (Q1^d <= 64) run as a
+// tree over the children; returns false for the others.
+template <typename T>
+bool xfer_tree(bool prolong, int dim, int q1, int nc, int ncomp, long long nwork, const T* P1, const T* in,
+               T* out, hipStream_t st) {
+  if (nwork >= (1LL << 31)) throw std::invalid_argument("transfer: more than 2^31 coarse element components");
+  if (dim == 3) {
+    switch (q1) {
+      case 2: launch_xfer_tree<T, 2, 3>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+      case 3: launch_xfer_tree<T, 3, 3>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+      case 4: launch_xfer_tree<T, 4, 3>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+      default: return false;
+    }
+  }
+  switch (q1) {
+    case 2: launch_xfer_tree<T, 2, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+    case 3: launch_xfer_tree<T, 3, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+    case 4: launch_xfer_tree<T, 4, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+    case 5: launch_xfer_tree<T, 5, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+    case 6: launch_xfer_tree<T, 6, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+    default: return false;
+  }
+}
+
 template <typename T>
 void restrict_op(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* rf, T* rc,
                  hipStream_t st) {
   long long nce = nc;
   for (int k = 1; k < dim; ++k) nce *= nc;
-  if (bss <= 64) {
-    const long long nwork = nce * ncomp;
-    k_restrict_sf<T><<<static_cast<int>((nwork + 3) / 4), 256, 0, st>>>(dim, nc, ncomp, q1, bss, P1, rf, rc, nwork);
-    check_launch("restrict_sf");
-    return;
-  }
+  if (xfer_tree<T>(false, dim, q1, nc, ncomp, nce * ncomp, P1, rf, rc, st)) return;
   const long long total = nce * ncomp * bss;
   k_restrict<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, rf, rc);
   check_launch("restrict");
@@ -1113,12 +1165,9 @@ void prolong_add(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const
                  hipStream_t st) {
   long long nfe = 2 * nc;
   for (int k = 1; k < dim; ++k) nfe *= 2 * nc;
-  if (bss <= 64) {
-    const long long nwork = nfe * ncomp;
-    k_prolong_sf<T><<<static_cast<int>((nwork + 3) / 4), 256, 0, st>>>(dim, nc, ncomp, q1, bss, P1, xc, xf, nwork);
-    check_launch("prolong_sf");
-    return;
-  }
+  long long nce = nc;
+  for (int k = 1; k < dim; ++k) nce *= nc;
+  if (xfer_tree<T>(true, dim, q1, nc, ncomp, nce * ncomp, P1, xc, xf, st)) return;
   const long long total = nfe * ncomp * bss;
   k_prolong_add<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, xc, xf);
   check_launch("prolong");
