@@ -4,18 +4,20 @@
 Workload (default): 3D Poisson, LDG Q_3 (64 unknowns per element, Legendre
 basis), uniform 64^3 grid of the unit cube (16,777,216 unknowns), Dirichlet
 boundaries, seeded N(0,1) right-hand sides; SAI_1 (OI ordering) V-cycle with
-FP32 block storage (operators; the SAI matrices optionally in BF16) and FP64
-arithmetic as the preconditioner of FP64 CG, solved to a 1e-10 relative
-residual.  One step = one full solve from x0 = 0 (every stage of the path:
+FP32 block storage (operators; the SAI matrices optionally in BF16), its block
+products in FP64 or (ldgmg_fp32_products) in FP32 on the matrix cores, as the
+preconditioner of FP64 CG, solved to a 1e-10 relative residual.  One step = one full solve from x0 = 0 (every stage of the path:
 residuals, SAI applies, transfers, bottom solve, V-cycle control, CG).  Inputs
 are resident in HBM before the timed region.
 
 Printed JSON (one line on stdout):
   value        V-cycle DOF/s = fine unknowns x V-cycles in the timed solves / time,
-               of the BF16-SAI path when it needs the same iterations as FP32
-               storage and meets the residual bar, else of the FP32 path
+               of the fastest path (FP32 or BF16-SAI storage, FP64 or FP32
+               products) that needs exactly the CG iterations of FP32 storage
+               with FP64 products and meets the residual bar
   solves_per_s, p50_ms / p99_ms per solve, iterations, eta, true residual
   fp32_path, bf16s_path, fp64_path   the same solves per storage precision (same MI355X)
+  fp32p_path, bf16sp_path            the FP32 and BF16-SAI handles with FP32 products
   expanded_path the headline precision with every block stored per slot (streamed from HBM)
   roofline     the dominant kernel (forward BSR apply with FP32 blocks on the
                fine level), timed with HIP events inside the library over the
@@ -37,6 +39,7 @@ METRIC = "V-cycle DOF/s & solves/s to 1e-10 rel. residual (FP32 vs FP64); p50/p9
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TF = 78.6      # MI355X FP64 vector (FMA) peak
 FP64_MFMA_PEAK_TF = 78.6        # MI355X dense FP64 matrix-core peak
+FP32_MFMA_PEAK_TF = 157.3       # MI355X dense FP32 matrix-core peak
 
 
 def log(*a):
@@ -48,19 +51,34 @@ def percentile(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
-def run_path(L, torch, args, precision, rhs, prof, storage="auto"):
+def run_path(L, torch, args, precision, rhs, prof, storage="auto", fp32_products=()):
     """Set up one precision and device storage, warm up, time args.steps
-    solves.  Returns stats."""
+    solves.  Returns stats; for each entry of fp32_products (a name) the same
+    handle is timed again with ldgmg_fp32_products on, and those stats are
+    returned under that name."""
     t0 = time.time()
     s = L.Solver(dim=3, n=args.n, p=args.p, smoother="sai", sai_level=1, order="OI",
                  precision=precision, storage=storage)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log(f"[{precision}] setup {setup_s:.1f}s ndofs {s.ndofs} levels {s.nlevels}")
+    out = time_solves(L, torch, args, s, precision, precision, rhs, prof, setup_s, False)
+    for name in fp32_products:
+        L.ldgmg_fp32_products(s.handle, True)
+        out[name] = time_solves(L, torch, args, s, precision, name, rhs, prof, setup_s, True)
+        L.ldgmg_fp32_products(s.handle, False)
+    s.close()
+    torch.cuda.synchronize()
+    return out
+
+
+def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_products):
+    """Warm up and time args.steps solves on handle s (storage precision
+    `precision`, logged as `label`)."""
     x = torch.empty_like(rhs[0])
     for i in range(args.warmup):
         info = s.solve(rhs[i], x, "cg", 1e-10, 200)
-        log(f"[{precision}] warmup {i}: iters {info['iters']}")
+        log(f"[{label}] warmup {i}: iters {info['iters']}")
     stream = torch.cuda.current_stream()
     if prof:
         L.ldgmg_profile(s.handle, True)
@@ -75,7 +93,7 @@ def run_path(L, torch, args, precision, rhs, prof, storage="auto"):
         info = s.solve(b, x, "cg", 1e-10, 200, stream=stream)
         ev[k][1].record(stream)
         infos.append(info)
-        log(f"[{precision}] step {k}: iters {info['iters']} rel_res {info['rel_res_true']:.2e}")
+        log(f"[{label}] step {k}: iters {info['iters']} rel_res {info['rel_res_true']:.2e}")
     torch.cuda.synchronize()
     wall = time.time() - t0
     lat = [a.elapsed_time(b) for a, b in ev]
@@ -95,6 +113,7 @@ def run_path(L, torch, args, precision, rhs, prof, storage="auto"):
         "rel_res_true_max": max(i["rel_res_true"] for i in infos),
         "vcycles": vcycles,
         "ndofs": s.ndofs,
+        "fp32_products": fp32_products,
     }
     if prof:
         info0 = L.ldgmg_level_info(s.handle, 0)
@@ -129,8 +148,6 @@ def run_path(L, torch, args, precision, rhs, prof, storage="auto"):
         out["kernels"] = kinds
         out["storage"] = storage
         L.ldgmg_profile(s.handle, False)
-    s.close()
-    torch.cuda.synchronize()
     return out
 
 
@@ -155,11 +172,11 @@ def counter_traffic(storage="expanded"):
     (None otherwise)."""
     import hashlib
     name = {"expanded": "bsr_fwd_fp32_bs64", "pooled": "bsr_fwd_fp32_pooled_bs64",
-            "tiled": "bsr_tiled_fp32_bs64"}[storage]
+            "tiled": "bsr_tiled_fp32_bs64", "tiled32": "bsr_tiled_fp32p_bs64"}[storage]
     prof = os.path.join(ROOT, "profiles", f"{name}_poisson3d_n64_counters.json")
     try:
         rec = json.load(open(prof))
-        text = kernel_source("tiled" if storage == "tiled" else "fwd")
+        text = kernel_source("tiled" if storage.startswith("tiled") else "fwd")
         if hashlib.sha256(text.encode()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
             return None
         return rec["traffic_bytes_per_launch"]
@@ -275,6 +292,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison")
     ap.add_argument("--no-bf16s", action="store_true", help="skip the BF16 SAI-storage path")
     ap.add_argument("--no-expanded", action="store_true", help="skip the expanded-storage reference path")
+    ap.add_argument("--no-fp32-products", action="store_true",
+                    help="skip the FP32-product timings (ldgmg_fp32_products) of the FP32 and BF16-SAI paths")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=8, help="grid of the CPU oracle sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -317,9 +336,13 @@ def main():
     nrhs = args.warmup + args.steps
     rhs = [torch.from_numpy(rhs_normal(ndofs, BASE_SEED + i)).to(dev) for i in range(nrhs)]
     torch.cuda.synchronize()
-    paths = {"fp32": run_path(L, torch, args, "fp32", rhs, prof=True)}
-    if not args.no_bf16s:
-        paths["bf16s"] = run_path(L, torch, args, "bf16s", rhs, prof=True)
+    paths = {}
+    for prec in ("fp32",) + (() if args.no_bf16s else ("bf16s",)):
+        pname = prec + "p"                  # the same handle with FP32 products
+        r = run_path(L, torch, args, prec, rhs, prof=True, fp32_products=() if args.no_fp32_products else (pname,))
+        if pname in r:
+            paths[pname] = r.pop(pname)
+        paths[prec] = r
     fp64 = None if args.no_fp64 else run_path(L, torch, args, "fp64", rhs, prof=False)
     # streaming reference: the same solves with every block stored per slot
     expanded = None if args.no_expanded else run_path(L, torch, args, "bf16s" if "bf16s" in paths else "fp32",
@@ -327,18 +350,21 @@ def main():
     del rhs
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_n)
 
-    # headline path: BF16 SAI storage when it needs the same CG iterations as
-    # FP32 storage and reaches the same true FP64 residual bar
-    head = "fp32"
-    bf = paths.get("bf16s")
-    if bf and bf["iters"] == paths["fp32"]["iters"] and bf["rel_res_true_max"] <= 2e-10:
-        head = "bf16s"
+    # headline path: the fastest of FP32 / BF16-SAI storage, each with FP64 or
+    # FP32 products, among those that need exactly the CG iterations of FP32
+    # storage with FP64 products on every right-hand side and reach the same
+    # true FP64 residual bar
+    ref_iters = paths["fp32"]["iters"]
+    ok = [nm for nm, pth in paths.items() if pth["iters"] == ref_iters and pth["rel_res_true_max"] <= 2e-10]
+    head = max(ok or ["fp32"], key=lambda nm: paths[nm]["vcycle_dof_per_s"])
     hp = paths[head]
     k = hp["kernels"]
+    p32 = hp["fp32_products"]
+    bf = paths.get("bf16s")
     # dominant kernel: the fine-level forward BSR apply of A with FP32 blocks
     # (with FP32 smoother storage the B applies run the same instantiation)
-    dom = ("A", "S") if head == "fp32" and (k["A"]["pooled"], k["A"]["tiled"]) == (k["S"]["pooled"], k["S"]["tiled"]) \
-        else ("A",)
+    dom = ("A", "S") if head.startswith("fp32") and \
+        (k["A"]["pooled"], k["A"]["tiled"]) == (k["S"]["pooled"], k["S"]["tiled"]) else ("A",)
     cnt = sum(k[d]["count"] for d in dom)
     ms = sum(k[d]["ms_total"] for d in dom)
     byts = sum(k[d]["bytes_per_launch"] * k[d]["count"] for d in dom) / max(cnt, 1)
@@ -347,14 +373,19 @@ def main():
     pooled, tiled = k["A"]["pooled"], k["A"]["tiled"]
     name = f"k_bsr_fwd<fp32 blocks, fp64 vectors, bs=64, {'pooled' if pooled else 'expanded'}> (fine level)"
     if tiled:
-        # pooled blocks applied on the FP64 matrix cores: priced against the
-        # FP64 MFMA peak (2 flops per stored entry and row)
-        name = "k_bsr_tiled<fp32 blocks, bs=64> (fine level, v_mfma_f64_16x16x4f64)"
+        # pooled blocks applied on the matrix cores: priced against the dense
+        # MFMA peak of the product type (2 flops per stored entry and row)
+        if p32:
+            name = "k_bsr_tiled<fp32 blocks, bs=64, FP32 products> (fine level, v_mfma_f32_16x16x4f32)"
+            peak = FP32_MFMA_PEAK_TF
+        else:
+            name = "k_bsr_tiled<fp32 blocks, bs=64> (fine level, v_mfma_f64_16x16x4f64)"
+            peak = FP64_MFMA_PEAK_TF
         achieved = flops / mean_s / 1e12 if cnt else None
-        roof = {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": FP64_MFMA_PEAK_TF,
-                "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TF if achieved else None,
-                "traffic": counter_traffic("tiled"), "hbm_gbs": byts / mean_s / 1e9 if cnt else None,
-                "flops_per_launch": flops}
+        roof = {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak if achieved else None,
+                "traffic": counter_traffic("tiled32" if p32 else "tiled"),
+                "hbm_gbs": byts / mean_s / 1e9 if cnt else None, "flops_per_launch": flops}
     elif pooled:
         # blocks come from the caches; each stored entry costs a widening and an
         # FP64 FMA on the vector ALUs: priced against the FP64 vector peak
@@ -385,8 +416,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "block_storage": ("A f32, SAI B bf16" if head == "bf16s" else "f32")
+        "dtype": "f32" if p32 else "f64",
+        "dtype_detail": ("block products f32 on the matrix cores (V-cycle applies); vectors, transfers, "
+                         "bottom and CG f64" if p32 else "f64 arithmetic on f32/bf16-stored blocks"),
+        "headline_path": head,
+        "block_storage": ("A f32, SAI B bf16" if head.startswith("bf16s") else "f32")
                          + (", tiled" if k["A"]["tiled"] else ", pooled" if k["A"]["pooled"] else ", expanded"),
         "data": "synthetic",
         "config": {"workload": f"poisson3d_p{args.p}_n{args.n}_sai1_oi_cg",
@@ -401,6 +435,8 @@ def main():
         "setup_s": hp["setup_s"],
         "fp32_path": {k2: paths["fp32"][k2] for k2 in summary},
         "bf16s_path": None if bf is None else {k2: bf[k2] for k2 in summary},
+        "fp32p_path": {k2: paths["fp32p"][k2] for k2 in summary} if "fp32p" in paths else None,
+        "bf16sp_path": {k2: paths["bf16sp"][k2] for k2 in summary} if "bf16sp" in paths else None,
         "fp64_path": None if fp64 is None else {k2: fp64[k2] for k2 in summary},
         "expanded_path": None if expanded is None else dict(
             {k2: expanded[k2] for k2 in summary},

@@ -166,6 +166,21 @@ int ldgmg_unload(ldgmg_handle h);
  * failure (serving).  Kept across ldgmg_unload / ldgmg_upload. */
 int ldgmg_cg_guard(ldgmg_handle h, int enable);
 
+/* FP32 products for the V-cycle of this handle: where a level is tiled
+ * (ldgmg_level_storage), its operator and smoother applies (A, B, B^T, and the
+ * block inverses of Jacobi) multiply on the FP32 matrix cores: the stored FP32
+ * or BF16 entries exactly, the vector entries rounded to FP32 to nearest, sums
+ * in FP32; the result is then combined with the FP64 vectors in FP64
+ * (out = alpha y + beta z).  A precision choice of this library (the
+ * method itself is stated in exact arithmetic): the V-cycle is only the
+ * preconditioner, while the outer Krylov iteration, its operator, the
+ * transfers and the bottom solve stay FP64.  The V-cycle is then no longer
+ * one fixed linear operator (the rounding of its input varies), so CG can
+ * need more iterations at high coefficient contrast.  Off by default; needs
+ * FP32 or BF16S precision (LDGMG_EINVAL otherwise).  Kept across
+ * ldgmg_unload / ldgmg_upload. */
+int ldgmg_fp32_products(ldgmg_handle h, int enable);
+
 /* Device bytes the handle holds now (0 when it holds no device data): what
  * ldgmg_upload allocated plus the batch workspace once a batched call made it. */
 int ldgmg_device_bytes(ldgmg_handle h, size_t* bytes);

@@ -66,6 +66,7 @@ struct DevLevel {
   int* bidS = nullptr;
   int* bidST = nullptr;
   Tiled tA, tS, tST;                // tiled storage (tab null when not tiled)
+  bool p32 = false;                 // FP32 products in the tiled applies of the V-cycle
   std::vector<int*> colour_rows;    // device lists per colour
   std::vector<int> colour_count;
   double* x = nullptr;              // level vectors are FP64 in both precisions
@@ -138,6 +139,7 @@ struct ldgmg_hier {
   std::unique_ptr<ldgmg::HostHierarchy> host;
   std::unique_ptr<ldgmg::DevHier> dev;
   bool cg_guard = false;            // ldgmg_cg_guard
+  bool fp32_products = false;       // ldgmg_fp32_products
 };
 
 namespace ldgmg {
@@ -490,6 +492,7 @@ void upload(ldgmg_hier* h, hipStream_t st) {
   HIPCHK(hipMemsetAsync(D->scal, 0, 64 * sizeof(double), st));
   HIPCHK(hipHostMalloc(&D->hscal, 64 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(st));
+  for (DevLevel& L : D->L) L.p32 = h->fp32_products;
   h->dev = std::move(D);
 }
 
@@ -543,6 +546,7 @@ BsrArgs<T, Vd> argsA(const DevLevel& L) {
   a.bid = L.bidA;
   a.blk = static_cast<const T*>(L.valA);
   set_tiled(a, L.tA);
+  a.p32 = L.p32;
   return a;
 }
 template <typename T>
@@ -556,6 +560,7 @@ BsrArgs<T, Vd> argsS(const DevLevel& L) {
   a.bid = L.bidS;
   a.blk = static_cast<const T*>(L.valS);
   set_tiled(a, L.tS);
+  a.p32 = L.p32;
   return a;
 }
 
@@ -1374,6 +1379,18 @@ int ldgmg_cg_guard(ldgmg_handle h, int enable) {
   return guarded([&] {
     if (!h || !h->host) throw std::invalid_argument("null handle");
     h->cg_guard = enable != 0;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_fp32_products(ldgmg_handle h, int enable) {
+  return guarded([&] {
+    if (!h || !h->host) throw std::invalid_argument("null handle");
+    if (enable && h->host->prob.precision == LDGMG_FP64)
+      throw std::invalid_argument("FP32 products need FP32 or BF16 storage");
+    h->fp32_products = enable != 0;
+    if (h->dev)
+      for (DevLevel& L : h->dev->L) L.p32 = h->fp32_products;
     return LDGMG_OK;
   });
 }

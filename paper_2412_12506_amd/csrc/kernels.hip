@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 }
 
 // ---------------------------------------------------------------------------
-// tiled forward BSR kernel on the FP64 matrix cores: out = alpha M x + beta z
+// tiled forward BSR kernel on the matrix cores: out = alpha M x + beta z
 // for a pooled matrix addressed by column offset, for nk <= 8 right-hand sides
 // (vectors q at x + q stride, z + q stride, out + q stride).  tab[row * noff +
 // d] is the pool id of block (row, row + off[d]) or -1; perm lists the block
@@ -394,37 +394,67 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 // perm[e0 .. e0 + 16 / kp - 1] and column c = (row c / kp, vector c % kp).  For
 // each offset it groups the columns by block id and accumulates
 // Y(bs x 16) += B(bs x bs) X(bs x 16), column c of X being its vector's block at
-// the row + off[d] (zero outside the group), with v_mfma_f64_16x16x4f64:
-// products and sums in FP64.
-// Pool layout (MT = ceil(bs/16) row tiles, KS = ceil(bs/4) k steps): entry
-// [block][m][lane][s] = B(16 m + lane % 16, (lane / 16) KS + s), zero outside
-// the block, so that lane l reads the KS operands of its k range contiguously.
-// MFMA operands: A lane l = (row l % 16, k l / 16), B lane l = (k l / 16,
-// column l % 16); result lane l = rows l / 16 + 4 i (i < 4) of column l % 16.
+// the row + off[d] (zero outside the group), with v_mfma_f64_16x16x4f64
+// (products and sums in FP64) or v_mfma_f32_16x16x4f32 (FP32 products).
+// MFMA operands: A lane l = (row l % 16, k lane l / 16), B lane l = (k lane
+// l / 16, column l % 16); result lane l = rows l / 16 + 4 i (FP64) or
+// 4 (l / 16) + i (FP32), i < 4, of column l % 16.
+// With MT = ceil(bs/16) row tiles and KS = ceil(bs/4) k steps, k lane q of
+// step s takes the block column tile_k(s, q): 8 (s / 2) + 2 q + s % 2 when
+// 8 divides bs, so that the four k lanes of a column read 64 contiguous bytes
+// of x per 16-byte load, else q KS + s.
+// Pool layout, E entries per 16 bytes (E = 16 / entry size when E divides KS,
+// else 1): entry [block][m][s / E][lane][s % E] = B(16 m + lane % 16,
+// tile_k(s, lane / 16)), zero outside the block; one 16-byte load of a
+// wavefront reads 1 KB contiguously.
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// KS consecutive stored entries, widened to FP64: 16-byte loads when KS fills
-// whole vectors (the tiled pool keeps each lane's run 16-byte aligned)
-template <typename TM, int KS>
-__device__ __forceinline__ void load_widen(const TM* p, double (&out)[KS]) {
-  constexpr int E = 16 / static_cast<int>(sizeof(TM));
-  if constexpr (KS % E == 0) {
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// entries per 16-byte group of the pool layout
+template <typename TM>
+__host__ __device__ constexpr int tile_vec(int KS) {
+  return KS % (16 / static_cast<int>(sizeof(TM))) == 0 ? 16 / static_cast<int>(sizeof(TM)) : 1;
+}
+
+// block column of k lane q at step s
+__host__ __device__ constexpr int tile_k(int bs, int KS, int s, int q) {
+  return bs % 8 == 0 ? 8 * (s >> 1) + 2 * q + (s & 1) : q * KS + s;
+}
+
+// the KS operands of this lane in row tile p (= pool block + m 64 KS), widened
+// to the operand type OP (FP64, or FP32 for stored FP32 / BF16: exact either way)
+template <typename TM, int KS, typename OP>
+__device__ __forceinline__ void load_widen(const TM* p, int lane, OP (&out)[KS]) {
+  constexpr int E = tile_vec<TM>(KS);
+  if constexpr (E > 1) {
     using VT = typename VecT<TM, E>::type;
-    const VT* v = reinterpret_cast<const VT*>(p);
+    const VT* v = reinterpret_cast<const VT*>(p) + lane;
 #pragma unroll
     for (int q = 0; q < KS / E; ++q) {
-      const VT w = v[q];
+      const VT w = v[q * 64];
 #pragma unroll
-      for (int e = 0; e < E; ++e) out[q * E + e] = static_cast<double>(elem(w, e));
+      for (int e = 0; e < E; ++e) out[q * E + e] = static_cast<OP>(elem(w, e));
     }
   } else {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) out[s] = static_cast<double>(widen(p[s]));
+    for (int s = 0; s < KS; ++s) out[s] = static_cast<OP>(widen(p[s * 64 + lane]));
   }
 }
 
-template <typename TM, int BS, int LKP>   // LKP = log2 of the power of two >= nk
+// one 16x16x4 MFMA step: FP64, or FP32 operands with FP32 accumulation
+__device__ __forceinline__ v4d mfma_step(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma_step(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// P32: FP32 products (operands rounded to FP32: the stored FP32 / BF16 entries
+// exactly, the vector entries to nearest) accumulated in FP32; the result is
+// combined with z in FP64.
+template <typename TM, int BS, int LKP, bool P32>   // LKP = log2 of the power of two >= nk
 __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
                                                         const int* __restrict__ tab,
                                                         const int* __restrict__ perm,
@@ -433,6 +463,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
                                                         double beta, long long stride, int nk) {
   constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
   constexpr int MG = sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
+  using OP = typename std::conditional<P32, float, double>::type;
+  using ACC = typename std::conditional<P32, v4f, v4d>::type;
   const int lane = threadIdx.x & 63;
   const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int e0 = tile * (16 >> LKP);        // 16 / kp block rows per tile
@@ -443,9 +475,9 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   const int row = perm[rv ? e0 + (col >> LKP) : e0];
   const int rowc = row;
   const size_t qoff = static_cast<size_t>(rv ? q : 0) * stride;
-  v4d acc[MT];
+  ACC acc[MT];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) acc[m] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int m = 0; m < MT; ++m) acc[m] = ACC{0, 0, 0, 0};
   for (int d = 0; d < noff; ++d) {
     const int o = off[d];
     const int t = tab[static_cast<size_t>(rowc) * noff + d];
@@ -457,37 +489,37 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const unsigned long long sel = __ballot(myid == id) & 0xFFFFull;
       const bool use = (sel >> col) & 1ull;
       const double* xp = x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0);
-      double xb[KS];
-      if constexpr (4 * KS == BS && KS % 2 == 0) {    // no padding: 16-byte loads
-        const double2* x2 = reinterpret_cast<const double2*>(xp + kq * KS);
+      OP xb[KS];
+      if constexpr (BS % 8 == 0) {    // steps 2j, 2j+1: columns 8j + 2 kq + {0, 1}, one 16-byte load
+        const double2* x2 = reinterpret_cast<const double2*>(xp + 2 * kq);
 #pragma unroll
         for (int q = 0; q < KS / 2; ++q) {
-          const double2 v = x2[q];
-          xb[2 * q] = use ? v.x : 0.0;
-          xb[2 * q + 1] = use ? v.y : 0.0;
+          const double2 v = x2[4 * q];
+          xb[2 * q] = use ? static_cast<OP>(v.x) : OP(0);
+          xb[2 * q + 1] = use ? static_cast<OP>(v.y) : OP(0);
         }
       } else {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const int c = kq * KS + s;
+          const int c = tile_k(BS, KS, s, kq);
           const double v = xp[c < BS ? c : 0];
-          xb[s] = (use && c < BS) ? v : 0.0;
+          xb[s] = (use && c < BS) ? static_cast<OP>(v) : OP(0);
         }
       }
-      const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(lane) * KS;
+      const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS);
       // MG row tiles at a time: their operands are loaded first and their
       // independent accumulations interleaved, so no MFMA waits on the last
 #pragma unroll
       for (int m0 = 0; m0 < MT; m0 += MG) {
-        double a[MG][KS];
+        OP a[MG][KS];
 #pragma unroll
         for (int g = 0; g < MG; ++g)
-          if (m0 + g < MT) load_widen<TM, KS>(bp + (m0 + g) * 64 * KS, a[g]);
+          if (m0 + g < MT) load_widen<TM, KS, OP>(bp + (m0 + g) * 64 * KS, lane, a[g]);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
           for (int g = 0; g < MG; ++g)
-            if (m0 + g < MT) acc[m0 + g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[g][s], xb[s], acc[m0 + g], 0, 0, 0);
+            if (m0 + g < MT) acc[m0 + g] = mfma_step(a[g][s], xb[s], acc[m0 + g]);
       }
       rem &= ~sel;
     }
@@ -497,10 +529,12 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = 16 * m + kq + 4 * i;      // result layout of the MFMA
+      // result layout: FP64 lane l holds rows l/16 + 4i, FP32 rows 4(l/16) + i
+      const int r = 16 * m + (P32 ? 4 * kq + i : kq + 4 * i);
       if (r < BS) {
         const size_t o = qoff + static_cast<size_t>(row) * BS + r;
-        out[o] = beta != 0.0 ? alpha * acc[m][i] + beta * z[o] : alpha * acc[m][i];
+        const double y = static_cast<double>(acc[m][i]);
+        out[o] = beta != 0.0 ? alpha * y + beta * z[o] : alpha * y;
       }
     }
 }
@@ -515,10 +549,13 @@ __global__ void k_expand_tiled(long long nblk, int bs, int MT, int KS, const dou
        t += static_cast<long long>(gridDim.x) * blockDim.x) {
     const long long b = t / per;
     const int rem = static_cast<int>(t - b * per);
-    const int m = rem / (64 * KS);
-    const int l = (rem / KS) % 64;
-    const int s = rem % KS;
-    const int r = 16 * m + l % 16, c = (l / 16) * KS + s;
+    const int E = tile_vec<T>(KS);
+    const int e = rem % E;
+    const int l = (rem / E) % 64;
+    const int gq = rem / (64 * E);          // m KS / E + s / E
+    const int m = gq / (KS / E);
+    const int s = (gq % (KS / E)) * E + e;
+    const int r = 16 * m + l % 16, c = tile_k(bs, KS, s, l / 16);
     double v = 0.0;
     if (r < bs && c < bs) v = transpose ? pool[b * bb + static_cast<long long>(c) * bs + r] : pool[b * bb + static_cast<long long>(r) * bs + c];
     out[t] = narrow<T>(v);
@@ -942,6 +979,9 @@ void launch_fwd_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
 
 template <typename TM, typename T, int BS>
 void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStream_t st) {
+  // FP32 products for FP32 / BF16 storage only: FP64 blocks keep FP64 products
+  constexpr bool P32 = !std::is_same<TM, double>::value;
+  if (a.p32 && !P32) throw std::invalid_argument("bsr_tiled: FP32 products need FP32 or BF16 storage");
   int lkp = 0;                              // log2 of the power of two >= nk
   while ((1 << lkp) < nk) ++lkp;
   const int rpt = 16 >> lkp;                // block rows per tile
@@ -949,10 +989,16 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
   if (blocks == 0) return;
   switch (lkp) {
-#define TILED(LK)                                                                                         \
-  case LK:                                                                                                \
-    k_bsr_tiled<TM, BS, LK><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, \
-                                                         a.x, a.z, a.out, a.alpha, a.beta, stride, nk);   \
+#define TILED(LK)                                                                                              \
+  case LK:                                                                                                     \
+    if (P32 && a.p32)                                                                                          \
+      k_bsr_tiled<TM, BS, LK, P32><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm,       \
+                                                               a.tblk, a.x, a.z, a.out, a.alpha, a.beta,       \
+                                                               stride, nk);                                    \
+    else                                                                                                       \
+      k_bsr_tiled<TM, BS, LK, false><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm,     \
+                                                                 a.tblk, a.x, a.z, a.out, a.alpha, a.beta,     \
+                                                                 stride, nk);                                  \
     break;
     TILED(0) TILED(1) TILED(2) TILED(3)
 #undef TILED

@@ -51,6 +51,7 @@ struct BsrArgs {
   const int* tperm = nullptr; // block rows ordered by their row of tab
   const int* toff = nullptr;
   int noff = 0;
+  bool p32 = false;           // tiled storage: FP32 products on the matrix cores
   T omega = T(1);
 };
 

@@ -61,7 +61,7 @@ SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", 
            "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
-           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage", "ldgmg_destroy",
+           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_fp32_products", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -98,6 +98,7 @@ def lib():
     L.ldgmg_profile_read.argtypes = [H, C.c_int, ip, dp]
     L.ldgmg_unload.argtypes = [H]
     L.ldgmg_cg_guard.argtypes = [H, C.c_int]
+    L.ldgmg_fp32_products.argtypes = [H, C.c_int]
     L.ldgmg_device_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.ldgmg_upload_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.ldgmg_level_storage.argtypes = [H, C.c_int, ip, ip, ip]
@@ -330,6 +331,10 @@ def ldgmg_cg_guard(h: int, enable: bool = True):
     _check(lib().ldgmg_cg_guard(h, 1 if enable else 0))
 
 
+def ldgmg_fp32_products(h: int, enable: bool = True):
+    _check(lib().ldgmg_fp32_products(h, 1 if enable else 0))
+
+
 def ldgmg_device_bytes(h: int) -> int:
     out = C.c_size_t(0)
     _check(lib().ldgmg_device_bytes(h, C.byref(out)))
@@ -367,10 +372,12 @@ class Solver:
         s = Solver(dim=3, n=16, p=3); s.upload(); info = s.solve(b, x)
     """
 
-    def __init__(self, host_only: bool = False, stream=None, **kw):
+    def __init__(self, host_only: bool = False, stream=None, fp32_products: bool = False, **kw):
         self.problem, self._mu = make_problem(**kw)
         self.handle = ldgmg_setup_host(self.problem)
         self.ndofs, self.bs, self.nlevels = ldgmg_sizes(self.handle)
+        if fp32_products:
+            ldgmg_fp32_products(self.handle, True)
         if not host_only:
             self.upload(stream)
 

@@ -75,3 +75,39 @@ def stored_vcycle(vc, prec):
         sd = SmootherData("sai", B=round_bf16(lv.sm.B))
         levels.append(MGLevel(A, lv.bs, lv.I, sd))
     return VCycle(levels, vc.order, vc.nu1, vc.nu2)
+
+
+class F32Products:
+    """A stored matrix whose products are taken in FP32: the entries (already
+    rounded as stored) times the input rounded to FP32 to nearest, summed in
+    FP32, returned as FP64.  The test-side model of ldgmg_fp32_products (the
+    summation order differs from the matrix cores')."""
+
+    def __init__(self, M):
+        self.M32 = sp.csr_matrix(M, dtype=np.float32)
+        self.shape = self.M32.shape
+
+    def __matmul__(self, x):
+        return (self.M32 @ np.asarray(x, dtype=np.float32)).astype(np.float64)
+
+    @property
+    def T(self):
+        return F32Products(self.M32.T)
+
+
+def fp32_products_vcycle(vc, prec):
+    """The oracle's V-cycle with FP32 products in every operator and SAI apply
+    above the bottom (matrices rounded as `prec` stores them: "fp32" or
+    "bf16s"); transfers, vector updates and the bottom stay FP64."""
+    from oracle.vcycle import MGLevel, SmootherData, VCycle
+    assert prec in ("fp32", "bf16s")
+    levels = []
+    for lv in vc.levels:
+        if lv.sm is None:
+            levels.append(MGLevel(lv.A, lv.bs, None, None, pinv=lv.pinv))
+            continue
+        assert lv.sm.kind == "sai"
+        B = round_bf16(lv.sm.B) if prec == "bf16s" else round_fp32(lv.sm.B)
+        sd = SmootherData("sai", B=F32Products(B))
+        levels.append(MGLevel(F32Products(round_fp32(lv.A)), lv.bs, lv.I, sd))
+    return VCycle(levels, vc.order, vc.nu1, vc.nu2)

@@ -1,0 +1,183 @@
+"""FP32 products on the matrix cores (ldgmg_fp32_products) against the oracle.
+
+With the mode on, every tiled operator and smoother apply of the V-cycle rounds
+its input to FP32 and multiplies and sums in FP32; the result is combined with
+the FP64 vectors in FP64.  Tolerances, from that arithmetic:
+  * level operations, entry by entry: a row of n stored terms summed in FP32
+    from an FP32-rounded input is within (n + 3) u32 (|M||x|)_i of the FP64
+    product of the stored matrix (u32 = 2^-24: n - 1 sums, the products, the
+    input rounding, and one unit for a stored entry that the two independent
+    setups round to neighbouring FP32 values);
+  * V-cycle: against the oracle's V-cycle with FP32 products
+    (tests/gpu_common.fp32_products_vcycle; the same roundings, another
+    summation order) within 1e-4 relative: each apply agrees to n u32 <= 3e-5
+    relative per entry for n <= 448 terms;
+  * solves: CG converges to a true FP64 residual <= 2e-10; its iteration count
+    is within +-1 of the oracle's CG preconditioned by that FP32-product
+    V-cycle, and on Poisson also within +-1 of the plain FP64 oracle's; the
+    solution differs from the FP64 oracle's by a vector whose residual is
+    within the two solves' residuals (<= 4e-10 ||b||);
+  * a level that is not tiled is not affected: with pooled storage the results
+    are bitwise those without the mode.
+"""
+import numpy as np
+import pytest
+
+from ldg_inputs import rhs_normal
+from tests.gpu_common import (fp32_products_vcycle, lib_kwargs, oracle_build, round_bf16, round_fp32,
+                              smoother_matrix)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+CASES = [
+    (dict(id="p3d-p3-sai1", dim=3, n=6, p=3, smoother="sai"), "fp32", True),
+    (dict(id="p3d-p3-sai1", dim=3, n=6, p=3, smoother="sai"), "bf16s", True),
+    (dict(id="p2d-p2-sai1", dim=2, n=32, p=2, smoother="sai"), "fp32", True),
+    (dict(id="i3d-p2-sphere-sai1", dim=3, n=8, p=2, smoother="sai", mu=("sphere", 0.3, 1e4)), "fp32", False),
+]
+
+_ORACLE = {}
+
+
+def _oracle(case):
+    if case["id"] not in _ORACLE:
+        _ORACLE.clear()
+        _ORACLE[case["id"]] = oracle_build(case)
+    return _ORACLE[case["id"]]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"{c[0]['id']}-{c[1]}")
+def built(request):
+    from paper_2412_12506_amd import ldgmg as L
+    case, prec, poisson = request.param
+    print(f"\n[fp32 products {case['id']} {prec}]", flush=True)
+    s = L.Solver(storage="tiled", fp32_products=True, **lib_kwargs(case, prec))
+    lv, vc = _oracle(case)
+    yield case, prec, poisson, s, lv, vc
+    s.close()
+
+
+def _check_rows(y, ref, M, x, what):
+    """Entry-wise FP32-product bound; M is the stored matrix (FP64 values)."""
+    M = M.tocsr()
+    n = np.diff(M.indptr)
+    bound = (n + 3) * U32 * (abs(M) @ np.abs(x))
+    err = np.abs(y - ref)
+    worst = float(np.max(err / np.maximum(bound, 1e-300)))
+    assert worst <= 1.0, (what, worst)
+    return worst
+
+
+def test_level_operations(built):
+    from paper_2412_12506_amd import ldgmg as L
+    case, prec, poisson, s, lv, vc = built
+    rng = np.random.default_rng(77)
+    for l in range(len(lv) - 1):
+        st = L.ldgmg_level_storage(s.handle, l)
+        assert st["tiled_A"] and st["tiled_S"], (l, st)
+        A = round_fp32(vc.levels[l].A)
+        S = smoother_matrix(vc, l)
+        S = round_bf16(S) if prec == "bf16s" else round_fp32(S)
+        N = A.shape[0]
+        x = rng.standard_normal(N)
+        b = rng.standard_normal(N)
+        xt, bt = torch.from_numpy(x).cuda(), torch.from_numpy(b).cuda()
+        out = torch.empty_like(xt)
+        L.ldgmg_level_op(s.handle, l, "residual", xt, bt, out)
+        torch.cuda.synchronize()
+        _check_rows(b - out.cpu().numpy(), A @ x, A, x, (l, "residual"))
+        for op, M in (("apply_a", A), ("apply_s", S), ("apply_st", S.T)):
+            L.ldgmg_level_op(s.handle, l, op, xt, None, out)
+            torch.cuda.synchronize()
+            w = _check_rows(out.cpu().numpy(), M @ x, M, x, (l, op))
+            print(f"  level {l} {op}: worst error / bound {w:.3f}", flush=True)
+
+
+def test_vcycle(built):
+    from paper_2412_12506_amd import ldgmg as L
+    case, prec, poisson, s, lv, vc = built
+    b = rhs_normal(lv[0].A.shape[0], 5)
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.empty_like(bt)
+    L.ldgmg_vcycle(s.handle, bt, xt)
+    torch.cuda.synchronize()
+    ref = fp32_products_vcycle(vc, prec).apply(b)
+    err = np.linalg.norm(xt.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"  V-cycle relative difference {err:.2e}", flush=True)
+    assert err <= 1e-4
+    xt2 = torch.empty_like(bt)
+    L.ldgmg_vcycle(s.handle, bt, xt2)
+    torch.cuda.synchronize()
+    assert torch.equal(xt, xt2)            # deterministic
+
+
+def test_solve(built):
+    from paper_2412_12506_amd import ldgmg as L
+    from oracle import krylov, solver as osolver
+    case, prec, poisson, s, lv, vc = built
+    b = rhs_normal(lv[0].A.shape[0], 11)
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.empty_like(bt)
+    info = L.ldgmg_solve(s.handle, bt, xt, "cg", 1e-10, 200)
+    torch.cuda.synchronize()
+    vm = fp32_products_vcycle(vc, prec)
+    model = krylov.pcg(lv[0].A.tocsr(), b, vm.apply)
+    ref = osolver.solve(lv, vc, b, "cg")
+    print(f"  iterations: GPU {info['iters']}, FP32-product model {model.iters}, FP64 oracle {ref.iters}",
+          flush=True)
+    assert info["converged"] and info["rel_res_true"] <= 2e-10
+    assert abs(info["iters"] - model.iters) <= 1
+    if poisson:
+        assert abs(info["iters"] - ref.iters) <= 1
+    # two CG runs converged to 1e-10 from V-cycles that differ in their FP32
+    # roundings: their solutions differ by A^-1 of two residuals each <= 2e-10 ||b||
+    d = xt.cpu().numpy() - ref.x
+    res = np.linalg.norm(lv[0].A @ d) / np.linalg.norm(b)
+    print(f"  solution difference {np.linalg.norm(d) / np.linalg.norm(ref.x):.2e}, A-residual of it {res:.2e}",
+          flush=True)
+    assert res <= 4e-10
+
+
+def test_untiled_levels_unaffected():
+    from paper_2412_12506_amd import ldgmg as L
+    case = dict(dim=3, n=6, p=3, smoother="sai")
+    a = L.Solver(storage="pooled", fp32_products=True, **lib_kwargs(case, "fp32"))
+    c = L.Solver(storage="pooled", **lib_kwargs(case, "fp32"))
+    try:
+        b = torch.from_numpy(rhs_normal(a.ndofs, 3)).cuda()
+        xa, xc = torch.empty_like(b), torch.empty_like(b)
+        L.ldgmg_vcycle(a.handle, b, xa)
+        L.ldgmg_vcycle(c.handle, b, xc)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xc)
+    finally:
+        a.close()
+        c.close()
+
+
+def test_batch_matches_single():
+    """The batched serving step with FP32 products: each right-hand side
+    converges to a true residual <= 2e-10 within +-1 iteration of its single
+    solve, and the two solutions agree to 1e-8 (two converged CG runs whose
+    FP32 V-cycle inputs differ in their last bits)."""
+    from paper_2412_12506_amd import ldgmg as L
+    case = dict(dim=3, n=6, p=3, smoother="sai")
+    s = L.Solver(storage="tiled", fp32_products=True, **lib_kwargs(case, "bf16s"))
+    try:
+        bs = [torch.from_numpy(rhs_normal(s.ndofs, 40 + q)).cuda() for q in range(3)]
+        xs = [torch.empty_like(b) for b in bs]
+        infos = L.ldgmg_solve_batch(s.handle, bs, xs, 1e-10, 200)
+        torch.cuda.synchronize()
+        for q in range(3):
+            x1 = torch.empty_like(bs[q])
+            one = L.ldgmg_solve(s.handle, bs[q], x1, "cg", 1e-10, 200)
+            torch.cuda.synchronize()
+            assert infos[q]["converged"] and abs(infos[q]["iters"] - one["iters"]) <= 1
+            assert infos[q]["rel_res_true"] <= 2e-10
+            rel = float(torch.linalg.norm(xs[q] - x1) / torch.linalg.norm(x1))
+            assert rel <= 1e-8, (q, rel)
+    finally:
+        s.close()

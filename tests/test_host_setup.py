@@ -88,6 +88,25 @@ def test_invalid_problems_are_rejected():
             assert ei.value.code == L.EINVAL
 
 
+def test_fp32_products_need_fp32_or_bf16_storage():
+    """ldgmg_fp32_products is refused for FP64 storage and accepted (before any
+    upload) for FP32 and BF16S storage."""
+    from paper_2412_12506_amd import ldgmg as L
+    for prec, ok in (("fp64", False), ("fp32", True), ("bf16s", True)):
+        s = L.Solver(host_only=True, dim=2, n=8, p=2, smoother="sai", precision=prec)
+        try:
+            if ok:
+                L.ldgmg_fp32_products(s.handle, True)
+                L.ldgmg_fp32_products(s.handle, False)
+            else:
+                with pytest.raises(L.LdgmgError) as ei:
+                    L.ldgmg_fp32_products(s.handle, True)
+                assert ei.value.code == L.EINVAL
+                L.ldgmg_fp32_products(s.handle, False)       # switching off is always allowed
+        finally:
+            s.close()
+
+
 def test_bottom_independent_of_thread_count():
     """The threaded eigensolver does the same arithmetic in the same order."""
     from paper_2412_12506_amd import ldgmg as L
