@@ -466,7 +466,12 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   using OP = typename std::conditional<P32, float, double>::type;
   using ACC = typename std::conditional<P32, v4f, v4d>::type;
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous
+  // range of tiles so that neighbouring rows share its L2
+  const int nb = gridDim.x, n8 = nb >> 3;
+  const int b = blockIdx.x;
+  const int lb = b < 8 * n8 ? (b & 7) * n8 + (b >> 3) : b;
+  const int tile = lb * kWaves + (threadIdx.x >> 6);
   const int e0 = tile * (16 >> LKP);        // 16 / kp block rows per tile
   if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
   const int col = lane & 15, kq = lane >> 4;
