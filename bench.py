@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--p", type=int, default=3, help="polynomial degree")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage comparison")
     ap.add_argument("--no-bf16s", action="store_true", help="skip the BF16 SAI-storage path")
+    ap.add_argument("--no-fp32-storage", action="store_true",
+                    help="skip the FP32-storage path (e.g. to count one path's kernels alone)")
     ap.add_argument("--no-expanded", action="store_true", help="skip the expanded-storage reference path")
     ap.add_argument("--no-fp32-products", action="store_true",
                     help="skip the FP32-product timings (ldgmg_fp32_products) of the FP32 and BF16-SAI paths")
@@ -337,7 +339,7 @@ def main():
     rhs = [torch.from_numpy(rhs_normal(ndofs, BASE_SEED + i)).to(dev) for i in range(nrhs)]
     torch.cuda.synchronize()
     paths = {}
-    for prec in ("fp32",) + (() if args.no_bf16s else ("bf16s",)):
+    for prec in (() if args.no_fp32_storage else ("fp32",)) + (() if args.no_bf16s else ("bf16s",)):
         pname = prec + "p"                  # the same handle with FP32 products
         r = run_path(L, torch, args, prec, rhs, prof=True, fp32_products=() if args.no_fp32_products else (pname,))
         if pname in r:
@@ -354,9 +356,10 @@ def main():
     # FP32 products, among those that need exactly the CG iterations of FP32
     # storage with FP64 products on every right-hand side and reach the same
     # true FP64 residual bar
-    ref_iters = paths["fp32"]["iters"]
+    ref = "fp32" if "fp32" in paths else next(iter(paths))
+    ref_iters = paths[ref]["iters"]
     ok = [nm for nm, pth in paths.items() if pth["iters"] == ref_iters and pth["rel_res_true_max"] <= 2e-10]
-    head = max(ok or ["fp32"], key=lambda nm: paths[nm]["vcycle_dof_per_s"])
+    head = max(ok or [ref], key=lambda nm: paths[nm]["vcycle_dof_per_s"])
     hp = paths[head]
     k = hp["kernels"]
     p32 = hp["fp32_products"]
@@ -433,7 +436,7 @@ def main():
         "eta": hp["eta"],
         "rel_res_true_max": hp["rel_res_true_max"],
         "setup_s": hp["setup_s"],
-        "fp32_path": {k2: paths["fp32"][k2] for k2 in summary},
+        "fp32_path": {k2: paths["fp32"][k2] for k2 in summary} if "fp32" in paths else None,
         "bf16s_path": None if bf is None else {k2: bf[k2] for k2 in summary},
         "fp32p_path": {k2: paths["fp32p"][k2] for k2 in summary} if "fp32p" in paths else None,
         "bf16sp_path": {k2: paths["bf16sp"][k2] for k2 in summary} if "bf16sp" in paths else None,
