@@ -727,11 +727,26 @@ void vcycle_level(const Ctx& c, int l) {
 // z = V r (FP64 vectors in and out; the stored blocks are FP32 or FP64)
 void vcycle64(const Ctx& c, const double* r, double* z) {
   DevLevel& L = c.D.L[0];
-  HIPCHK(hipMemcpyAsync(L.b, r, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
+  const size_t n = static_cast<size_t>(L.N);
+  // the fine level reads r and writes z in place unless the two overlap
+  const bool direct = r + n <= z || z + n <= r;
+  double* const b0 = L.b;
+  double* const x0 = L.x;
+  double* const t0 = L.t;
+  if (direct) {
+    L.b = const_cast<double*>(r);         // read only
+    L.x = z;
+  } else {
+    HIPCHK(hipMemcpyAsync(L.b, r, n * 8, hipMemcpyDeviceToDevice, c.st));
+  }
   if (c.D.prec == LDGMG_FP64) vcycle_level<double, double>(c, 0);
   else if (c.D.prec == LDGMG_BF16S) vcycle_level<float, bf16s>(c, 0);
   else vcycle_level<float, float>(c, 0);
-  HIPCHK(hipMemcpyAsync(z, L.x, static_cast<size_t>(L.N) * 8, hipMemcpyDeviceToDevice, c.st));
+  // Jacobi smoothing swaps the roles of x and t: the result is in L.x
+  if (L.x != z) HIPCHK(hipMemcpyAsync(z, L.x, n * 8, hipMemcpyDeviceToDevice, c.st));
+  L.b = b0;
+  L.x = x0;
+  L.t = t0;
 }
 
 void apply_A64(const Ctx& c, const double* x, double* y) {
