@@ -67,6 +67,7 @@ struct DevLevel {
   int* bidST = nullptr;
   Tiled tA, tS, tST;                // tiled storage (tab null when not tiled)
   bool p32 = false;                 // FP32 products in the tiled applies of the V-cycle
+  float* r32 = nullptr;             // FP32 smoothing residual for those products (levels with tiled A and S, 16 | bs)
   std::vector<int*> colour_rows;    // device lists per colour
   std::vector<int> colour_count;
   double* x = nullptr;              // level vectors are FP64 in both precisions
@@ -390,6 +391,16 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
 }
 
 // exact device bytes of ldgmg_upload for a host hierarchy (batch workspace excluded)
+// levels that keep an FP32 smoothing residual for FP32 products: SAI smoother,
+// A and S tiled, 16 | bs
+bool fp32_residual_level(const HostHierarchy& H, int l, int prec) {
+  const HostLevel& L = H.levels[l];
+  const int storage = H.prob.storage;
+  return l + 1 < static_cast<int>(H.levels.size()) && prec != LDGMG_FP64 && H.prob.smoother == LDGMG_SMOOTH_SAI &&
+         L.bs % 16 == 0 && use_tiled(L.A, L.bs, elem_bytes_A(prec), storage) &&
+         use_tiled(L.S, L.bs, elem_bytes_S(prec), storage);
+}
+
 size_t estimate_from_host(const HostHierarchy& H, int prec) {
   const int storage = H.prob.storage;
   const size_t ea = elem_bytes_A(prec), es = elem_bytes_S(prec);
@@ -408,6 +419,7 @@ size_t estimate_from_host(const HostHierarchy& H, int prec) {
       b += N * N * 8;
     }
     b += 4 * N * 8;
+    if (fp32_residual_level(H, l, prec)) b += N * 4;
     b += (static_cast<size_t>(1) << L.em.dim) * L.bss * L.bss * 8 + 2 * L.em.q1 * L.em.q1 * 8;
   }
   const HostLevel& F = H.levels[0];
@@ -443,6 +455,10 @@ void upload(ldgmg_hier* h, hipStream_t st) {
       upload_level<float, bf16s>(*D, D->L[l], H.levels[l], l == nl - 1, st);
     else
       upload_level<float, float>(*D, D->L[l], H.levels[l], l == nl - 1, st);
+    if (fp32_residual_level(H, l, D->prec)) {
+      if (!D->L[l].tA.tab || !D->L[l].tS.tab) throw std::logic_error("tiled storage differs from its estimate");
+      D->L[l].r32 = static_cast<float*>(D->alloc(static_cast<size_t>(D->L[l].N) * sizeof(float)));
+    }
   }
   const HostLevel& F = H.levels[0];
   DevLevel& f = D->L[0];
@@ -564,30 +580,33 @@ BsrArgs<T, Vd> argsS(const DevLevel& L) {
   return a;
 }
 
-// out = b - A x
+// out = b - A x (or, given out32, the same rounded to FP32 into out32 only)
 template <typename T>
-void residual(const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st) {
+void residual(const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st, float* out32 = nullptr) {
   BsrArgs<T, Vd> a = argsA<T>(L);
   a.x = x;
   a.z = b;
-  a.out = out;
+  a.out = out32 ? nullptr : out;
+  a.out32 = out32;
   a.alpha = -1.0;
   a.beta = 1.0;
   bsr_forward<T, Vd>(a, st);
 }
 
 template <typename T>
-void residual(DevHier& D, const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st) {
+void residual(DevHier& D, const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st,
+              float* out32 = nullptr) {
   ProfScope ps(D, L, st, K_A);
-  residual<T>(L, x, b, out, st);
+  residual<T>(L, x, b, out, st, out32);
 }
 
 // out = alpha S x + beta z   (transposed: S^T)
 template <typename T>
 void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* out, Vd alpha, Vd beta,
-             hipStream_t st) {
+             hipStream_t st, const float* x32 = nullptr) {
   BsrArgs<T, Vd> a = argsS<T>(L);
-  a.x = x;
+  a.x = x32 ? nullptr : x;
+  a.x32 = x32;
   a.z = z;
   a.out = out;
   a.alpha = alpha;
@@ -606,9 +625,9 @@ void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* o
 
 template <typename T>
 void apply_S(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* out, Vd alpha,
-             Vd beta, hipStream_t st) {
+             Vd beta, hipStream_t st, const float* x32 = nullptr) {
   ProfScope ps(D, L, st, transposed ? K_ST : K_SF);
-  apply_S<T>(L, transposed, x, z, out, alpha, beta, st);
+  apply_S<T>(L, transposed, x, z, out, alpha, beta, st, x32);
 }
 
 // one smoothing step on level L with x (in/out), b.  `zero_x`: x is known to be 0.
@@ -626,8 +645,11 @@ Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, boo
       apply_S<TS>(c.D, L, !forward, b, nullptr, x, 1.0, 0.0, c.st);
       return x;
     }
-    residual<T>(c.D, L, x, b, r, c.st);
-    apply_S<TS>(c.D, L, !forward, r, x, x, 1.0, 1.0, c.st);
+    // with FP32 products the smoother apply rounds r to FP32 anyway: the
+    // residual is written in FP32 only, and read as such
+    float* r32 = L.p32 ? L.r32 : nullptr;
+    residual<T>(c.D, L, x, b, r, c.st, r32);
+    apply_S<TS>(c.D, L, !forward, r, x, x, 1.0, 1.0, c.st, r32);
     return x;
   }
   if (sm == LDGMG_SMOOTH_JACOBI) {

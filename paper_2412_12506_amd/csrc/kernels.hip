@@ -400,9 +400,10 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 // l / 16, column l % 16); result lane l = rows l / 16 + 4 i (FP64) or
 // 4 (l / 16) + i (FP32), i < 4, of column l % 16.
 // With MT = ceil(bs/16) row tiles and KS = ceil(bs/4) k steps, k lane q of
-// step s takes the block column tile_k(s, q): 8 (s / 2) + 2 q + s % 2 when
-// 8 divides bs, so that the four k lanes of a column read 64 contiguous bytes
-// of x per 16-byte load, else q KS + s.
+// step s takes the block column tile_k(s, q): 16 (s / 4) + 4 q + s % 4 when
+// 16 divides bs (steps 4j .. 4j+3 of a lane are 4 contiguous entries of x: two
+// 16-byte loads of FP64 x or one of FP32 x), 8 (s / 2) + 2 q + s % 2 when 8
+// divides bs, else q KS + s.
 // Pool layout, E entries per 16 bytes (E = 16 / entry size when E divides KS,
 // else 1): entry [block][m][s / E][lane][s % E] = B(16 m + lane % 16,
 // tile_k(s, lane / 16)), zero outside the block; one 16-byte load of a
@@ -420,7 +421,7 @@ __host__ __device__ constexpr int tile_vec(int KS) {
 
 // block column of k lane q at step s
 __host__ __device__ constexpr int tile_k(int bs, int KS, int s, int q) {
-  return bs % 8 == 0 ? 8 * (s >> 1) + 2 * q + (s & 1) : q * KS + s;
+  return bs % 16 == 0 ? 16 * (s >> 2) + 4 * q + (s & 3) : bs % 8 == 0 ? 8 * (s >> 1) + 2 * q + (s & 1) : q * KS + s;
 }
 
 // the KS operands of this lane in row tile p (= pool block + m 64 KS), widened
@@ -453,14 +454,17 @@ __device__ __forceinline__ v4f mfma_step(float a, float b, v4f c) {
 
 // P32: FP32 products (operands rounded to FP32: the stored FP32 / BF16 entries
 // exactly, the vector entries to nearest) accumulated in FP32; the result is
-// combined with z in FP64.
-template <typename TM, int BS, int LKP, bool P32>   // LKP = log2 of the power of two >= nk
+// combined with z in FP64.  XT / OT: element type of x / out; FP32 x (already
+// rounded by its producer, so the same operand values) or FP32 out only with
+// FP32 products, one right-hand side and 16 | bs.
+template <typename TM, int BS, int LKP, bool P32, typename XT = double, typename OT = double>
 __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
                                                         const int* __restrict__ tab,
                                                         const int* __restrict__ perm,
-                                                        const TM* __restrict__ blk, const double* x,
-                                                        const double* z, double* out, double alpha,
+                                                        const TM* __restrict__ blk, const XT* x,
+                                                        const double* z, OT* out, double alpha,
                                                         double beta, long long stride, int nk) {
+  static_assert(std::is_same<XT, double>::value || (P32 && BS % 16 == 0), "FP32 x: FP32 products, 16 | bs");
   constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
   constexpr int MG = sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
   using OP = typename std::conditional<P32, float, double>::type;
@@ -493,9 +497,29 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const int id = __shfl(myid, c0);
       const unsigned long long sel = __ballot(myid == id) & 0xFFFFull;
       const bool use = (sel >> col) & 1ull;
-      const double* xp = x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0);
+      const XT* xp = x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0);
       OP xb[KS];
-      if constexpr (BS % 8 == 0) {    // steps 2j, 2j+1: columns 8j + 2 kq + {0, 1}, one 16-byte load
+      if constexpr (BS % 16 == 0 && std::is_same<XT, float>::value) {   // steps 4j..4j+3: one 16-byte load
+        const float4* x4 = reinterpret_cast<const float4*>(xp + 4 * kq);
+#pragma unroll
+        for (int j = 0; j < KS / 4; ++j) {
+          const float4 v = x4[4 * j];
+          xb[4 * j] = use ? v.x : OP(0);
+          xb[4 * j + 1] = use ? v.y : OP(0);
+          xb[4 * j + 2] = use ? v.z : OP(0);
+          xb[4 * j + 3] = use ? v.w : OP(0);
+        }
+      } else if constexpr (BS % 16 == 0) {   // steps 4j..4j+3: columns 16j + 4 kq + {0..3}, two 16-byte loads
+        const double2* x2 = reinterpret_cast<const double2*>(xp + 4 * kq);
+#pragma unroll
+        for (int j = 0; j < KS / 4; ++j) {
+          const double2 v0 = x2[8 * j], v1 = x2[8 * j + 1];
+          xb[4 * j] = use ? static_cast<OP>(v0.x) : OP(0);
+          xb[4 * j + 1] = use ? static_cast<OP>(v0.y) : OP(0);
+          xb[4 * j + 2] = use ? static_cast<OP>(v1.x) : OP(0);
+          xb[4 * j + 3] = use ? static_cast<OP>(v1.y) : OP(0);
+        }
+      } else if constexpr (BS % 8 == 0) {    // steps 2j, 2j+1: columns 8j + 2 kq + {0, 1}, one 16-byte load
         const double2* x2 = reinterpret_cast<const double2*>(xp + 2 * kq);
 #pragma unroll
         for (int q = 0; q < KS / 2; ++q) {
@@ -539,7 +563,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       if (r < BS) {
         const size_t o = qoff + static_cast<size_t>(row) * BS + r;
         const double y = static_cast<double>(acc[m][i]);
-        out[o] = beta != 0.0 ? alpha * y + beta * z[o] : alpha * y;
+        out[o] = static_cast<OT>(beta != 0.0 ? alpha * y + beta * z[o] : alpha * y);
       }
     }
 }
@@ -987,6 +1011,24 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   // FP32 products for FP32 / BF16 storage only: FP64 blocks keep FP64 products
   constexpr bool P32 = !std::is_same<TM, double>::value;
   if (a.p32 && !P32) throw std::invalid_argument("bsr_tiled: FP32 products need FP32 or BF16 storage");
+  if (a.x32 || a.out32) {                   // an FP32 vector in or out (smoothing residuals)
+    if constexpr (P32 && BS % 16 == 0) {
+      if (!a.p32 || nk != 1 || (a.x32 && a.out32))
+        throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products and one right-hand side");
+      const int blocks = static_cast<int>((a.nrows + 16 * kWaves - 1) / (16 * kWaves));
+      if (blocks == 0) return;
+      if (a.x32)
+        k_bsr_tiled<TM, BS, 0, true, float, double><<<blocks, kThreads, 0, st>>>(
+            a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x32, a.z, a.out, a.alpha, a.beta, 0, 1);
+      else
+        k_bsr_tiled<TM, BS, 0, true, double, float><<<blocks, kThreads, 0, st>>>(
+            a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out32, a.alpha, a.beta, 0, 1);
+      check_launch("bsr_tiled");
+      return;
+    } else {
+      throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products and 16 | bs");
+    }
+  }
   int lkp = 0;                              // log2 of the power of two >= nk
   while ((1 << lkp) < nk) ++lkp;
   const int rpt = 16 >> lkp;                // block rows per tile

@@ -52,6 +52,8 @@ struct BsrArgs {
   const int* toff = nullptr;
   int noff = 0;
   bool p32 = false;           // tiled storage: FP32 products on the matrix cores
+  const float* x32 = nullptr; // with p32, one right-hand side and 16 | bs: FP32 input in place of x
+  float* out32 = nullptr;     // ... or FP32 output in place of out
   T omega = T(1);
 };
 

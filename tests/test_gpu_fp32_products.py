@@ -3,7 +3,9 @@
 With the mode on, every tiled operator and smoother apply of the V-cycle rounds
 its input to FP32 and multiplies and sums in FP32; the result is combined with
 the FP64 vectors in FP64.  Tolerances, from that arithmetic:
-  * level operations, entry by entry: a row of n stored terms summed in FP32
+  * level operations (operator and smoother applies, smoothing steps, whose
+    residual is written in FP32 where the level is tiled with 16 | bs), entry
+    by entry: a row of n stored terms summed in FP32
     from an FP32-rounded input is within (n + 3) u32 (|M||x|)_i of the FP64
     product of the stored matrix (u32 = 2^-24: n - 1 sums, the products, the
     input rounding, and one unit for a stored entry that the two independent
@@ -94,6 +96,20 @@ def test_level_operations(built):
             torch.cuda.synchronize()
             w = _check_rows(out.cpu().numpy(), M @ x, M, x, (l, op))
             print(f"  level {l} {op}: worst error / bound {w:.3f}", flush=True)
+        # smoothing steps x + B (b - A x): the residual is rounded to FP32 once
+        # (written in FP32 where the level keeps an FP32 residual), then B's
+        # FP32 products; entry-wise first-order bound from both products
+        nA, nS = np.diff(A.tocsr().indptr), np.diff(S.tocsr().indptr)
+        absAx = abs(A) @ np.abs(x)
+        for op, M, n in (("smooth_fwd", S, nS), ("smooth_rev", S.T.tocsr(), np.diff(S.T.tocsr().indptr))):
+            L.ldgmg_level_op(s.handle, l, op, xt, bt, out)
+            torch.cuda.synchronize()
+            ref = x + M @ (b - A @ x)
+            bound = (n + 3) * U32 * (abs(M) @ (np.abs(b) + absAx)) + abs(M) @ ((nA + 3) * U32 * absAx)
+            err = np.abs(out.cpu().numpy() - ref)
+            worst = float(np.max(err / np.maximum(bound, 1e-300)))
+            print(f"  level {l} {op}: worst error / bound {worst:.3f}", flush=True)
+            assert worst <= 1.0, (l, op, worst)
 
 
 def test_vcycle(built):
