@@ -133,13 +133,20 @@ def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_pr
             tiled = storage["tiled_A"] if kind in ("A", "A64") else storage["tiled_S"]
             # algorithmic HBM bytes per launch: the stored blocks (expanded: every
             # slot's block; pooled: the distinct blocks once plus a 4-byte block
-            # id per slot) + block indices + vectors (FP64 input read, FP64 added
-            # vector read, FP64 output written)
+            # id per slot) + block indices + vectors (input read, added vector
+            # read, output written; FP64, but FP32 for the smoothing residual
+            # with FP32 products)
             vec = 3 * N * 8 if kind != "A64" else 2 * N * 8
+            if fp32_products and tiled and bs % 16 == 0 and storage["tiled_A"] and storage["tiled_S"]:
+                # the smoothing residuals are FP32: B and B^T read r in FP32;
+                # of the 6 fine A launches of a V-cycle (nu1 = nu2 = 3, x = 0 at
+                # entry) 5 write r in FP32 and the one before restriction in FP64
+                vec = (4 + 8 + 8) * N if kind in ("S", "ST") else \
+                    ((5 * (8 + 8 + 4) + (8 + 8 + 8)) * N) // 6 if kind == "A" else vec
             idx = (ne + 1) * 4 + nnzb * 4
             blocks = pool * bs * bs * ebk + nnzb * 4 if pool else nnzb * bs * bs * ebk
             byts = blocks + idx + vec
-            flops = 2 * nnzb * bs * bs          # one FP64 FMA per stored entry
+            flops = 2 * nnzb * bs * bs          # one FMA per stored entry (FP64 or FP32 products)
             mean_s = ms / cnt / 1e3 if cnt else None
             kinds[kind] = {"count": cnt, "ms_total": ms, "bytes_per_launch": byts, "flops_per_launch": flops,
                            "pooled": bool(pool), "tiled": bool(tiled), "mean_ms": ms / cnt if cnt else None,
