@@ -176,9 +176,14 @@ int ldgmg_cg_guard(ldgmg_handle h, int enable);
  * preconditioner, while the outer Krylov iteration, its operator, the
  * transfers and the bottom solve stay FP64.  The V-cycle is then no longer
  * one fixed linear operator (the rounding of its input varies), so CG can
- * need more iterations at high coefficient contrast.  Off by default; needs
- * FP32 or BF16S precision (LDGMG_EINVAL otherwise).  Kept across
- * ldgmg_unload / ldgmg_upload. */
+ * need more iterations at high coefficient contrast.  With an SAI smoother,
+ * on levels whose A and B are both tiled and whose block size is a multiple of
+ * 16, the smoothing residual (consumed only by the B or B^T apply, which rounds
+ * it to FP32 anyway) is written in FP32 to a per-level buffer that ldgmg_upload
+ * allocates for such levels whether or not this mode is on (N * 4 bytes,
+ * counted by ldgmg_upload_bytes).  Off by default; needs FP32 or BF16S
+ * precision (LDGMG_EINVAL otherwise).  Kept across ldgmg_unload /
+ * ldgmg_upload. */
 int ldgmg_fp32_products(ldgmg_handle h, int enable);
 
 /* Device bytes the handle holds now (0 when it holds no device data): what
