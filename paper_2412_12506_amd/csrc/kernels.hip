@@ -739,8 +739,8 @@ struct XferLane {
   }
 };
 
-// x_f += I x_c over the children of every coarse element (Section 3.2: the
-// prolongation is the injection of the coarse polynomial into the children).
+// x_f += I x_c over the children of every coarse element (Section 2.2: the
+// interpolation is the injection of the coarse polynomial into the children).
 // The tensor-product child matrices are applied direction by direction as a
 // tree: the direction-k pass turns each of the 2^k partial results into one
 // per child index c_k in {0, 1}, and one shuffle of an input value serves both.
@@ -781,7 +781,8 @@ __global__ __launch_bounds__(256) void k_prolong_tree(int nc, int ncomp, const T
     if (L.valid) xf[L.fine[cp]] = old[cp] + v[cp];
 }
 
-// r_c = I^T r_f (Section 3.2: restriction is the transpose of prolongation),
+// r_c = I^T r_f (Section 2.2: the restriction is the adjoint of the
+// interpolation, which on residual vectors of the discrete system is I^T),
 // the tree of the prolongation run backwards: the direction-k pass pairs the
 // partial results of child index c_k = 0 and 1 and applies the transposed
 // child matrices.
