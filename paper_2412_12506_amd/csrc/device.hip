@@ -47,6 +47,7 @@ struct Tiled {
   int* perm = nullptr;              // rows ordered by their row of tab
   int* off = nullptr;               // column offsets
   int noff = 0;
+  bool quad = false;                // pool in the 4-step k mapping (read with FP32 x)
 };
 
 struct DevLevel {
@@ -267,7 +268,7 @@ size_t level_bytes(int ne, int bs, int bss, int dim, long long nnzA, long long n
 // tiled form of a pooled matrix: the pool in the tiled kernel's operand layout
 // (transposed blocks if asked), the column offsets and the pool-id table
 template <typename T>
-void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, Tiled& t, hipStream_t st) {
+void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, bool quad, Tiled& t, hipStream_t st) {
   const std::vector<int> off = column_offsets(P);
   const int noff = static_cast<int>(off.size());
   // rows with equal blocks at every offset side by side (stable: interior rows
@@ -285,15 +286,18 @@ void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, Tiled& t, hip
   double* pool = nullptr;
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&pool), std::max<size_t>(16, P.pool.data.size() * sizeof(double)), st));
   HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  expand_tiled<T>(nd, bs, pool, blk, transpose, st);
+  expand_tiled<T>(nd, bs, pool, blk, transpose, quad, st);
   HIPCHK(hipFreeAsync(pool, st));
   HIPCHK(hipStreamSynchronize(st));   // the host tables above must outlive their copies
   t.blk = blk;
   t.noff = noff;
+  t.quad = quad;
 }
 
 template <typename TA, typename TS>   // element types of the stored operator and smoother blocks
-void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hipStream_t st) {
+// quad_S: the smoother matrix and its transpose take the 4-step k mapping (they
+// read the FP32 smoothing residual)
+void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, bool quad_S, hipStream_t st) {
   dl.n = hl.n;
   dl.ne = hl.ne;
   dl.bs = hl.bs;
@@ -310,10 +314,10 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
   // device blocks of type T for a pooled host matrix (transposed blocks if
   // asked): every slot's block (expanded), or the distinct blocks once with
   // the block id of every slot in `bid` (pooled; bid stays null otherwise)
-  auto place = [&](auto tag, const PMat& P, bool transpose, int*& bid, Tiled& tiled, bool want_tiled) {
+  auto place = [&](auto tag, const PMat& P, bool transpose, int*& bid, Tiled& tiled, bool want_tiled, bool quad) {
     using T = decltype(tag);
     const bool pooled = use_pool(P, hl.bs, sizeof(T), storage);
-    if (want_tiled) make_tiled<T>(D, P, hl.bs, transpose, tiled, st);
+    if (want_tiled) make_tiled<T>(D, P, hl.bs, transpose, quad, tiled, st);
     const int nd = P.pool.size();
     std::vector<int> order;
     if (pooled) {
@@ -338,14 +342,14 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
   dl.nnzA = hl.A.nnzb();
   dl.rpA = up_ints(hl.A.rp);
   dl.ciA = up_ints(hl.A.ci);
-  dl.valA = place(TA{}, hl.A, false, dl.bidA, dl.tA, use_tiled(hl.A, hl.bs, sizeof(TA), storage));
+  dl.valA = place(TA{}, hl.A, false, dl.bidA, dl.tA, use_tiled(hl.A, hl.bs, sizeof(TA), storage), false);
   if (!bottom) {
     dl.nnzS = hl.S.nnzb();
     dl.rpS = up_ints(hl.S.rp);
     dl.ciS = up_ints(hl.S.ci);
     dl.tposS = up_ints(hl.tpos);
     const bool tiled_S = use_tiled(hl.S, hl.bs, sizeof(TS), storage);
-    dl.valS = place(TS{}, hl.S, false, dl.bidS, dl.tS, tiled_S);
+    dl.valS = place(TS{}, hl.S, false, dl.bidS, dl.tS, tiled_S, quad_S && tiled_S);
     if (fast_bs(hl.bs)) {   // S^T applies stream a transposed copy through the forward kernel
       PMat st;
       st.nbr = hl.S.nbr;
@@ -357,7 +361,7 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, hi
       st.pool.r = hl.S.pool.r;
       st.pool.c = hl.S.pool.c;
       st.pool.data = hl.S.pool.data;
-      dl.valST = place(TS{}, st, true, dl.bidST, dl.tST, tiled_S);
+      dl.valST = place(TS{}, st, true, dl.bidST, dl.tST, tiled_S, quad_S && tiled_S);
     }
     for (const auto& rows : hl.colour_rows) {
       dl.colour_rows.push_back(up_ints(rows));
@@ -450,11 +454,11 @@ void upload(ldgmg_hier* h, hipStream_t st) {
   for (int l = 0; l < nl; ++l) {
     D->L[l].index = l;
     if (D->prec == LDGMG_FP64)
-      upload_level<double, double>(*D, D->L[l], H.levels[l], l == nl - 1, st);
+      upload_level<double, double>(*D, D->L[l], H.levels[l], l == nl - 1, fp32_residual_level(H, l, D->prec), st);
     else if (D->prec == LDGMG_BF16S)
-      upload_level<float, bf16s>(*D, D->L[l], H.levels[l], l == nl - 1, st);
+      upload_level<float, bf16s>(*D, D->L[l], H.levels[l], l == nl - 1, fp32_residual_level(H, l, D->prec), st);
     else
-      upload_level<float, float>(*D, D->L[l], H.levels[l], l == nl - 1, st);
+      upload_level<float, float>(*D, D->L[l], H.levels[l], l == nl - 1, fp32_residual_level(H, l, D->prec), st);
     if (fp32_residual_level(H, l, D->prec)) {
       if (!D->L[l].tA.tab || !D->L[l].tS.tab) throw std::logic_error("tiled storage differs from its estimate");
       D->L[l].r32 = static_cast<float*>(D->alloc(static_cast<size_t>(D->L[l].N) * sizeof(float)));
@@ -488,7 +492,7 @@ void upload(ldgmg_hier* h, hipStream_t st) {
     if (f.tA.tab) {                         // tiled A: the FP64 copy gets its own operand-layout pool
       const long long nd = F.A.pool.size();
       double* tb = static_cast<double*>(D->alloc(static_cast<size_t>(nd) * tiled_block_elems(F.bs) * sizeof(double)));
-      expand_tiled<double>(nd, F.bs, pool, tb, false, st);
+      expand_tiled<double>(nd, F.bs, pool, tb, false, false, st);
       D->t64 = f.tA;
       D->t64.blk = tb;
     }
@@ -550,6 +554,7 @@ void set_tiled(BsrArgs<T, Vd>& a, const Tiled& t) {
   a.tperm = t.perm;
   a.toff = t.off;
   a.noff = t.noff;
+  a.tquad = t.quad;
 }
 
 template <typename T>

@@ -400,10 +400,12 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 // l / 16, column l % 16); result lane l = rows l / 16 + 4 i (FP64) or
 // 4 (l / 16) + i (FP32), i < 4, of column l % 16.
 // With MT = ceil(bs/16) row tiles and KS = ceil(bs/4) k steps, k lane q of
-// step s takes the block column tile_k(s, q): 16 (s / 4) + 4 q + s % 4 when
-// 16 divides bs (steps 4j .. 4j+3 of a lane are 4 contiguous entries of x: two
-// 16-byte loads of FP64 x or one of FP32 x), 8 (s / 2) + 2 q + s % 2 when 8
-// divides bs, else q KS + s.
+// step s takes the block column tile_k(s, q): for a matrix laid out for FP32
+// x ("quad", 16 | bs) 16 (s / 4) + 4 q + s % 4, so that steps 4j .. 4j+3 of a
+// lane are 4 contiguous entries of x (one 16-byte load of FP32 x, two of
+// FP64); otherwise 8 (s / 2) + 2 q + s % 2 when 8 divides bs (the four k lanes
+// of a column read 64 contiguous bytes of FP64 x per 16-byte load), else
+// q KS + s.
 // Pool layout, E entries per 16 bytes (E = 16 / entry size when E divides KS,
 // else 1): entry [block][m][s / E][lane][s % E] = B(16 m + lane % 16,
 // tile_k(s, lane / 16)), zero outside the block; one 16-byte load of a
@@ -420,8 +422,9 @@ __host__ __device__ constexpr int tile_vec(int KS) {
 }
 
 // block column of k lane q at step s
-__host__ __device__ constexpr int tile_k(int bs, int KS, int s, int q) {
-  return bs % 16 == 0 ? 16 * (s >> 2) + 4 * q + (s & 3) : bs % 8 == 0 ? 8 * (s >> 1) + 2 * q + (s & 1) : q * KS + s;
+__host__ __device__ constexpr int tile_k(int bs, int KS, int s, int q, bool quad) {
+  return quad && bs % 16 == 0 ? 16 * (s >> 2) + 4 * q + (s & 3)
+                              : bs % 8 == 0 ? 8 * (s >> 1) + 2 * q + (s & 1) : q * KS + s;
 }
 
 // the KS operands of this lane in row tile p (= pool block + m 64 KS), widened
@@ -456,15 +459,17 @@ __device__ __forceinline__ v4f mfma_step(float a, float b, v4f c) {
 // exactly, the vector entries to nearest) accumulated in FP32; the result is
 // combined with z in FP64.  XT / OT: element type of x / out; FP32 x (already
 // rounded by its producer, so the same operand values) or FP32 out only with
-// FP32 products, one right-hand side and 16 | bs.
-template <typename TM, int BS, int LKP, bool P32, typename XT = double, typename OT = double>
+// FP32 products, one right-hand side and 16 | bs.  QUAD: the matrix is laid out
+// with the 4-step k mapping (required for FP32 x).
+template <typename TM, int BS, int LKP, bool P32, typename XT = double, typename OT = double, bool QUAD = false>
 __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
                                                         const int* __restrict__ tab,
                                                         const int* __restrict__ perm,
                                                         const TM* __restrict__ blk, const XT* x,
                                                         const double* z, OT* out, double alpha,
                                                         double beta, long long stride, int nk) {
-  static_assert(std::is_same<XT, double>::value || (P32 && BS % 16 == 0), "FP32 x: FP32 products, 16 | bs");
+  static_assert(std::is_same<XT, double>::value || (P32 && QUAD && BS % 16 == 0), "FP32 x: FP32 products, quad layout");
+  static_assert(!QUAD || BS % 16 == 0, "the quad layout needs 16 | bs");
   constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
   constexpr int MG = sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
   using OP = typename std::conditional<P32, float, double>::type;
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const bool use = (sel >> col) & 1ull;
       const XT* xp = x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0);
       OP xb[KS];
-      if constexpr (BS % 16 == 0 && std::is_same<XT, float>::value) {   // steps 4j..4j+3: one 16-byte load
+      if constexpr (QUAD && std::is_same<XT, float>::value) {   // steps 4j..4j+3: one 16-byte load
         const float4* x4 = reinterpret_cast<const float4*>(xp + 4 * kq);
 #pragma unroll
         for (int j = 0; j < KS / 4; ++j) {
@@ -509,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
           xb[4 * j + 2] = use ? v.z : OP(0);
           xb[4 * j + 3] = use ? v.w : OP(0);
         }
-      } else if constexpr (BS % 16 == 0) {   // steps 4j..4j+3: columns 16j + 4 kq + {0..3}, two 16-byte loads
+      } else if constexpr (QUAD) {   // steps 4j..4j+3: columns 16j + 4 kq + {0..3}, two 16-byte loads
         const double2* x2 = reinterpret_cast<const double2*>(xp + 4 * kq);
 #pragma unroll
         for (int j = 0; j < KS / 4; ++j) {
@@ -530,7 +535,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       } else {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const int c = tile_k(BS, KS, s, kq);
+          const int c = tile_k(BS, KS, s, kq, QUAD);
           const double v = xp[c < BS ? c : 0];
           xb[s] = (use && c < BS) ? static_cast<OP>(v) : OP(0);
         }
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
 // pooled blocks (row-major FP64) -> the operand layout of k_bsr_tiled
 template <typename T>
 __global__ void k_expand_tiled(long long nblk, int bs, int MT, int KS, const double* __restrict__ pool,
-                               T* __restrict__ out, int transpose) {
+                               T* __restrict__ out, int transpose, int quad) {
   const long long per = static_cast<long long>(MT) * 64 * KS;
   const long long bb = static_cast<long long>(bs) * bs;
   for (long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; t < nblk * per;
@@ -584,7 +589,7 @@ __global__ void k_expand_tiled(long long nblk, int bs, int MT, int KS, const dou
     const int gq = rem / (64 * E);          // m KS / E + s / E
     const int m = gq / (KS / E);
     const int s = (gq % (KS / E)) * E + e;
-    const int r = 16 * m + l % 16, c = tile_k(bs, KS, s, l / 16);
+    const int r = 16 * m + l % 16, c = tile_k(bs, KS, s, l / 16, quad != 0);
     double v = 0.0;
     if (r < bs && c < bs) v = transpose ? pool[b * bb + static_cast<long long>(c) * bs + r] : pool[b * bb + static_cast<long long>(r) * bs + c];
     out[t] = narrow<T>(v);
@@ -1014,15 +1019,19 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   if (a.p32 && !P32) throw std::invalid_argument("bsr_tiled: FP32 products need FP32 or BF16 storage");
   if (a.x32 || a.out32) {                   // an FP32 vector in or out (smoothing residuals)
     if constexpr (P32 && BS % 16 == 0) {
-      if (!a.p32 || nk != 1 || (a.x32 && a.out32))
-        throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products and one right-hand side");
+      if (!a.p32 || nk != 1 || (a.x32 && a.out32) || (a.x32 && !a.tquad))
+        throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products, one right-hand side and, "
+                                    "for FP32 x, the quad layout");
       const int blocks = static_cast<int>((a.nrows + 16 * kWaves - 1) / (16 * kWaves));
       if (blocks == 0) return;
       if (a.x32)
-        k_bsr_tiled<TM, BS, 0, true, float, double><<<blocks, kThreads, 0, st>>>(
+        k_bsr_tiled<TM, BS, 0, true, float, double, true><<<blocks, kThreads, 0, st>>>(
             a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x32, a.z, a.out, a.alpha, a.beta, 0, 1);
+      else if (a.tquad)
+        k_bsr_tiled<TM, BS, 0, true, double, float, true><<<blocks, kThreads, 0, st>>>(
+            a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out32, a.alpha, a.beta, 0, 1);
       else
-        k_bsr_tiled<TM, BS, 0, true, double, float><<<blocks, kThreads, 0, st>>>(
+        k_bsr_tiled<TM, BS, 0, true, double, float, false><<<blocks, kThreads, 0, st>>>(
             a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out32, a.alpha, a.beta, 0, 1);
       check_launch("bsr_tiled");
       return;
@@ -1030,6 +1039,8 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
       throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products and 16 | bs");
     }
   }
+  if (a.tquad && !(P32 && BS % 16 == 0))
+    throw std::invalid_argument("bsr_tiled: the quad layout needs FP32 or BF16 storage and 16 | bs");
   int lkp = 0;                              // log2 of the power of two >= nk
   while ((1 << lkp) < nk) ++lkp;
   const int rpt = 16 >> lkp;                // block rows per tile
@@ -1039,6 +1050,17 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   switch (lkp) {
 #define TILED(LK)                                                                                              \
   case LK:                                                                                                     \
+    if constexpr (P32 && BS % 16 == 0) {                                                                       \
+      if (a.tquad) {                                                                                           \
+        if (a.p32)                                                                                             \
+          k_bsr_tiled<TM, BS, LK, true, double, double, true><<<blocks, kThreads, 0, st>>>(                    \
+              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+        else                                                                                                   \
+          k_bsr_tiled<TM, BS, LK, false, double, double, true><<<blocks, kThreads, 0, st>>>(                   \
+              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+        break;                                                                                                 \
+      }                                                                                                        \
+    }                                                                                                          \
     if (P32 && a.p32)                                                                                          \
       k_bsr_tiled<TM, BS, LK, P32><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm,       \
                                                                a.tblk, a.x, a.z, a.out, a.alpha, a.beta,       \
@@ -1198,11 +1220,13 @@ void expand_blocks(long long nslots, int bs, const int* ids, const double* pool,
 }
 
 template <typename T>
-void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool transpose, hipStream_t st) {
+void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool transpose, bool quad, hipStream_t st) {
+  if (quad && bs % 16 != 0) throw std::invalid_argument("expand_tiled: the quad layout needs 16 | bs");
   if (nblk == 0) return;
   const int MT = (bs + 15) / 16, KS = (bs + 3) / 4;
   const long long total = nblk * MT * 64 * KS;
-  k_expand_tiled<T><<<grid_for(total, 256, 65536), 256, 0, st>>>(nblk, bs, MT, KS, pool, out, transpose ? 1 : 0);
+  k_expand_tiled<T><<<grid_for(total, 256, 65536), 256, 0, st>>>(nblk, bs, MT, KS, pool, out, transpose ? 1 : 0,
+                                                                 quad ? 1 : 0);
   check_launch("expand_tiled");
 }
 
@@ -1334,9 +1358,9 @@ template void bsr_forward<bf16s, double>(const BsrArgs<bf16s, double>&, hipStrea
 template void bsr_transposed<bf16s, double>(const BsrArgs<bf16s, double>&, hipStream_t);
 template void bsr_forward_multi<bf16s, double>(const BsrArgs<bf16s, double>&, long long, int, hipStream_t);
 template void expand_blocks<bf16s>(long long, int, const int*, const double*, bf16s*, bool, hipStream_t);
-template void expand_tiled<float>(long long, int, const double*, float*, bool, hipStream_t);
-template void expand_tiled<double>(long long, int, const double*, double*, bool, hipStream_t);
-template void expand_tiled<bf16s>(long long, int, const double*, bf16s*, bool, hipStream_t);
+template void expand_tiled<float>(long long, int, const double*, float*, bool, bool, hipStream_t);
+template void expand_tiled<double>(long long, int, const double*, double*, bool, bool, hipStream_t);
+template void expand_tiled<bf16s>(long long, int, const double*, bf16s*, bool, bool, hipStream_t);
 template void expand_blocks<float>(long long, int, const int*, const double*, float*, bool, hipStream_t);
 template void expand_blocks<double>(long long, int, const int*, const double*, double*, bool, hipStream_t);
 template void restrict_op<double>(int, int, int, int, int, const double*, const double*, const double*, double*,

@@ -52,6 +52,7 @@ struct BsrArgs {
   const int* toff = nullptr;
   int noff = 0;
   bool p32 = false;           // tiled storage: FP32 products on the matrix cores
+  bool tquad = false;         // the tiled pool uses the 4-step k mapping (16 | bs; required for x32)
   const float* x32 = nullptr; // with p32, one right-hand side and 16 | bs: FP32 input in place of x
   float* out32 = nullptr;     // ... or FP32 output in place of out
   T omega = T(1);
@@ -59,7 +60,7 @@ struct BsrArgs {
 
 // expand pooled FP64 blocks (row-major) into the operand layout of the tiled kernel
 template <typename T>
-void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool transpose, hipStream_t st);
+void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool transpose, bool quad, hipStream_t st);
 // elements per pooled block in that layout
 inline long long tiled_block_elems(int bs) { return static_cast<long long>((bs + 15) / 16) * 64 * ((bs + 3) / 4); }
 
