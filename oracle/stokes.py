@@ -28,7 +28,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .ldg import (Grid, ElementMatrices, assemble_gradient, assemble_penalty,
-                  block_diag, to_bsr)
+                  block_diag, to_bsr, volume_load, dirichlet_lifting, face_load)
 from .hierarchy import Level, level_sizes, injection, coarsen_factors
 
 
@@ -113,3 +113,47 @@ def _ones_moments(ref):
     from .basis import gauss_legendre
     t, w = gauss_legendre(ref.p + 2)
     return ref.basis.eval(t) @ w
+
+
+def stokes_rhs(level: Level, mu, f_qp=None, nq: int = 8, g=None,
+               tau0: float = 1.0) -> np.ndarray:
+    """Right-hand side of eq:components with a body force and velocity
+    Dirichlet data (Section 3.1; the scalar data terms of Section 2.1 applied
+    per velocity component).
+
+    f_qp: list of d arrays [ne, nq^d], f_i at the tensor Gauss points;
+    g:    list of d callables, the boundary velocity.
+    Moving the data part of each velocity gradient, G_k^full u_i =
+    G_k u_i + L_k g_i, to the right-hand side gives
+      b_{u_i} = int f_i v - sum_k G_k^T M_mu L_k g_i
+                - gamma sum_j G_j^T M_mu L_i g_j + sum_{F Dirichlet} tau_F int_F g_i v,
+      b_p     = sum_j M L_j g_j
+    (the continuity row of eq:components is -sum_j M G_j^full u_j - E_p p = 0).
+    Returns the element-major vector [u_1 .. u_d, p] per element."""
+    grid, em = level.grid, level.em
+    d, bss, ne = grid.dim, em.bs, grid.ne
+    mu = np.asarray(mu, dtype=np.float64)
+    comp = np.zeros((d + 1, ne * bss))
+    if f_qp is not None:
+        for i in range(d):
+            comp[i] += volume_load(em, f_qp[i], nq)
+    if g is not None:
+        G = [Gk.tocsr() for Gk in level.G]
+        Mmu = level.Mmu.tocsr()
+        M = level.M.tocsr()
+        L = [dirichlet_lifting(level, g[i], nq) for i in range(d)]   # L[i][k] = L_k g_i
+        for i in range(d):
+            for k in range(d):
+                comp[i] -= G[k].T @ (Mmu @ L[i][k])
+                comp[i] -= level.gamma * (G[k].T @ (Mmu @ L[k][i]))
+            for e in range(ne):
+                for k in range(d):
+                    for side in (-1, 1):
+                        if grid.neighbour(e, k, side) is None and \
+                                grid.boundary_type(k, side) == "D":
+                            tau = tau0 * mu[e] / grid.h
+                            comp[i, e * bss:(e + 1) * bss] += \
+                                tau * face_load(grid, em, e, k, side, g[i], nq)
+        for j in range(d):
+            comp[d] += M @ L[j][j]
+    return comp.reshape(d + 1, ne, bss).transpose(1, 0, 2).reshape(-1)

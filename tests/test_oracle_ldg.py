@@ -143,3 +143,112 @@ def test_transfer_identities():
     assert np.abs((I.T @ Mh @ I - M2h).toarray()).max() < 1e-14
     R = np.linalg.inv(M2h.toarray()) @ (I.T @ Mh).toarray()
     assert np.allclose(R @ I.toarray(), np.eye(M2h.shape[0]), atol=1e-12)
+
+
+def _l2_coefficients(level, funcs, nq):
+    """Element-wise L2 projection of each callable onto Q_p (per component),
+    stacked element-major [u_1 .. u_d, p]."""
+    em, n, dim = level.em, level.grid.n, level.grid.dim
+    cols = [ldg.volume_load(em, sample_on_elements(dim, n, nq, f), nq).reshape(-1, em.bs)
+            @ em.Minv.T for f in funcs]
+    return np.stack(cols, axis=1).reshape(-1)
+
+
+def _stokes_exactness_residual(dim, n, p, gamma, mu, u, pres, f, nq):
+    """max |A x_ex - b| / max(|A||x_ex| + |b|) for the exact solution's
+    coefficients x_ex (a solution in the discrete space satisfies the
+    discrete equations exactly: LDG consistency, Section 3.1)."""
+    lv = stokes.stokes_levels(dim, n, p, mu=mu, gamma=gamma, cp=0.1)[0]
+    fq = [sample_on_elements(dim, n, nq, fi) for fi in f]
+    b = stokes.stokes_rhs(lv, mu, fq, nq, u)
+    x = _l2_coefficients(lv, list(u) + [pres], nq)
+    A = lv.A.tocsr()
+    r = A @ x - b
+    return np.abs(r).max() / (abs(A) @ np.abs(x) + np.abs(b)).max(), lv, b
+
+
+@pytest.mark.parametrize("gamma", [0, 1])
+def test_stokes_polynomial_reproduction_2d(gamma):
+    """Divergence-free u in Q_2^2 (u = curl of x^2 y^2) and p = x y in Q_2 with
+    unit viscosity, velocity Dirichlet data g = u and f = -Lap u + grad p (the
+    stress term gamma grad(div u) vanishes): the discrete Stokes system of
+    eq:components is solved exactly, in standard (gamma = 0) and stress
+    (gamma = 1) form.  Both the residual of the exact coefficients and the
+    solution of the singular system (bordered with the pressure kernel) are
+    checked; the pressure is compared modulo its constant."""
+    dim, n, p, nq = 2, 3, 2, 5
+    u = [lambda x, y: 2 * x ** 2 * y, lambda x, y: -2 * x * y ** 2]
+    pres = lambda x, y: x * y
+    f = [lambda x, y: -4 * y + y, lambda x, y: 4 * x + x]
+    res, lv, b = _stokes_exactness_residual(dim, n, p, gamma, np.ones(n * n), u, pres, f, nq)
+    assert res < 1e-13
+    A = lv.A.toarray()
+    k = stokes.pressure_kernel(lv)
+    N = A.shape[0]
+    K = np.block([[A, k[:, None]], [k[None, :], np.zeros((1, 1))]])
+    x = np.linalg.solve(K, np.concatenate([b, [0.0]]))
+    assert abs(x[N]) < 1e-12 * np.abs(b).max()      # b is consistent (orthogonal to the kernel)
+    X = x[:N].reshape(n * n, dim + 1, -1)
+    for i, fn in enumerate(list(u) + [pres]):
+        vals, W = ldg.evaluate(lv, X[:, i].reshape(-1), nq)
+        ex = sample_on_elements(dim, n, nq, fn)
+        if i == dim:
+            vals = vals - (vals * W).sum() / (W.sum() * n * n)
+            ex = ex - (ex * W).sum() / (W.sum() * n * n)
+        assert np.abs(vals - ex).max() < 1e-11
+
+
+@pytest.mark.parametrize("gamma", [0, 1])
+def test_stokes_polynomial_reproduction_3d(gamma):
+    """3D: u = (2x^2yz, -2xy^2z, xy) (divergence free, Q_2^3), p = x + yz."""
+    u = [lambda x, y, z: 2 * x ** 2 * y * z, lambda x, y, z: -2 * x * y ** 2 * z,
+         lambda x, y, z: x * y + 0 * z]
+    pres = lambda x, y, z: x + y * z
+    f = [lambda x, y, z: -4 * y * z + 1 + 0 * x, lambda x, y, z: 4 * x * z + z + 0 * y,
+         lambda x, y, z: y + 0 * x]
+    res, _, _ = _stokes_exactness_residual(3, 2, 2, gamma, np.ones(8), u, pres, f, 4)
+    assert res < 1e-13
+
+
+@pytest.mark.parametrize("ratio", [1e-4, 1e4, 10.0])
+def test_stokes_stress_form_planar_interface(ratio):
+    """Stress form across the face-aligned interface x = 1/2 (viscosity
+    `ratio` left, 1 right): u = (c y, b(x)) with b piecewise linear is
+    divergence free and force free in the bulk, and the traction
+    mu (grad u + grad u^T) e_x is continuous iff mu_L (b_L' + c) =
+    mu_R (b_R' + c).  That solution is reproduced exactly by the stress form
+    only: the same data do not satisfy the standard form (whose traction is
+    mu grad u e_x), and a stress term with its indices swapped
+    (gamma G_i^T M_mu G_j, a grad-div term) leaves a residual of 2-5e-2."""
+    dim, n, p, nq = 2, 4, 2, 5
+    mu = np.array([ratio if (e % n) < n // 2 else 1.0 for e in range(n * n)])
+    c, sR = 1.0, 1.0
+    sL = (sR + c) / ratio - c
+    u = [lambda x, y: c * y + 0 * x,
+         lambda x, y: np.where(x < 0.5, sL * x, sL * 0.5 + sR * (x - 0.5)) + 0 * y]
+    zero = lambda x, y: 0 * x
+    res, _, _ = _stokes_exactness_residual(dim, n, p, 1, mu, u, zero, [zero, zero], nq)
+    assert res < 1e-13
+    res0, _, _ = _stokes_exactness_residual(dim, n, p, 0, mu, u, zero, [zero, zero], nq)
+    assert res0 > 1e-7
+
+
+@pytest.mark.parametrize("system", ["poisson", "stokes"])
+@pytest.mark.parametrize("dim,p", [(2, 2), (3, 1)])
+@pytest.mark.parametrize("ratio", [1e-4, 1e4])
+def test_factor_coarsening_variable_mu_aligned_box(system, dim, p, ratio):
+    """Inner box (1/4,3/4)^d at viscosity ratio 1e+-4 on n = 8, whose faces lie
+    on faces of the n = 4 grid: the factor-coarsened A_2h (upwinded G, mu-mass,
+    1/2 I^T E I, 2 I^T E_p I) equals A assembled directly on the n = 4 grid
+    with the same box (Section 2.2: operator coarsening is equivalent to
+    re-discretisation)."""
+    n = 8
+    mu_f, mu_c = mu_box(dim, n, ratio), mu_box(dim, n // 2, ratio)
+    if system == "poisson":
+        lv = hierarchy.scalar_levels(dim, n, p, mu=mu_f)
+        direct = ldg.assemble_scalar(dim, n // 2, p, mu=mu_c).A
+    else:
+        lv = stokes.stokes_levels(dim, n, p, mu=mu_f, gamma=1, cp=0.1)
+        direct = stokes.stokes_levels(dim, n // 2, p, mu=mu_c, gamma=1, cp=0.1)[0].A
+    D = direct.toarray()
+    assert np.abs(lv[1].A.toarray() - D).max() <= 1e-13 * np.abs(D).max()

@@ -231,3 +231,21 @@ def test_stokes_sai_beats_gs_loose():
         etas[sm_ + order] = r.eta
     assert etas["saiOI"] < etas["gsOO"] < etas["saiIO"]
     assert etas["saiOI"] < 1.0
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dim,n,p", [(2, 16, 2), (3, 6, 2)])
+def test_headline_iteration_anchor_sai2(dim, n, p):
+    """The paper's quantitative anchor (abstract; Section 4): for every test
+    at least one combination reaches a 1e10 residual reduction within 4-8
+    iterations, SAI_2 among the fastest.  SAI_2 OI CG on Poisson with a
+    U[-1,1] right-hand side reaches 1e-10 in at most 8 iterations in 2D and
+    3D (the oracle gives 3 and 6), and converges faster than SAI_1 OI
+    (Section 4: eta(SAI_2) is up to 2-3x smaller than eta(SAI_1))."""
+    lv = hierarchy.scalar_levels(dim, n, p)
+    b = rhs_uniform(lv[0].A.shape[0], 11)
+    A = lv[0].A.tocsr()
+    r2 = krylov.pcg(A, b, vcycle.build_mg(lv, "sai", 2, "OI").apply)
+    r1 = krylov.pcg(A, b, vcycle.build_mg(lv, "sai", 1, "OI").apply)
+    assert r2.converged and r2.iters <= 8 and r2.rel_res_true < 1e-10 * 1.5
+    assert r1.converged and r2.iters < r1.iters and r2.eta < r1.eta
