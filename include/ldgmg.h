@@ -44,7 +44,8 @@ enum {
   LDGMG_ENOMEM = -2,    /* over the HBM budget or device allocation failed    */
   LDGMG_EHIP = -3,      /* HIP runtime error                                  */
   LDGMG_ENOCONV = -4,   /* maxit reached; the info struct is still filled     */
-  LDGMG_ESINGULAR = -5, /* rank-deficient local problem in the setup          */
+  LDGMG_ESINGULAR = -5, /* rank-deficient local problem in the setup, or an
+                           inconsistent right-hand side (ldgmg_rhs_check)     */
   LDGMG_ESTATE = -6     /* call not valid in the handle's state (e.g. no device data) */
 };
 
@@ -103,6 +104,22 @@ typedef struct {
   int nthreads;       /* host threads for the setup; <= 0 -> hardware count      */
   size_t hbm_budget;  /* refuse ldgmg_upload above this many bytes; 0 = no limit */
   int storage;        /* LDGMG_STORE_* (default AUTO)                            */
+  /* Device memory of the handle.  NULL (the default): hipMalloc / hipFree.
+   * Otherwise every device buffer the handle owns (what ldgmg_upload
+   * allocates, its temporary upload buffers, and the batch and GMRES
+   * workspaces made by later calls) is taken with dev_alloc(bytes, alloc_ctx),
+   * which returns device memory of the current device aligned to 256 bytes, or
+   * NULL (the call then fails with LDGMG_ENOMEM); it is handed back with
+   * dev_free(ptr, alloc_ctx) by ldgmg_unload / ldgmg_destroy, and temporary
+   * upload buffers once the upload's stream has drained.  Both or neither
+   * (else LDGMG_EINVAL).  The callbacks are called from the calling thread of
+   * the entry point and must not call into the library.  For callers whose
+   * allocator accounts for device memory (a caching allocator of a tensor
+   * framework): hierarchies then count in its budget, and evicting one returns
+   * its memory to that allocator without a device-wide synchronisation. */
+  void* (*dev_alloc)(size_t bytes, void* alloc_ctx);
+  void (*dev_free)(void* ptr, void* alloc_ctx);
+  void* alloc_ctx;
 } ldgmg_problem;
 
 typedef struct {
@@ -224,22 +241,81 @@ int ldgmg_vcycle(ldgmg_handle h, const double* b_dev, double* x_dev, void* strea
  * (LDGMG_GMRES, no restart, at most min(maxit, 200) iterations).  Stops when
  * ||r||_2 <= rtol ||b||_2 (CG, FP64 recursive residual) or
  * ||V r||_2 <= rtol ||V b||_2 (GMRES).  Returns LDGMG_ENOCONV if maxit is hit
- * or, with ldgmg_cg_guard enabled, at a CG breakdown.  info may be NULL. */
+ * or, with ldgmg_cg_guard enabled, at a CG breakdown.  info may be NULL.
+ *
+ * Singular operators (Section 3.1: the Stokes pressure is defined up to a
+ * constant; likewise a scalar problem without a Dirichlet face): the kernel of
+ * constants found at upload (ldgmg_kernel) is handled by projecting b on the
+ * range, b' = b - sum_i (b . k_i) k_i with orthonormal kernel vectors k_i,
+ * solving A x = b', and returning the solution whose kernel components have
+ * zero mean (for Stokes with velocity Dirichlet data: int p = 0).  The
+ * residuals in info are relative to ||b'||.  With ldgmg_rhs_check set, a
+ * right-hand side with |b . k_i| > tol ||b|| is refused with LDGMG_ESINGULAR
+ * before any iteration. */
 int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov,
                 double rtol, int maxit, ldgmg_info* info, void* stream);
 
-/* Batched serving step: k <= 8 right-hand sides of the same hierarchy.  Each
- * right-hand side runs its own preconditioned CG recurrence (as ldgmg_solve
- * with LDGMG_CG; right-hand sides that converge are frozen), while every
- * V-cycle stage and every operator apply of the batch streams each matrix
- * block once for all k vectors.  b_dev / x_dev: host arrays of k device FP64
- * pointers (fine-level layout).  infos: k entries or NULL.  Returns
- * LDGMG_ENOCONV if any right-hand side reaches maxit.  Needs workspace of
- * 9 k-vector sets on the fine level (allocated on the first batched call). */
-int ldgmg_solve_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k,
-                      double rtol, int maxit, ldgmg_info* infos, void* stream);
+/* Consistency check of right-hand sides for singular operators: tol > 0
+ * makes ldgmg_solve / ldgmg_solve_batch return LDGMG_ESINGULAR when
+ * |b . k_i| > tol ||b||_2 for a unit kernel vector k_i (Section 3.1: A x = b
+ * has a solution only for b orthogonal to the kernel of the symmetric A);
+ * tol = 0 (the default) projects every b silently.  Kept across
+ * ldgmg_unload / ldgmg_upload.  No effect on nonsingular operators. */
+int ldgmg_rhs_check(ldgmg_handle h, double tol);
 
-/* x_q = V b_q for k <= 8 right-hand sides with one batched V-cycle. */
+/* Kernel of the fine operator found at upload (needs device data): *count
+ * unit vectors (0 for a nonsingular operator), each the constant function of
+ * one component (the pressure of Stokes; the scalar field, or the velocity
+ * components, when no box face is Dirichlet), kept only if A k = 0 to
+ * 1e-10 |A||k| row by row.  host_out: NULL, or *count * ndofs doubles,
+ * receiving the vectors (fine-level layout). */
+int ldgmg_kernel(ldgmg_handle h, int* count, double* host_out);
+
+/* Batched serving step: k right-hand sides, right-hand side q on hierarchy
+ * hs[q] (the same handle may appear several times; handles may differ in
+ * size and problem).  Every right-hand side is solved as by ldgmg_solve with
+ * `krylov` (same stopping rule, kernel handling and info).  Right-hand sides
+ * of one handle share the work: with LDGMG_CG they run in groups of up to 16,
+ * each with its own preconditioned CG recurrence (a right-hand side that
+ * converges is frozen) while every V-cycle stage and operator apply streams
+ * each matrix block once for the group; with LDGMG_GMRES they run one after
+ * the other.  b_dev / x_dev: host arrays of k device FP64 pointers
+ * (fine-level layout of their handle).  infos: k entries or NULL; vcycles
+ * counts the V-cycles applied to that right-hand side.  Returns LDGMG_ENOCONV
+ * if any right-hand side is not converged.  Handles must be distinct or
+ * identical, never two handles sharing device data, and all on the current
+ * device.  A handle's first batched CG call allocates 5 fine-level vector
+ * sets plus 4 on every level, each of 8 vectors (16 once more than 8
+ * right-hand sides share a group). */
+int ldgmg_solve_batch(const ldgmg_handle* hs, const double* const* b_dev, double* const* x_dev, int k,
+                      int krylov, double rtol, int maxit, ldgmg_info* infos, void* stream);
+
+/* Continuous batching on one hierarchy (serving): CG solves whose right-hand
+ * sides are handed over while others are in flight.  Up to `slots` (1..16)
+ * preconditioned CG recurrences run at once, each exactly that of
+ * ldgmg_solve with LDGMG_CG on its own right-hand side (same stopping rule,
+ * guard and kernel handling), while every V-cycle stage and operator apply
+ * streams each matrix block once for all slots in use.  Before every V-cycle
+ * stage the library fills free slots by calling
+ *     next(ctx, &b_dev, &x_dev, &tag)
+ * which returns 1 with a right-hand side, its solution vector (device FP64,
+ * fine-level layout, valid until done() reports that tag) and a caller tag,
+ * or 0 when nothing is waiting now (it is asked again at the next stage while
+ * a slot is free, so right-hand sides that arrive meanwhile are admitted).  A
+ * new right-hand side joins the batch at that stage with its first V-cycle.  When a recurrence stops (converged, maxit, guarded
+ * breakdown) its solution is written to x_dev, then
+ *     done(ctx, tag, status, &info)
+ * is called (status LDGMG_OK or LDGMG_ENOCONV; info as ldgmg_solve fills
+ * it) and the slot is free again.  Returns when no slot is in flight and
+ * next() returns 0: LDGMG_ENOCONV if any right-hand side did not converge.  The callbacks run on the calling thread, between the library's
+ * launches on `stream`, and must not call into the library with this
+ * handle.  Workspace as for ldgmg_solve_batch with `slots` right-hand sides. */
+int ldgmg_solve_stream(ldgmg_handle h, int slots, double rtol, int maxit,
+                       int (*next)(void* ctx, const double** b_dev, double** x_dev, long long* tag),
+                       void (*done)(void* ctx, long long tag, int status, const ldgmg_info* info),
+                       void* ctx, void* stream);
+
+/* x_q = V b_q for k <= 16 right-hand sides with one batched V-cycle. */
 int ldgmg_vcycle_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k,
                        void* stream);
 

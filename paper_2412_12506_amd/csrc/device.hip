@@ -33,6 +33,9 @@ struct BudgetError : std::runtime_error {
 struct StateError : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
+struct SingularError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
 
 #define HIPCHK(x)                                                                      \
   do {                                                                                 \
@@ -98,13 +101,26 @@ struct DevHier {
   int Qcap = 0;
   double* hvec = nullptr;           // device small vectors (GMRES coefficients)
   std::vector<void*> allocs;
+  std::vector<size_t> sizes;
   size_t bytes = 0;
+  // caller's device allocator (ldgmg_problem::dev_alloc / dev_free), or null: hipMalloc / hipFree
+  void* (*ualloc)(size_t, void*) = nullptr;
+  void (*ufree)(void*, void*) = nullptr;
+  void* uctx = nullptr;
+  // kernel of the fine operator (singular problems): nker unit vectors khat_i
+  // (Euclidean norm 1) and their mean weights w_i = M khat_i / (khat_i^T M khat_i),
+  // each [N]; bproj holds projected right-hand sides (kMaxRhs vectors)
+  int nker = 0;
+  double* khat = nullptr;
+  double* kw = nullptr;
+  double* bproj = nullptr;
   // batched solves (ldgmg_solve_batch): per level [kMaxRhs][N] x, b, r, t and the
   // fine-level Krylov vectors; allocated on the first batched call
   struct BatchLevel {
     double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
   };
   std::vector<BatchLevel> BL;
+  int bcap = 0;                     // right-hand sides the batch vectors hold (8 or kMaxRhs)
   double *bx = nullptr, *br = nullptr, *bp = nullptr, *bq = nullptr, *bz = nullptr;
   double* bscal = nullptr;          // per right-hand side scalars [kMaxRhs][8]
   double* hbscal = nullptr;         // pinned host mirror
@@ -117,18 +133,60 @@ struct DevHier {
   };
   std::vector<Rec> recs;
 
-  void* alloc(size_t n) {
+  void* raw_alloc(size_t n) {
     void* p = nullptr;
     if (n == 0) n = 16;
+    if (ualloc) {
+      p = ualloc(n, uctx);
+      if (!p) throw BudgetError("the caller's dev_alloc returned NULL for " + std::to_string(n) + " bytes");
+      return p;
+    }
     const hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) throw BudgetError(std::string("hipMalloc failed: ") + hipGetErrorString(e));
-    allocs.push_back(p);
-    bytes += n;
     return p;
+  }
+  void* alloc(size_t n) {
+    void* p = raw_alloc(n);
+    allocs.push_back(p);
+    sizes.push_back(n == 0 ? 16 : n);
+    bytes += n == 0 ? 16 : n;
+    return p;
+  }
+  // give one buffer of `alloc` back before the handle goes (its users on the
+  // device must have finished: the caller synchronises first)
+  void release(void* p) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        if (ufree) ufree(p, uctx);
+        else (void)hipFree(p);
+        bytes -= sizes[i];
+        allocs.erase(allocs.begin() + static_cast<long>(i));
+        sizes.erase(sizes.begin() + static_cast<long>(i));
+        return;
+      }
+  }
+  // temporary upload buffers: stream-ordered with HIP's pool, or the caller's
+  // allocator (freed once the stream has drained)
+  void* stage(size_t n, hipStream_t st) {
+    if (ualloc) return raw_alloc(n);
+    void* p = nullptr;
+    HIPCHK(hipMallocAsync(&p, std::max<size_t>(16, n), st));
+    return p;
+  }
+  void unstage(void* p, hipStream_t st) {
+    if (ualloc) {
+      HIPCHK(hipStreamSynchronize(st));
+      ufree(p, uctx);
+      return;
+    }
+    HIPCHK(hipFreeAsync(p, st));   // stream-ordered: no device-wide synchronisation
   }
   ~DevHier() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) {
+      if (ufree) ufree(p, uctx);
+      else (void)hipFree(p);
+    }
     if (hscal) (void)hipHostFree(hscal);
     if (hbscal) (void)hipHostFree(hbscal);
   }
@@ -142,12 +200,13 @@ struct ldgmg_hier {
   std::unique_ptr<ldgmg::DevHier> dev;
   bool cg_guard = false;            // ldgmg_cg_guard
   bool fp32_products = false;       // ldgmg_fp32_products
+  double rhs_check = 0.0;           // ldgmg_rhs_check tolerance (0: off)
 };
 
 namespace ldgmg {
 namespace {
 
-enum { S_BB = 0, S_RZ = 1, S_ALPHA = 2, S_RR = 3, S_BETA = 4, S_PQ = 5, S_TMP = 6, S_W = 7 };
+enum { S_BB = 0, S_RZ = 1, S_ALPHA = 2, S_RR = 3, S_BETA = 4, S_PQ = 5, S_TMP = 6, S_W = 7, S_K = 8 };
 
 // bytes per stored entry of the operators A and of the smoother S
 size_t elem_bytes_A(int prec) { return prec == LDGMG_FP64 ? 8 : 4; }
@@ -283,11 +342,10 @@ void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, bool quad, Ti
   t.off = static_cast<int*>(D.alloc(std::max<size_t>(16, off.size() * sizeof(int))));
   HIPCHK(hipMemcpyAsync(t.tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(t.off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  double* pool = nullptr;
-  HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&pool), std::max<size_t>(16, P.pool.data.size() * sizeof(double)), st));
+  double* pool = static_cast<double*>(D.stage(P.pool.data.size() * sizeof(double), st));
   HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
   expand_tiled<T>(nd, bs, pool, blk, transpose, quad, st);
-  HIPCHK(hipFreeAsync(pool, st));
+  D.unstage(pool, st);
   HIPCHK(hipStreamSynchronize(st));   // the host tables above must outlive their copies
   t.blk = blk;
   t.noff = noff;
@@ -326,15 +384,13 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, bo
     }
     const std::vector<int>& ids_h = pooled ? order : P.id;
     T* out = static_cast<T*>(D.alloc(ids_h.size() * bb * sizeof(T)));
-    double* pool = nullptr;
-    int* ids = nullptr;
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&pool), std::max<size_t>(16, P.pool.data.size() * sizeof(double)), st));
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&ids), std::max<size_t>(16, ids_h.size() * sizeof(int)), st));
+    double* pool = static_cast<double*>(D.stage(P.pool.data.size() * sizeof(double), st));
+    int* ids = static_cast<int*>(D.stage(ids_h.size() * sizeof(int), st));
     HIPCHK(hipMemcpyAsync(pool, P.pool.data.data(), P.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ids, ids_h.data(), ids_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
     expand_blocks<T>(static_cast<long long>(ids_h.size()), hl.bs, ids, pool, out, transpose, st);
-    HIPCHK(hipFreeAsync(pool, st));   // stream-ordered: no device-wide synchronisation
-    HIPCHK(hipFreeAsync(ids, st));
+    D.unstage(pool, st);
+    D.unstage(ids, st);
     HIPCHK(hipStreamSynchronize(st));  // the host id list must outlive its copy
     bid = pooled ? up_ints(P.id) : nullptr;
     return out;
@@ -439,6 +495,136 @@ size_t estimate_from_host(const HostHierarchy& H, int prec) {
   return b;
 }
 
+// Kernel of the fine operator.  Candidates: the constant function in one
+// component (the scalar field of a problem with no Dirichlet face, the
+// pressure of Stokes, the velocity components of Stokes with no Dirichlet
+// face); a candidate k is kept when |A k| <= 1e-10 (|A| |k|) row by row in
+// FP64, evaluated per distinct block of the pooled A.  Per element the
+// constant's coefficients are c1 (x) c1 (x) c1 with c1 = m^-1 (int psi_i),
+// m the 1-D mass matrix.
+std::vector<std::vector<double>> kernel_patterns(const HostHierarchy& H) {
+  const HostLevel& F = H.levels[0];
+  const int d = H.prob.dim, q1 = F.em.q1, bss = F.bss, bs = F.bs;
+  bool any_dirichlet = false;
+  for (int f = 0; f < 2 * d; ++f) any_dirichlet = any_dirichlet || H.prob.bc[f] == LDGMG_BC_DIRICHLET;
+  std::vector<int> comps;
+  if (H.prob.system == LDGMG_POISSON) {
+    if (!any_dirichlet) comps.push_back(0);
+  } else {
+    if (!any_dirichlet)
+      for (int c = 0; c < d; ++c) comps.push_back(c);
+    comps.push_back(d);
+  }
+  std::vector<std::vector<double>> out;
+  if (comps.empty()) return out;
+  std::vector<double> t, w, v(q1), dv(q1);
+  gauss_legendre(q1 + 1, t, w);
+  std::vector<double> m(static_cast<size_t>(q1) * q1, 0.0), c1(q1, 0.0);
+  for (size_t q = 0; q < t.size(); ++q) {
+    basis_eval(F.em.p, H.prob.basis, t[q], v.data(), dv.data());
+    for (int i = 0; i < q1; ++i) {
+      c1[i] += w[q] * v[i];
+      for (int j = 0; j < q1; ++j) m[static_cast<size_t>(i) * q1 + j] += w[q] * v[i] * v[j];
+    }
+  }
+  // c1 = m^-1 (int psi_i): Gaussian elimination with partial pivoting (q1 <= 6)
+  for (int k = 0; k < q1; ++k) {
+    int pv = k;
+    for (int i = k + 1; i < q1; ++i)
+      if (std::fabs(m[static_cast<size_t>(i) * q1 + k]) > std::fabs(m[static_cast<size_t>(pv) * q1 + k])) pv = i;
+    for (int j = 0; j < q1; ++j) std::swap(m[static_cast<size_t>(k) * q1 + j], m[static_cast<size_t>(pv) * q1 + j]);
+    std::swap(c1[k], c1[pv]);
+    for (int i = k + 1; i < q1; ++i) {
+      const double f = m[static_cast<size_t>(i) * q1 + k] / m[static_cast<size_t>(k) * q1 + k];
+      for (int j = k; j < q1; ++j) m[static_cast<size_t>(i) * q1 + j] -= f * m[static_cast<size_t>(k) * q1 + j];
+      c1[i] -= f * c1[k];
+    }
+  }
+  for (int k = q1 - 1; k >= 0; --k) {
+    for (int j = k + 1; j < q1; ++j) c1[k] -= m[static_cast<size_t>(k) * q1 + j] * c1[j];
+    c1[k] /= m[static_cast<size_t>(k) * q1 + k];
+  }
+  std::vector<double> cs(bss);
+  for (int a = 0; a < bss; ++a) {
+    double val = c1[a % q1] * c1[(a / q1) % q1];
+    if (d == 3) val *= c1[a / (q1 * q1)];
+    cs[a] = val;
+  }
+  const PMat& A = F.A;
+  const int np = A.pool.size();
+  for (int comp : comps) {
+    std::vector<double> k(bs, 0.0);
+    std::copy(cs.begin(), cs.end(), k.begin() + static_cast<size_t>(comp) * bss);
+    // per distinct block: B k and |B| |k|
+    std::vector<double> bk(static_cast<size_t>(np) * bs), ak(static_cast<size_t>(np) * bs);
+    for (int id = 0; id < np; ++id) {
+      const double* B = A.pool.at(id);
+      for (int r = 0; r < bs; ++r) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int c = 0; c < bs; ++c) {
+          s1 += B[static_cast<size_t>(r) * bs + c] * k[c];
+          s2 += std::fabs(B[static_cast<size_t>(r) * bs + c] * k[c]);
+        }
+        bk[static_cast<size_t>(id) * bs + r] = s1;
+        ak[static_cast<size_t>(id) * bs + r] = s2;
+      }
+    }
+    bool in_kernel = true;
+    std::vector<double> s1(bs), s2(bs);
+    for (int i = 0; i < A.nbr && in_kernel; ++i) {
+      std::fill(s1.begin(), s1.end(), 0.0);
+      std::fill(s2.begin(), s2.end(), 0.0);
+      for (int sl = A.rp[i]; sl < A.rp[i + 1]; ++sl)
+        for (int r = 0; r < bs; ++r) {
+          s1[r] += bk[static_cast<size_t>(A.id[sl]) * bs + r];
+          s2[r] += ak[static_cast<size_t>(A.id[sl]) * bs + r];
+        }
+      for (int r = 0; r < bs; ++r)
+        if (std::fabs(s1[r]) > 1e-10 * s2[r]) in_kernel = false;
+    }
+    if (in_kernel) out.push_back(k);
+  }
+  return out;
+}
+
+// the kernel vectors of the fine operator on the device: khat_i = k_i / ||k_i||
+// and the mean weights w_i = M khat_i / (khat_i^T M khat_i), so that
+// (w_i . x) khat_i is the M-orthogonal projection of x on khat_i
+void upload_kernel(DevHier& D, const HostHierarchy& H, hipStream_t st) {
+  const std::vector<std::vector<double>> pats = kernel_patterns(H);
+  D.nker = static_cast<int>(pats.size());
+  if (!D.nker) return;
+  const HostLevel& F = H.levels[0];
+  const long long N = static_cast<long long>(F.ne) * F.bs;
+  const int bs = F.bs, bss = F.bss;
+  std::vector<double> kh(static_cast<size_t>(D.nker) * N), kw(static_cast<size_t>(D.nker) * N);
+  for (int i = 0; i < D.nker; ++i) {
+    const std::vector<double>& k = pats[i];
+    std::vector<double> mk(bs, 0.0);          // element mass applied per component block
+    for (int c = 0; c < bs / bss; ++c)
+      for (int a = 0; a < bss; ++a)
+        for (int b = 0; b < bss; ++b)
+          mk[c * bss + a] += F.em.M[static_cast<size_t>(a) * bss + b] * k[c * bss + b];
+    double kk = 0.0, kmk = 0.0;
+    for (int a = 0; a < bs; ++a) {
+      kk += k[a] * k[a];
+      kmk += k[a] * mk[a];
+    }
+    const double nrm = std::sqrt(kk * F.ne);   // ||k|| over the grid
+    const double den = kmk / kk;               // khat^T M khat
+    for (long long e = 0; e < F.ne; ++e)
+      for (int a = 0; a < bs; ++a) {
+        kh[static_cast<size_t>(i) * N + e * bs + a] = k[a] / nrm;
+        kw[static_cast<size_t>(i) * N + e * bs + a] = mk[a] / nrm / den;
+      }
+  }
+  D.khat = static_cast<double*>(D.alloc(kh.size() * sizeof(double)));
+  D.kw = static_cast<double*>(D.alloc(kw.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(D.khat, kh.data(), kh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(D.kw, kw.data(), kw.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));   // the host vectors must outlive their copies
+}
+
 void upload(ldgmg_hier* h, hipStream_t st) {
   const HostHierarchy& H = *h->host;
   const size_t need = estimate_from_host(H, H.prob.precision);
@@ -448,6 +634,9 @@ void upload(ldgmg_hier* h, hipStream_t st) {
   auto D = std::make_unique<DevHier>();
   D->prec = H.prob.precision;
   D->storage = H.prob.storage;
+  D->ualloc = H.prob.dev_alloc;
+  D->ufree = H.prob.dev_free;
+  D->uctx = H.prob.alloc_ctx;
   HIPCHK(hipGetDevice(&D->device));
   const int nl = static_cast<int>(H.levels.size());
   D->L.resize(nl);
@@ -482,10 +671,8 @@ void upload(ldgmg_hier* h, hipStream_t st) {
     const std::vector<int>& ids_h = f.bidA ? order : F.A.id;
     D->val64 = static_cast<double*>(D->alloc(ids_h.size() * bb * sizeof(double)));
     D->bid64 = f.bidA;
-    double* pool = nullptr;
-    int* ids = nullptr;
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&pool), std::max<size_t>(16, F.A.pool.data.size() * sizeof(double)), st));
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&ids), std::max<size_t>(16, ids_h.size() * sizeof(int)), st));
+    double* pool = static_cast<double*>(D->stage(F.A.pool.data.size() * sizeof(double), st));
+    int* ids = static_cast<int*>(D->stage(ids_h.size() * sizeof(int), st));
     HIPCHK(hipMemcpyAsync(pool, F.A.pool.data.data(), F.A.pool.data.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ids, ids_h.data(), ids_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
     expand_blocks<double>(static_cast<long long>(ids_h.size()), F.bs, ids, pool, D->val64, false, st);
@@ -496,8 +683,8 @@ void upload(ldgmg_hier* h, hipStream_t st) {
       D->t64 = f.tA;
       D->t64.blk = tb;
     }
-    HIPCHK(hipFreeAsync(pool, st));   // stream-ordered: no device-wide synchronisation
-    HIPCHK(hipFreeAsync(ids, st));
+    D->unstage(pool, st);
+    D->unstage(ids, st);
     HIPCHK(hipStreamSynchronize(st));
     D->own64 = true;
   }
@@ -512,6 +699,7 @@ void upload(ldgmg_hier* h, hipStream_t st) {
   HIPCHK(hipMemsetAsync(D->scal, 0, 64 * sizeof(double), st));
   HIPCHK(hipHostMalloc(&D->hscal, 64 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(st));
+  upload_kernel(*D, H, st);
   for (DevLevel& L : D->L) L.p32 = h->fp32_products;
   h->dev = std::move(D);
 }
@@ -974,14 +1162,64 @@ int solve_gmres(const Ctx& c, const double* b, double* x, double rtol, int maxit
 }
 
 // ---------------------------------------------------------------------------
+// singular operators (a kernel of constants): right-hand side projection and
+// the zero-mean convention for the solution
+// ---------------------------------------------------------------------------
+// out = b - sum_i (b . khat_i) khat_i: b projected on the range of the
+// symmetric operator (the khat_i are orthonormal: one component each)
+void project_rhs(const Ctx& c, const double* b, double* out) {
+  DevHier& D = c.D;
+  const long long N = D.L[0].N;
+  if (out != b) HIPCHK(hipMemcpyAsync(out, b, N * 8, hipMemcpyDeviceToDevice, c.st));
+  for (int i = 0; i < D.nker; ++i) {
+    dot_partial(N, out, D.khat + static_cast<size_t>(i) * N, D.partial, c.st);
+    finalize(D.partial, D.scal, 3, S_K, 0, c.st);                       // -(b . khat_i)
+    axpby(N, D.khat + static_cast<size_t>(i) * N, out, D.scal, S_K, 0.0, -1, 1.0, c.st);
+  }
+}
+
+// x <- x - sum_i (w_i . x) khat_i: the kernel components of x get zero mean
+void remove_kernel(const Ctx& c, double* x) {
+  DevHier& D = c.D;
+  const long long N = D.L[0].N;
+  for (int i = 0; i < D.nker; ++i) {
+    dot_partial(N, x, D.kw + static_cast<size_t>(i) * N, D.partial, c.st);
+    finalize(D.partial, D.scal, 3, S_K, 0, c.st);
+    axpby(N, D.khat + static_cast<size_t>(i) * N, x, D.scal, S_K, 0.0, -1, 1.0, c.st);
+  }
+}
+
+// |b . khat_i| <= tol ||b|| for every kernel vector, else SingularError
+void check_rhs(const Ctx& c, const double* b, double tol) {
+  DevHier& D = c.D;
+  const long long N = D.L[0].N;
+  const double bn = std::sqrt(dot_host(c, b, b, S_TMP));
+  for (int i = 0; i < D.nker; ++i) {
+    const double v = dot_host(c, b, D.khat + static_cast<size_t>(i) * N, S_K);
+    if (!(std::fabs(v) <= tol * bn))
+      throw SingularError("inconsistent right-hand side: |b . k| / ||b|| = " + std::to_string(std::fabs(v) / bn) +
+                          " for kernel vector " + std::to_string(i) + " (tolerance " + std::to_string(tol) + ")");
+  }
+}
+
+// ---------------------------------------------------------------------------
 // batched V-cycle and CG: nk right-hand sides on one hierarchy; every level
 // vector holds nk vectors at a stride of the level size
 // ---------------------------------------------------------------------------
-void ensure_batch(DevHier& D, hipStream_t st) {
-  if (!D.BL.empty()) return;
-  D.BL.resize(D.L.size());
+// batch vectors for nk right-hand sides: sets of 8, or of kMaxRhs once more
+// than 8 are asked for (the 8-sets are then given back)
+void ensure_batch(DevHier& D, int nk, hipStream_t st) {
+  const int cap = nk <= 8 ? 8 : kMaxRhs;
+  if (D.bcap >= cap) return;
+  if (D.bcap) {
+    HIPCHK(hipStreamSynchronize(st));
+    for (auto& B : D.BL)
+      for (double* p : {B.x, B.b, B.r, B.t}) D.release(p);
+    for (double* p : {D.bx, D.br, D.bp, D.bq, D.bz}) D.release(p);
+  }
+  D.BL.assign(D.L.size(), DevHier::BatchLevel{});
   for (size_t l = 0; l < D.L.size(); ++l) {
-    const size_t vb = static_cast<size_t>(D.L[l].N) * kMaxRhs * sizeof(double);
+    const size_t vb = static_cast<size_t>(D.L[l].N) * cap * sizeof(double);
     auto& B = D.BL[l];
     B.x = static_cast<double*>(D.alloc(vb));
     B.b = static_cast<double*>(D.alloc(vb));
@@ -990,15 +1228,18 @@ void ensure_batch(DevHier& D, hipStream_t st) {
     HIPCHK(hipMemsetAsync(B.r, 0, vb, st));
     HIPCHK(hipMemsetAsync(B.t, 0, vb, st));
   }
-  const size_t vb = static_cast<size_t>(D.L[0].N) * kMaxRhs * sizeof(double);
+  const size_t vb = static_cast<size_t>(D.L[0].N) * cap * sizeof(double);
   D.bx = static_cast<double*>(D.alloc(vb));
   D.br = static_cast<double*>(D.alloc(vb));
   D.bp = static_cast<double*>(D.alloc(vb));
   D.bq = static_cast<double*>(D.alloc(vb));
   D.bz = static_cast<double*>(D.alloc(vb));
-  D.bscal = static_cast<double*>(D.alloc(kMaxRhs * 8 * sizeof(double)));
-  HIPCHK(hipMemsetAsync(D.bscal, 0, kMaxRhs * 8 * sizeof(double), st));
-  HIPCHK(hipHostMalloc(&D.hbscal, kMaxRhs * 8 * sizeof(double), hipHostMallocDefault));
+  if (!D.bscal) {
+    D.bscal = static_cast<double*>(D.alloc(kMaxRhs * 8 * sizeof(double)));
+    HIPCHK(hipMemsetAsync(D.bscal, 0, kMaxRhs * 8 * sizeof(double), st));
+    HIPCHK(hipHostMalloc(&D.hbscal, kMaxRhs * 8 * sizeof(double), hipHostMallocDefault));
+  }
+  D.bcap = cap;
 }
 
 template <typename T>
@@ -1135,7 +1376,7 @@ void apply_A64_multi(const Ctx& c, const double* x, double* y, int nk) {
 int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int nk, double rtol, int maxit,
                    ldgmg_info* infos) {
   DevHier& D = c.D;
-  ensure_batch(D, c.st);
+  ensure_batch(D, nk, c.st);
   const long long N = D.L[0].N;
   double* sc = D.bscal;
   auto slot = [](int q, int s) { return q * 8 + s; };
@@ -1158,7 +1399,9 @@ int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int n
     done[q] = bb[q] == 0.0;
   }
   vcycle64_multi(c, D.br, D.bz, nk);
-  int vcycles = 1;
+  // V-cycles spent on each right-hand side (a converged one is frozen while
+  // the batch runs on for the others)
+  std::vector<int> vcq(nk, 1);
   for (int q = 0; q < nk; ++q) {
     dot_partial(N, D.br + q * N, D.bz + q * N, D.partial, c.st);
     finalize(D.partial, sc, 0, slot(q, RZ), 0, c.st);
@@ -1194,7 +1437,7 @@ int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int n
     }
     if (!more) break;
     vcycle64_multi(c, D.br, D.bz, nk);
-    ++vcycles;
+    for (int q = 0; q < nk; ++q) vcq[q] += done[q] ? 0 : 1;
     for (int q = 0; q < nk; ++q) {
       if (done[q]) continue;
       dot_partial(N, D.br + q * N, D.bz + q * N, D.partial, c.st);
@@ -1208,7 +1451,7 @@ int solve_cg_batch(const Ctx& c, const double* const* b, double* const* x, int n
     all_conv = all_conv && done[q] == 1;
     if (infos) {
       finish_info(c, b[q], x[q], bb[q], hist[q], iters[q], done[q] == 1,
-                  bb[q] > 0 ? std::sqrt(std::fabs(rr[q]) / bb[q]) : 0.0, vcycles, &infos[q]);
+                  bb[q] > 0 ? std::sqrt(std::fabs(rr[q]) / bb[q]) : 0.0, vcq[q], &infos[q]);
     }
   }
   HIPCHK(hipStreamSynchronize(c.st));
@@ -1269,6 +1512,177 @@ void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, v
   }
 }
 
+void ensure_bproj(DevHier& D) {
+  if (!D.bproj) D.bproj = static_cast<double*>(D.alloc(static_cast<size_t>(D.L[0].N) * kMaxRhs * sizeof(double)));
+}
+
+// one solve of ldgmg_solve: on a singular operator the right-hand side is
+// checked (ldgmg_rhs_check) and projected on the range first, and the kernel
+// components of the solution are given zero mean afterwards
+int solve_one(ldgmg_hier* h, const double* b, double* x, int krylov, double rtol, int maxit, ldgmg_info* info,
+              hipStream_t st) {
+  DevHier& D = *h->dev;
+  Ctx c{*h->host, D, st, h->cg_guard};
+  const double* bb = b;
+  if (D.nker) {
+    if (h->rhs_check > 0) check_rhs(c, b, h->rhs_check);
+    ensure_bproj(D);
+    project_rhs(c, b, D.bproj);
+    bb = D.bproj;
+  }
+  const int rc = krylov == LDGMG_CG ? solve_cg(c, bb, x, rtol, maxit, info) : solve_gmres(c, bb, x, rtol, maxit, info);
+  if (D.nker) {
+    remove_kernel(c, x);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return rc;
+}
+
+// batched CG for nk <= kMaxRhs right-hand sides of one hierarchy, with the
+// same treatment of singular operators as solve_one
+int solve_cg_chunk(ldgmg_hier* h, const double* const* b, double* const* x, int nk, double rtol, int maxit,
+                   ldgmg_info* infos, hipStream_t st) {
+  DevHier& D = *h->dev;
+  Ctx c{*h->host, D, st, h->cg_guard};
+  std::vector<const double*> bb(b, b + nk);
+  if (D.nker) {
+    for (int q = 0; q < nk; ++q)
+      if (h->rhs_check > 0) check_rhs(c, b[q], h->rhs_check);
+    ensure_bproj(D);
+    for (int q = 0; q < nk; ++q) {
+      double* dst = D.bproj + static_cast<size_t>(q) * D.L[0].N;
+      project_rhs(c, b[q], dst);
+      bb[q] = dst;
+    }
+  }
+  const int rc = solve_cg_batch(c, bb.data(), x, nk, rtol, maxit, infos);
+  if (D.nker) {
+    for (int q = 0; q < nk; ++q) remove_kernel(c, x[q]);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return rc;
+}
+
+// Continuous batching on one hierarchy: up to `slots` CG recurrences in
+// flight, each exactly the recurrence of solve_cg on its own right-hand side,
+// sharing every V-cycle stage and operator apply (multi-vector kernels over
+// the slots in use).  A free slot is refilled from next() before every
+// V-cycle stage: the new right-hand side starts with its first V-cycle there
+// (r = b, z = V r, p = z) while the others take their (k+1)-th.  A slot whose
+// recurrence stops (converged, maxit, guarded breakdown) is written out,
+// reported through done() and freed at once.
+int solve_cg_stream(ldgmg_hier* h, int slots, double rtol, int maxit,
+                    int (*next)(void*, const double**, double**, long long*),
+                    void (*done)(void*, long long, int, const ldgmg_info*), void* ctx, hipStream_t st) {
+  DevHier& D = *h->dev;
+  Ctx c{*h->host, D, st, h->cg_guard};
+  ensure_batch(D, slots, st);
+  if (D.nker) ensure_bproj(D);
+  const long long N = D.L[0].N;
+  double* sc = D.bscal;
+  auto slot = [](int q, int s) { return q * 8 + s; };
+  enum { BB = 0, RZ = 1, AL = 2, RR = 3, BE = 4 };
+  struct Slot {
+    bool used = false, fresh = false;
+    const double* b = nullptr;   // the right-hand side the recurrence solves (projected when singular)
+    double* x = nullptr;         // caller's solution vector
+    long long tag = 0;
+    int iters = 0, vcycles = 0;
+    double bb = 0, rr = 0;
+    std::vector<double> hist;
+  };
+  std::vector<Slot> S(slots);
+  int worst = LDGMG_OK;
+  auto finish = [&](int q, bool conv) {
+    Slot& s = S[q];
+    HIPCHK(hipMemcpyAsync(s.x, D.bx + q * N, N * 8, hipMemcpyDeviceToDevice, st));
+    ldgmg_info info{};
+    finish_info(c, s.b, s.x, s.bb, s.hist, s.iters, conv, s.bb > 0 ? std::sqrt(std::fabs(s.rr) / s.bb) : 0.0,
+                s.vcycles, &info);
+    if (D.nker) remove_kernel(c, s.x);
+    HIPCHK(hipStreamSynchronize(st));
+    if (!conv) worst = LDGMG_ENOCONV;
+    const long long tag = s.tag;
+    s = Slot{};
+    done(ctx, tag, conv ? LDGMG_OK : LDGMG_ENOCONV, &info);
+  };
+  for (;;) {
+    // admit waiting right-hand sides into free slots
+    for (int q = 0; q < slots; ++q) {
+      if (S[q].used) continue;
+      const double* b = nullptr;
+      double* x = nullptr;
+      long long tag = 0;
+      if (!next(ctx, &b, &x, &tag)) break;     // nothing waiting now
+      if (!b || !x) throw std::invalid_argument("next() gave a null vector");
+      Slot& s = S[q];
+      s.used = s.fresh = true;
+      s.b = b;
+      s.x = x;
+      s.tag = tag;
+      if (D.nker) {
+        if (h->rhs_check > 0) check_rhs(c, b, h->rhs_check);
+        double* dst = D.bproj + static_cast<size_t>(q) * N;
+        project_rhs(c, b, dst);
+        s.b = dst;
+      }
+      HIPCHK(hipMemcpyAsync(D.br + q * N, s.b, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemsetAsync(D.bx + q * N, 0, N * 8, st));
+      s.bb = dot_host(c, s.b, s.b, S_BB);
+      if (!std::isfinite(s.bb)) throw std::invalid_argument("right-hand side contains NaN or Inf");
+      if (s.bb == 0.0) {                 // x = 0 solves it: no iteration
+        s.rr = 0.0;
+        finish(q, true);
+        --q;                             // the slot is free again
+      }
+    }
+    int nk = 0;
+    for (int q = 0; q < slots; ++q)
+      if (S[q].used) nk = q + 1;
+    if (nk == 0) break;                        // nothing in flight and nothing waiting
+    // V-cycle stage of every slot in use: z = V r; fresh slots start p = z,
+    // the others take beta = (r.z)_new / (r.z)_old and p = z + beta p
+    vcycle64_multi(c, D.br, D.bz, nk);
+    for (int q = 0; q < nk; ++q) {
+      Slot& s = S[q];
+      if (!s.used) continue;
+      ++s.vcycles;
+      dot_partial(N, D.br + q * N, D.bz + q * N, D.partial, st);
+      if (s.fresh) {
+        finalize(D.partial, sc, 0, slot(q, RZ), 0, st);
+        HIPCHK(hipMemcpyAsync(D.bp + q * N, D.bz + q * N, N * 8, hipMemcpyDeviceToDevice, st));
+        s.fresh = false;
+      } else {
+        finalize(D.partial, sc, 2, slot(q, BE), slot(q, RZ), st);
+        cg_dir(N, D.bp + q * N, D.bz + q * N, sc, slot(q, BE), st);
+      }
+    }
+    // operator stage: q = A p, alpha = (r.z) / (p.q), x += alpha p, r -= alpha q
+    apply_A64_multi(c, D.bp, D.bq, nk);
+    for (int q = 0; q < nk; ++q) {
+      if (!S[q].used) continue;
+      dot_partial(N, D.bp + q * N, D.bq + q * N, D.partial, st);
+      finalize(D.partial, sc, 1, slot(q, AL), slot(q, RZ), st);
+      cg_update(N, D.bx + q * N, D.br + q * N, D.bp + q * N, D.bq + q * N, sc, slot(q, AL), D.partial, st);
+      finalize(D.partial, sc, 0, slot(q, RR), 0, st);
+    }
+    HIPCHK(hipMemcpyAsync(D.hbscal, sc, kMaxRhs * 8 * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < nk; ++q) {
+      Slot& s = S[q];
+      if (!s.used) continue;
+      s.hist.push_back(std::sqrt(std::fabs(D.hbscal[slot(q, RZ)])));
+      ++s.iters;
+      s.rr = D.hbscal[slot(q, RR)];
+      if (!std::isfinite(s.rr)) throw std::runtime_error("CG breakdown (non-finite residual)");
+      if (s.rr <= rtol * rtol * s.bb) finish(q, true);
+      else if (c.guard && (!(D.hbscal[slot(q, RZ)] > 0.0) || !(D.hbscal[slot(q, AL)] > 0.0))) finish(q, false);
+      else if (s.iters >= maxit) finish(q, false);
+    }
+  }
+  return worst;
+}
+
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -1285,6 +1699,8 @@ int guarded(F&& fn) {
     return fail(LDGMG_EHIP, e.what());
   } catch (const StateError& e) {
     return fail(LDGMG_ESTATE, e.what());
+  } catch (const SingularError& e) {
+    return fail(LDGMG_ESINGULAR, e.what());
   } catch (const std::invalid_argument& e) {
     return fail(LDGMG_EINVAL, e.what());
   } catch (const std::bad_alloc&) {
@@ -1340,6 +1756,9 @@ int ldgmg_problem_default(ldgmg_problem* p) {
   p->nthreads = 0;
   p->hbm_budget = 0;
   p->storage = LDGMG_STORE_AUTO;
+  p->dev_alloc = nullptr;
+  p->dev_free = nullptr;
+  p->alloc_ctx = nullptr;
   return LDGMG_OK;
 }
 
@@ -1421,6 +1840,29 @@ int ldgmg_cg_guard(ldgmg_handle h, int enable) {
   return guarded([&] {
     if (!h || !h->host) throw std::invalid_argument("null handle");
     h->cg_guard = enable != 0;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_rhs_check(ldgmg_handle h, double tol) {
+  return guarded([&] {
+    if (!h || !h->host) throw std::invalid_argument("null handle");
+    if (!(tol >= 0) || !std::isfinite(tol)) throw std::invalid_argument("tolerance must be finite and >= 0");
+    h->rhs_check = tol;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_kernel(ldgmg_handle h, int* count, double* host_out) {
+  return guarded([&] {
+    need_dev(h);
+    if (!count) throw std::invalid_argument("null count");
+    const DevHier& D = *h->dev;
+    *count = D.nker;
+    if (host_out && D.nker) {
+      HIPCHK(hipMemcpy(host_out, D.khat, static_cast<size_t>(D.nker) * D.L[0].N * sizeof(double),
+                       hipMemcpyDeviceToHost));
+    }
     return LDGMG_OK;
   });
 }
@@ -1562,10 +2004,8 @@ int ldgmg_solve(ldgmg_handle h, const double* b_dev, double* x_dev, int krylov, 
     need_dev(h);
     if (!b_dev || !x_dev) throw std::invalid_argument("null vector");
     if (!(rtol > 0) || maxit < 1) throw std::invalid_argument("rtol must be > 0 and maxit >= 1");
-    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream), h->cg_guard};
-    if (krylov == LDGMG_CG) return solve_cg(c, b_dev, x_dev, rtol, maxit, info);
-    if (krylov == LDGMG_GMRES) return solve_gmres(c, b_dev, x_dev, rtol, maxit, info);
-    throw std::invalid_argument("unknown krylov method");
+    if (krylov != LDGMG_CG && krylov != LDGMG_GMRES) throw std::invalid_argument("unknown krylov method");
+    return solve_one(h, b_dev, x_dev, krylov, rtol, maxit, info, static_cast<hipStream_t>(stream));
   });
 }
 
@@ -1574,7 +2014,7 @@ int ldgmg_vcycle_batch(ldgmg_handle h, const double* const* b_dev, double* const
     need_dev(h);
     if (!b_dev || !x_dev || k < 1 || k > kMaxRhs) throw std::invalid_argument("bad batch arguments");
     Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
-    ensure_batch(*h->dev, c.st);
+    ensure_batch(*h->dev, k, c.st);
     const long long N = h->dev->L[0].N;
     for (int q = 0; q < k; ++q) {
       if (!b_dev[q] || !x_dev[q]) throw std::invalid_argument("null vector in batch");
@@ -1587,16 +2027,70 @@ int ldgmg_vcycle_batch(ldgmg_handle h, const double* const* b_dev, double* const
   });
 }
 
-int ldgmg_solve_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k, double rtol,
-                      int maxit, ldgmg_info* infos, void* stream) {
+int ldgmg_solve_batch(const ldgmg_handle* hs, const double* const* b_dev, double* const* x_dev, int k, int krylov,
+                      double rtol, int maxit, ldgmg_info* infos, void* stream) {
+  return guarded([&] {
+    if (!hs || !b_dev || !x_dev || k < 1) throw std::invalid_argument("bad batch arguments");
+    if (!(rtol > 0) || maxit < 1) throw std::invalid_argument("rtol must be > 0 and maxit >= 1");
+    if (krylov != LDGMG_CG && krylov != LDGMG_GMRES) throw std::invalid_argument("unknown krylov method");
+    for (int q = 0; q < k; ++q) {
+      need_dev(hs[q]);
+      if (!b_dev[q] || !x_dev[q]) throw std::invalid_argument("null vector in batch");
+    }
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    // group the right-hand sides by hierarchy, in order of first appearance
+    std::vector<ldgmg_hier*> order;
+    std::vector<std::vector<int>> members;
+    for (int q = 0; q < k; ++q) {
+      size_t g = 0;
+      while (g < order.size() && order[g] != hs[q]) ++g;
+      if (g == order.size()) {
+        order.push_back(hs[q]);
+        members.emplace_back();
+      }
+      members[g].push_back(q);
+    }
+    int worst = LDGMG_OK;
+    for (size_t g = 0; g < order.size(); ++g) {
+      ldgmg_hier* h = order[g];
+      const std::vector<int>& idx = members[g];
+      if (krylov == LDGMG_GMRES) {
+        for (int q : idx)
+          if (solve_one(h, b_dev[q], x_dev[q], krylov, rtol, maxit, infos ? &infos[q] : nullptr, st) != LDGMG_OK)
+            worst = LDGMG_ENOCONV;
+        continue;
+      }
+      for (size_t c0 = 0; c0 < idx.size(); c0 += kMaxRhs) {
+        const int nk = static_cast<int>(std::min<size_t>(kMaxRhs, idx.size() - c0));
+        std::vector<const double*> bq(nk);
+        std::vector<double*> xq(nk);
+        std::vector<ldgmg_info> iq(nk);
+        for (int j = 0; j < nk; ++j) {
+          const int q = idx[c0 + j];
+          bq[j] = b_dev[q];
+          xq[j] = x_dev[q];
+          iq[j] = infos ? infos[q] : ldgmg_info{};
+        }
+        if (solve_cg_chunk(h, bq.data(), xq.data(), nk, rtol, maxit, infos ? iq.data() : nullptr, st) != LDGMG_OK)
+          worst = LDGMG_ENOCONV;
+        if (infos)
+          for (int j = 0; j < nk; ++j) infos[idx[c0 + j]] = iq[j];
+      }
+    }
+    return worst;
+  });
+}
+
+int ldgmg_solve_stream(ldgmg_handle h, int slots, double rtol, int maxit,
+                       int (*next)(void* ctx, const double** b_dev, double** x_dev, long long* tag),
+                       void (*done)(void* ctx, long long tag, int status, const ldgmg_info* info), void* ctx,
+                       void* stream) {
   return guarded([&] {
     need_dev(h);
-    if (!b_dev || !x_dev || k < 1 || k > kMaxRhs) throw std::invalid_argument("bad batch arguments");
+    if (slots < 1 || slots > kMaxRhs) throw std::invalid_argument("slots must be in 1..16");
     if (!(rtol > 0) || maxit < 1) throw std::invalid_argument("rtol must be > 0 and maxit >= 1");
-    for (int q = 0; q < k; ++q)
-      if (!b_dev[q] || !x_dev[q]) throw std::invalid_argument("null vector in batch");
-    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream), h->cg_guard};
-    return solve_cg_batch(c, b_dev, x_dev, k, rtol, maxit, infos);
+    if (!next || !done) throw std::invalid_argument("null callback");
+    return solve_cg_stream(h, slots, rtol, maxit, next, done, ctx, static_cast<hipStream_t>(stream));
   });
 }
 

@@ -328,6 +328,8 @@ void validate_problem(const ldgmg_problem& p) {
   if (p.precision == LDGMG_BF16S && p.smoother != LDGMG_SMOOTH_SAI)
     throw std::invalid_argument("BF16 smoother storage is for the SAI smoothers only");
   if (!(p.tau0 > 0) || !(p.cp >= 0)) throw std::invalid_argument("penalty constants must be positive");
+  if ((p.dev_alloc == nullptr) != (p.dev_free == nullptr))
+    throw std::invalid_argument("dev_alloc and dev_free must be given together");
   for (int k = 0; k < p.dim; ++k) {
     const int a = p.bc[2 * k], b = p.bc[2 * k + 1];
     if (a < 0 || a > 2 || b < 0 || b > 2) throw std::invalid_argument("unknown bc");

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tr(int nrows, const int* __res
 
 // ---------------------------------------------------------------------------
 // tiled forward BSR kernel on the matrix cores: out = alpha M x + beta z
-// for a pooled matrix addressed by column offset, for nk <= 8 right-hand sides
+// for a pooled matrix addressed by column offset, for nk <= 16 right-hand sides
 // (vectors q at x + q stride, z + q stride, out + q stride).  tab[row * noff +
 // d] is the pool id of block (row, row + off[d]) or -1; perm lists the block
 // rows ordered by their row of tab (rows with the same blocks are adjacent).
@@ -895,6 +895,7 @@ __global__ void k_cg_dir(long long n, double* __restrict__ p, const double* __re
 //   op 0: scal[dst] = v
 //   op 1: scal[dst] = scal[a] / v
 //   op 2: scal[dst] = v / scal[a]; scal[a] = v
+//   op 3: scal[dst] = -v
 __global__ __launch_bounds__(kRedThreads) void k_finalize(int nparts, const double* __restrict__ partial,
                                                           double* __restrict__ scal, int op, int dst,
                                                           int a) {
@@ -906,6 +907,8 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(int nparts, const doub
       scal[dst] = v;
     } else if (op == 1) {
       scal[dst] = scal[a] / v;
+    } else if (op == 3) {
+      scal[dst] = -v;
     } else {
       scal[dst] = v / scal[a];
       scal[a] = v;
@@ -1070,10 +1073,10 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
                                                                  a.tblk, a.x, a.z, a.out, a.alpha, a.beta,     \
                                                                  stride, nk);                                  \
     break;
-    TILED(0) TILED(1) TILED(2) TILED(3)
+    TILED(0) TILED(1) TILED(2) TILED(3) TILED(4)
 #undef TILED
     default:
-      throw std::invalid_argument("bsr_tiled: at most 8 right-hand sides");
+      throw std::invalid_argument("bsr_tiled: at most 16 right-hand sides");
   }
   check_launch("bsr_tiled");
 }

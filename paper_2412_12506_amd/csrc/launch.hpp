@@ -13,7 +13,7 @@ namespace ldgmg {
 constexpr int kRedBlocks = 1024;   // partial sums per dot product
 constexpr int kRedThreads = 256;
 constexpr int kMdotBlocks = 256;   // partial sums per vector of a multi-dot
-constexpr int kMaxRhs = 8;         // right-hand sides per multi-vector BSR launch
+constexpr int kMaxRhs = 16;        // right-hand sides per multi-vector BSR launch
 
 // block sizes with a specialised (wave-mapped) kernel; others use the generic one
 bool fast_bs(int bs);
@@ -87,7 +87,8 @@ void prolong_add(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const
 template <typename T> void dense_gemv(int N, const double* P, const T* in, T* out, hipStream_t st);
 
 void dot_partial(long long n, const double* a, const double* b, double* partial, hipStream_t st);
-// op 0: scal[dst] = v;  op 1: scal[dst] = scal[a] / v;  op 2: scal[dst] = v / scal[a], scal[a] = v
+// op 0: scal[dst] = v;  op 1: scal[dst] = scal[a] / v;  op 2: scal[dst] = v / scal[a], scal[a] = v;
+// op 3: scal[dst] = -v
 void finalize(const double* partial, double* scal, int op, int dst, int a, hipStream_t st);
 void cg_update(long long n, double* x, double* r, const double* p, const double* q, const double* scal,
                int ia, double* partial, hipStream_t st);

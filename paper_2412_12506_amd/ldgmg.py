@@ -39,7 +39,46 @@ class Problem(C.Structure):
                 ("smoother", C.c_int), ("sai_level", C.c_int), ("order", C.c_int),
                 ("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("zeta", C.c_double),
                 ("precision", C.c_int), ("nthreads", C.c_int), ("hbm_budget", C.c_size_t),
-                ("storage", C.c_int)]
+                ("storage", C.c_int), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
+                ("alloc_ctx", C.c_void_p)]
+
+
+# dev_alloc / dev_free callback types of ldgmg_problem
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchAllocator:
+    """dev_alloc / dev_free backed by torch's caching allocator, so that a
+    hierarchy's device memory is counted by torch (memory_allocated) and
+    returned to its cache on unload.  Allocations are associated with
+    `stream` (torch's current stream when None) on `device`."""
+
+    def __init__(self, device=None, stream=None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = stream
+        self.live = 0
+
+        def _alloc(nbytes, ctx):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:
+                return None
+            self.live += 1
+            return ptr
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+            self.live -= 1
+
+        self._alloc = ALLOC_FN(_alloc)      # kept alive as long as this object
+        self._free = FREE_FN(_free)
+
+    def install(self, problem: "Problem"):
+        problem.dev_alloc = C.cast(self._alloc, C.c_void_p)
+        problem.dev_free = C.cast(self._free, C.c_void_p)
+        problem.alloc_ctx = None
 
 
 class Info(C.Structure):
@@ -47,6 +86,12 @@ class Info(C.Structure):
                 ("rel_res_krylov", C.c_double), ("eta", C.c_double),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int),
                 ("history_len", C.c_int), ("vcycles", C.c_int)]
+
+
+# callbacks of ldgmg_solve_stream
+NEXT_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                      C.POINTER(C.c_longlong))
+DONE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_longlong, C.c_int, C.POINTER(Info))
 
 
 class LdgmgError(RuntimeError):
@@ -61,7 +106,8 @@ SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", 
            "ldgmg_upload",
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
-           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_fp32_products", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage", "ldgmg_destroy",
+           "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_fp32_products", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage",
+           "ldgmg_rhs_check", "ldgmg_kernel", "ldgmg_solve_stream", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -88,8 +134,11 @@ def lib():
     L.ldgmg_vcycle.argtypes = [H, vp, vp, vp]
     L.ldgmg_solve.argtypes = [H, vp, vp, C.c_int, C.c_double, C.c_int, C.POINTER(Info), vp]
     L.ldgmg_level_op.argtypes = [H, C.c_int, C.c_int, vp, vp, vp, vp]
-    L.ldgmg_solve_batch.argtypes = [H, C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_double, C.c_int,
-                                    C.POINTER(Info), vp]
+    L.ldgmg_solve_batch.argtypes = [C.POINTER(H), C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_int, C.c_double,
+                                    C.c_int, C.POINTER(Info), vp]
+    L.ldgmg_rhs_check.argtypes = [H, C.c_double]
+    L.ldgmg_solve_stream.argtypes = [H, C.c_int, C.c_double, C.c_int, NEXT_FN, DONE_FN, vp, vp]
+    L.ldgmg_kernel.argtypes = [H, ip, dp]
     L.ldgmg_vcycle_batch.argtypes = [H, C.POINTER(vp), C.POINTER(vp), C.c_int, vp]
     L.ldgmg_export.argtypes = [H, C.c_int, C.c_int, ip, ip, dp, ip, ip]
     L.ldgmg_export_colours.argtypes = [H, C.c_int, ip]
@@ -125,8 +174,16 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
-def _stream(s) -> Optional[int]:
+def _stream(s, *tensors) -> Optional[int]:
+    """hipStream_t of `s`; with s None, torch's current stream on the device
+    of the first torch tensor among `tensors` (so that the library's work is
+    ordered after torch's producers of b and before its consumers of x), else
+    the null stream."""
     if s is None:
+        for t in tensors:
+            if getattr(t, "is_cuda", False):
+                import torch
+                return torch.cuda.current_stream(t.device).cuda_stream
         return None
     if isinstance(s, int):
         return s
@@ -143,8 +200,10 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
                  gamma: int = 1, bc=None, mu=None, tau0: float = 1.0, cp: float = 0.1,
                  smoother: str = "sai", sai_level: int = 1, order: str = "OI", nu1: int = 3,
                  nu2: int = 3, omega: float = 0.0, zeta: float = 0.0, precision: str = "fp32",
-                 nthreads: int = 0, hbm_budget: int = 0, storage: str = "auto"):
-    """Problem struct plus the numpy array that backs `mu` (keep both alive)."""
+                 nthreads: int = 0, hbm_budget: int = 0, storage: str = "auto", allocator=None):
+    """Problem struct plus the numpy array that backs `mu` (keep both alive).
+    allocator: None (hipMalloc) or an object with install(problem), such as
+    TorchAllocator (keep it alive as long as the handle)."""
     pr = ldgmg_problem_default()
     pr.dim, pr.n, pr.p = dim, n, p
     pr.system = POISSON if system == "poisson" else STOKES
@@ -169,6 +228,8 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
     pr.nthreads = nthreads
     pr.hbm_budget = hbm_budget
     pr.storage = STORAGE[storage]
+    if allocator is not None:
+        allocator.install(pr)
     return pr, mu_arr
 
 
@@ -215,11 +276,11 @@ def ldgmg_level_info(h: int, level: int):
 def ldgmg_rhs_volume(h: int, f_qp: np.ndarray, nq: int, b, stream=None):
     f = np.ascontiguousarray(f_qp, dtype=np.float64)
     _check(lib().ldgmg_rhs_volume(h, f.ctypes.data_as(C.POINTER(C.c_double)), nq, _ptr(b),
-                                  _stream(stream)))
+                                  _stream(stream, b)))
 
 
 def ldgmg_vcycle(h: int, b, x, stream=None):
-    _check(lib().ldgmg_vcycle(h, _ptr(b), _ptr(x), _stream(stream)))
+    _check(lib().ldgmg_vcycle(h, _ptr(b), _ptr(x), _stream(stream, b, x)))
 
 
 def ldgmg_solve(h: int, b, x, krylov: str = "cg", rtol: float = 1e-10, maxit: int = 200,
@@ -229,14 +290,14 @@ def ldgmg_solve(h: int, b, x, krylov: str = "cg", rtol: float = 1e-10, maxit: in
     info.history = hist.ctypes.data_as(C.POINTER(C.c_double))
     info.history_cap = history_cap
     rc = _check(lib().ldgmg_solve(h, _ptr(b), _ptr(x), KRYLOV[krylov], rtol, maxit,
-                                  C.byref(info), _stream(stream)), allow=(ENOCONV,))
+                                  C.byref(info), _stream(stream, b, x)), allow=(ENOCONV,))
     return {"iters": info.iters, "converged": bool(info.converged),
             "rel_res_true": info.rel_res_true, "rel_res_krylov": info.rel_res_krylov,
             "eta": info.eta, "history": hist[: info.history_len].copy(),
             "vcycles": info.vcycles, "status": rc}
 
 
-MAX_BATCH = 8
+MAX_BATCH = 16
 
 
 def _ptr_array(ts):
@@ -246,30 +307,98 @@ def _ptr_array(ts):
     return arr
 
 
-def ldgmg_solve_batch(h: int, bs, xs, rtol: float = 1e-10, maxit: int = 200, stream=None,
-                      history_cap: int = 256) -> list:
-    """Batched CG for k = len(bs) <= 8 right-hand sides of one hierarchy."""
+def ldgmg_solve_batch(hs, bs, xs, rtol: float = 1e-10, maxit: int = 200, stream=None,
+                      history_cap: int = 256, krylov: str = "cg") -> list:
+    """Batched solve of k = len(bs) right-hand sides; hs is one handle (for
+    all of them) or a list of k handles (right-hand side q on hs[q])."""
     k = len(bs)
+    hl = [hs] * k if isinstance(hs, int) else list(hs)
+    if len(hl) != k:
+        raise ValueError("one handle per right-hand side")
+    harr = (C.c_void_p * k)(*hl)
     hists = [np.zeros(history_cap) for _ in range(k)]
     infos = (Info * k)()
     for i in range(k):
         infos[i].history = hists[i].ctypes.data_as(C.POINTER(C.c_double))
         infos[i].history_cap = history_cap
-    rc = _check(lib().ldgmg_solve_batch(h, _ptr_array(bs), _ptr_array(xs), k, rtol, maxit, infos,
-                                        _stream(stream)), allow=(ENOCONV,))
+    rc = _check(lib().ldgmg_solve_batch(harr, _ptr_array(bs), _ptr_array(xs), k, KRYLOV[krylov], rtol, maxit,
+                                        infos, _stream(stream, *bs)), allow=(ENOCONV,))
     return [{"iters": infos[i].iters, "converged": bool(infos[i].converged),
              "rel_res_true": infos[i].rel_res_true, "rel_res_krylov": infos[i].rel_res_krylov,
              "eta": infos[i].eta, "history": hists[i][: infos[i].history_len].copy(),
              "vcycles": infos[i].vcycles, "status": rc} for i in range(k)]
 
 
+def _info_dict(info, hist, rc):
+    return {"iters": info.iters, "converged": bool(info.converged), "rel_res_true": info.rel_res_true,
+            "rel_res_krylov": info.rel_res_krylov, "eta": info.eta,
+            "history": hist[: info.history_len].copy() if hist is not None else None,
+            "vcycles": info.vcycles, "status": rc}
+
+
+def ldgmg_solve_stream(h: int, slots: int, next_rhs, on_done, rtol: float = 1e-10, maxit: int = 200,
+                       stream=None) -> int:
+    """Continuous batching (ldgmg_solve_stream).  next_rhs() returns None or
+    (b, x, tag) with b, x device tensors (kept alive by the caller until
+    on_done(tag, info) has been called for that tag).  Returns the status."""
+    held = {}
+    err = []
+
+    def _next(ctx, pb, px, ptag):
+        try:
+            item = next_rhs()
+        except Exception as ex:          # stop feeding; reported after the call
+            err.append(ex)
+            return 0
+        if item is None:
+            return 0
+        b, x, tag = item
+        held[int(tag)] = (b, x)
+        pb[0] = _ptr(b)
+        px[0] = _ptr(x)
+        ptag[0] = int(tag)
+        return 1
+
+    def _done(ctx, tag, status, pinfo):
+        try:
+            on_done(int(tag), _info_dict(pinfo.contents, None, status))
+        except Exception as ex:
+            err.append(ex)
+        held.pop(int(tag), None)
+
+    nf, df = NEXT_FN(_next), DONE_FN(_done)
+    rc = _check(lib().ldgmg_solve_stream(h, slots, rtol, maxit, nf, df, None, _stream(stream)),
+                allow=(ENOCONV,))
+    if err:
+        raise err[0]
+    return rc
+
+
+def ldgmg_rhs_check(h: int, tol: float):
+    _check(lib().ldgmg_rhs_check(h, tol))
+
+
+def ldgmg_kernel(h: int, with_vectors: bool = False):
+    """Number of kernel vectors of the fine operator (and the vectors,
+    [count, ndofs], if asked)."""
+    cnt = C.c_int(0)
+    _check(lib().ldgmg_kernel(h, C.byref(cnt), None))
+    if not with_vectors:
+        return cnt.value
+    nd, _, _ = ldgmg_sizes(h)
+    out = np.zeros((cnt.value, nd))
+    if cnt.value:
+        _check(lib().ldgmg_kernel(h, C.byref(cnt), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return cnt.value, out
+
+
 def ldgmg_vcycle_batch(h: int, bs, xs, stream=None):
-    _check(lib().ldgmg_vcycle_batch(h, _ptr_array(bs), _ptr_array(xs), len(bs), _stream(stream)))
+    _check(lib().ldgmg_vcycle_batch(h, _ptr_array(bs), _ptr_array(xs), len(bs), _stream(stream, *bs)))
 
 
 def ldgmg_level_op(h: int, level: int, op: str, in1, in2, out, stream=None):
     _check(lib().ldgmg_level_op(h, level, OP[op], _ptr(in1), _ptr(in2), _ptr(out),
-                                _stream(stream)))
+                                _stream(stream, in1, in2, out)))
 
 
 def ldgmg_export(h: int, level: int, what: str):
@@ -373,6 +502,7 @@ class Solver:
     """
 
     def __init__(self, host_only: bool = False, stream=None, fp32_products: bool = False, **kw):
+        self._allocator = kw.get("allocator")
         self.problem, self._mu = make_problem(**kw)
         self.handle = ldgmg_setup_host(self.problem)
         self.ndofs, self.bs, self.nlevels = ldgmg_sizes(self.handle)
@@ -388,6 +518,7 @@ class Solver:
         """A host-only Solver for the same problem with another smoother (kw as
         for the constructor), reusing this hierarchy's operators and bottom."""
         new = Solver.__new__(Solver)
+        new._allocator = kw.get("allocator")
         new.problem, new._mu = make_problem(**kw)
         new.handle = ldgmg_rebuild_smoother(self.handle, new.problem)
         new.ndofs, new.bs, new.nlevels = ldgmg_sizes(new.handle)

@@ -28,11 +28,13 @@ requests of the key use it.
 
 Scheduling: several workers, each with its own HIP stream, take the key whose
 oldest waiting request is oldest among the keys not in use (ties: the most
-work first), and solve up to 8
-of its waiting requests together with ldgmg_solve_batch (each matrix block
-streamed once per V-cycle for the whole batch).  Requests that arrive while a
-batch runs join a later one, and batches of different hierarchies run on the
-device at the same time.  A request's latency is completion minus arrival.
+work first) and serve it with continuous batching (ldgmg_solve_stream): up to
+max_batch CG recurrences of that key run together, every matrix block streamed
+once per V-cycle stage for all of them, and a slot freed by a converged
+request is refilled at the next stage with a request of the same key that is
+waiting by then, including requests that arrived while the batch ran.  Batches
+of different hierarchies run on the device at the same time.  A request's
+latency is completion minus arrival.
 
 Interface requests put the request's viscosity contrast inside the box
 (1/4, 3/4)^d (the multiphase geometry of Section 2.4.3).
@@ -66,11 +68,11 @@ def problem_kwargs(key, precision="fp32", smoother="sai"):
                 precision=precision)
 
 
-def batch_workspace_bytes(ndofs_fine: int, dim: int) -> int:
+def batch_workspace_bytes(ndofs_fine: int, dim: int, max_batch: int = 8) -> int:
     """Device bytes of the batched-solve workspace: 4 level vectors on every
     level (geometric sum over the hierarchy) and 5 fine Krylov vectors, each
-    holding 8 right-hand sides in FP64."""
-    nrhs = L.MAX_BATCH
+    holding 8 right-hand sides in FP64 (16 when more than 8 share a batch)."""
+    nrhs = 8 if max_batch <= 8 else 16
     levels = ndofs_fine * nrhs * 8 * 4 / (1.0 - 0.5 ** dim)
     return int(levels + ndofs_fine * nrhs * 8 * 5) + 4096
 
@@ -120,7 +122,7 @@ class Result:
 class ServingEngine:
     def __init__(self, hbm_budget: int, workers: int = 4, max_batch: int = 8, precision: str = "bf16s",
                  smoother: str = "sai", rtol: float = 1e-10, maxit: int = 200, keep_solutions: bool = False,
-                 setup_threads: int = 0):
+                 setup_threads: int = 0, allocator: str = "torch"):
         import torch
         self.torch = torch
         self.budget = int(hbm_budget)
@@ -129,6 +131,10 @@ class ServingEngine:
         self.precision, self.smoother = precision, smoother
         self.rtol, self.maxit = rtol, maxit
         self.keep = keep_solutions
+        # "torch": hierarchies live in torch's caching allocator (counted by it;
+        # eviction hands memory back without a device-wide synchronisation);
+        # "hip": the library's own hipMalloc / hipFree
+        self.allocator = allocator
         # host setup threads per worker: the host's share of cores split over the workers
         self.setup_threads = setup_threads or max(1, min(16, os.cpu_count() or 1) // workers)
         self.entries: "OrderedDict[tuple, Entry]" = OrderedDict()   # LRU order of use
@@ -159,7 +165,7 @@ class ServingEngine:
         with self.cv:
             smoother = self._entry(key).smoother
         kw = problem_kwargs(key, self.precision, smoother)
-        solver = L.Solver(host_only=True, nthreads=self.setup_threads, **kw)
+        solver = L.Solver(host_only=True, nthreads=self.setup_threads, allocator=self._new_allocator(), **kw)
         L.ldgmg_cg_guard(solver.handle, True)     # fail fast when the V-cycle is not SPD
         with self.cv:
             e = self._entry(key)
@@ -188,9 +194,9 @@ class ServingEngine:
         ndofs = n ** dim * (p + 1) ** dim
         e = self.entries.get(key)
         if e is not None and e.solver is not None:
-            return e.solver.upload_bytes + batch_workspace_bytes(ndofs, dim)
+            return e.solver.upload_bytes + batch_workspace_bytes(ndofs, dim, self.max_batch)
         pr, _ = L.make_problem(**problem_kwargs(key, self.precision, self.smoother))
-        return L.ldgmg_estimate_bytes(pr) + batch_workspace_bytes(ndofs, dim)
+        return L.ldgmg_estimate_bytes(pr) + batch_workspace_bytes(ndofs, dim, self.max_batch)
 
     def _reserve(self, e: Entry, need: int) -> bool:
         """Under the lock: make room for `need` bytes (need <= budget) by
@@ -241,9 +247,16 @@ class ServingEngine:
         q = self.waiting[best]
         return best, [q.popleft() for _ in range(min(self.max_batch, len(q)))]
 
+    def _new_allocator(self):
+        # allocations follow the calling thread's current stream: uploads run
+        # under the worker's stream, which the hierarchy's kernels then use
+        return L.TorchAllocator() if self.allocator == "torch" else None
+
+    def _new_stream(self):
+        return self.torch.cuda.Stream()
+
     def _worker(self, stop):
-        torch = self.torch
-        stream = torch.cuda.Stream()
+        stream = self._new_stream()
         while True:
             with self.cv:
                 key, batch = self._pick()
@@ -255,6 +268,7 @@ class ServingEngine:
                 e = self._entry(key)
                 self.entries.move_to_end(key)
                 e.busy = True
+                owned = True                 # this worker holds the key until it clears `owned`
                 if e.solver is None:
                     e.building = True
             setup_s = upload_s = 0.0
@@ -267,15 +281,21 @@ class ServingEngine:
                         if need > self.budget:
                             self._reject(key, batch, f"needs {need} bytes, budget {self.budget}")
                             continue
-                        if not self._reserve(e, need):        # wait for memory: put the batch back
+                        if not self._reserve(e, need):        # wait for memory: hand the key back
                             self.waiting[key].extendleft(reversed(batch))
                             e.busy = False
+                            owned = False                     # another worker may take it meanwhile
+                            self.cv.notify_all()
                             self.cv.wait(timeout=0.005)
                             continue
                         self.admissions.append((key, self._now()))
                     tu = time.perf_counter()
                     try:
-                        e.solver.upload(stream)
+                        if stream is not None:
+                            with self.torch.cuda.stream(stream):
+                                e.solver.upload(stream)
+                        else:
+                            e.solver.upload(stream)
                     except Exception:
                         with self.cv:
                             self.used -= e.bytes
@@ -286,61 +306,115 @@ class ServingEngine:
                     e.uploads += 1
                 failed = self._solve_batch(e, batch, stream, setup_s, upload_s)
                 if failed:                         # SAI did not converge: switch the key to GS
-                    with self.cv:
-                        old = e.solver
-                        old.unload()
-                        e.resident = False
-                        self.used -= e.bytes
-                        e.bytes = 0
-                        e.smoother = "gs"
-                        e.fallbacks += 1
-                        self.fallback_keys.append(key)
-                    # same operators and bottom, new smoother (the key stays busy meanwhile)
-                    new = old.resmoothed(nthreads=self.setup_threads,
-                                         **problem_kwargs(key, self.precision, "gs"))
-                    L.ldgmg_cg_guard(new.handle, True)
-                    old.close()
-                    with self.cv:
-                        e.solver = new
-                        self.waiting[key].extendleft(reversed(failed))
+                    self._fallback(e, key, failed)
             except Exception as ex:  # keep serving; report the failure
                 with self.cv:
-                    self._reject(key, batch, str(ex))
+                    # requests already recorded by _solve_batch are not reported twice
+                    done_ids = {r.rid for r in self.results}
+                    self._reject(key, [r for r in batch if r.rid not in done_ids], str(ex))
             finally:
                 with self.cv:
-                    e.busy = False
-                    e.building = False
+                    if owned:
+                        e.busy = False
+                        e.building = False
                     self.cv.notify_all()
 
+    def _fallback(self, e: Entry, key, failed):
+        """Rebuild e's hierarchy with the coloured Gauss-Seidel smoother (same
+        operators and bottom) and queue `failed` again at the front.  The key
+        stays busy meanwhile.  If the rebuild fails, the entry is reset to no
+        host tier with the GS label, so that its next batch builds the GS
+        hierarchy from scratch; `failed` is queued again either way."""
+        with self.cv:
+            old = e.solver
+            old.unload()
+            e.resident = False
+            self.used -= e.bytes
+            e.bytes = 0
+            e.smoother = "gs"
+            e.fallbacks += 1
+            self.fallback_keys.append(key)
+        try:
+            new = old.resmoothed(nthreads=self.setup_threads, allocator=self._new_allocator(),
+                                 **problem_kwargs(key, self.precision, "gs"))
+            L.ldgmg_cg_guard(new.handle, True)
+        except Exception as ex:
+            with self.cv:
+                e.solver = None
+                self.errors.append(f"{key}: GS rebuild failed ({ex}); rebuilding from scratch")
+                self.waiting[key].extendleft(reversed(failed))
+            old.close()
+            return
+        old.close()
+        with self.cv:
+            e.solver = new
+            self.waiting[key].extendleft(reversed(failed))
+
+    def _other_key_waiting(self, key) -> bool:
+        """Under the lock: another idle key has waiting requests."""
+        for k, q in self.waiting.items():
+            if k != key and q:
+                o = self.entries.get(k)
+                if o is None or not (o.busy or o.building):
+                    return True
+        return False
+
     def _solve_batch(self, e: Entry, batch, stream, setup_s, upload_s):
-        """Solve `batch` on e's hierarchy and record the results; returns the
-        requests to retry (not converged with the SAI smoother)."""
+        """Solve `batch`, and the requests of the same key that arrive while it
+        runs, with continuous batching (ldgmg_solve_stream: up to max_batch CG
+        recurrences in flight; a slot freed by a converged request is refilled
+        at the next V-cycle stage).  Records the results; returns the requests
+        to retry (not converged with the SAI smoother).  Admission stops after
+        4 x max_batch requests when another key is waiting, so that a busy key
+        does not hold a worker forever."""
         from ldg_inputs import rhs_normal
         torch = self.torch
         n = e.solver.ndofs
-        with torch.cuda.stream(stream):
-            bs = [torch.from_numpy(rhs_normal(n, r.seed)).to("cuda") for r in batch]
-            xs = [torch.empty_like(b) for b in bs]
-        stream.synchronize()
-        start = self._now()
-        infos = L.ldgmg_solve_batch(e.solver.handle, bs, xs, self.rtol, self.maxit, stream=stream)
-        stream.synchronize()
-        end = self._now()
-        actual = e.solver.device_bytes
+        first = deque(batch)
+        inflight = {}
         failed = []
+        admitted = [0]
+
+        def next_rhs():
+            with self.cv:
+                if failed:                    # the SAI V-cycle fails on this key: stop feeding it
+                    return None
+                if first:
+                    r = first.popleft()
+                else:
+                    q = self.waiting.get(e.key)
+                    if not q or (admitted[0] >= 4 * self.max_batch and self._other_key_waiting(e.key)):
+                        return None
+                    r = q.popleft()
+                admitted[0] += 1
+            with torch.cuda.stream(stream):
+                b = torch.from_numpy(rhs_normal(n, r.seed)).to("cuda")
+                x = torch.empty_like(b)
+            inflight[r.rid] = (r, self._now(), len(inflight) + 1, x)
+            return b, x, r.rid
+
+        def on_done(tag, info):
+            r, start, width, x = inflight.pop(tag)
+            if not info["converged"] and e.smoother == "sai":
+                failed.append(r)
+                return
+            xs = x.cpu().numpy() if self.keep else None
+            with self.cv:
+                self.results.append(Result(r.rid, e.key, r.arrival, start, self._now(), info["iters"],
+                                           info["converged"], info["rel_res_true"], width, setup_s, upload_s,
+                                           xs, smoother=e.smoother))
+
+        L.ldgmg_solve_stream(e.solver.handle, self.max_batch, next_rhs, on_done, self.rtol, self.maxit,
+                             stream=stream)
         with self.cv:
+            first_left = list(first)
+            if first_left:                    # not admitted (the key failed first): back to the queue
+                self.waiting[e.key].extendleft(reversed(first_left))
+            actual = e.solver.device_bytes
             if actual > e.bytes:           # measured bytes replace the estimate
                 self.used += actual - e.bytes
                 e.bytes = actual
                 self.peak_used = max(self.peak_used, self.used)
-            for r, info, x in zip(batch, infos, xs):
-                if not info["converged"] and e.smoother == "sai":
-                    failed.append(r)
-                    continue
-                self.results.append(Result(r.rid, e.key, r.arrival, start, end, info["iters"],
-                                           info["converged"], info["rel_res_true"], len(batch), setup_s,
-                                           upload_s, x.cpu().numpy() if self.keep else None,
-                                           smoother=e.smoother))
         return failed
 
     def run(self, requests, time_scale: float = 1.0) -> List[Result]:

@@ -228,3 +228,51 @@ def test_batch_matches_single():
             assert rel <= 1e-8, (q, rel)
     finally:
         s.close()
+
+
+def test_headline_path_fine_level_n12():
+    """The benchmark's path on a grid whose fine-level launches span 27
+    workgroups (3D Q_3, 12^3 = 1,728 block rows, 64 rows per workgroup): BF16
+    SAI storage, tiled storage, FP32 products, the FP32 smoothing residual
+    (16 | bs, A and B tiled), the 4-step k layout of B and B^T and the XCD
+    tile order (24 workgroups remapped, a tail of 3).  Every fine-level apply
+    and both smoothing steps against the oracle's fine operator and balanced
+    SAI_1 matrix (rounded as stored), entry by entry within the bounds of
+    test_level_operations."""
+    from paper_2412_12506_amd import ldgmg as L
+    from oracle import ldg, smoothers as sm
+    dim, n, p = 3, 12, 3
+    A64 = ldg.assemble_scalar(dim, n, p).A
+    bs = (p + 1) ** dim
+    B64, _ = sm.sai(A64, bs, 1, sm.balance_scalar(A64, bs))
+    A, S = round_fp32(A64), round_bf16(B64)
+    s = L.Solver(dim=dim, n=n, p=p, smoother="sai", precision="bf16s", storage="tiled", fp32_products=True)
+    try:
+        st = L.ldgmg_level_storage(s.handle, 0)
+        assert st["tiled_A"] and st["tiled_S"], st
+        rng = np.random.default_rng(2024)
+        N = A.shape[0]
+        x, b = rng.standard_normal(N), rng.standard_normal(N)
+        xt, bt = torch.from_numpy(x).cuda(), torch.from_numpy(b).cuda()
+        out = torch.empty_like(xt)
+        L.ldgmg_level_op(s.handle, 0, "residual", xt, bt, out)
+        torch.cuda.synchronize()
+        _check_rows(b - out.cpu().numpy(), A @ x, A, x, "residual n12")
+        for op, M in (("apply_a", A), ("apply_s", S), ("apply_st", S.T)):
+            L.ldgmg_level_op(s.handle, 0, op, xt, None, out)
+            torch.cuda.synchronize()
+            w = _check_rows(out.cpu().numpy(), M @ x, M, x, (op, "n12"))
+            print(f"  12^3 {op}: worst error / bound {w:.3f}", flush=True)
+        nA = np.diff(A.tocsr().indptr)
+        absAx = abs(A) @ np.abs(x)
+        for op, M in (("smooth_fwd", S.tocsr()), ("smooth_rev", S.T.tocsr())):
+            L.ldgmg_level_op(s.handle, 0, op, xt, bt, out)
+            torch.cuda.synchronize()
+            nM = np.diff(M.indptr)
+            ref = x + M @ (b - A @ x)
+            bound = (nM + 3) * U32 * (abs(M) @ (np.abs(b) + absAx)) + abs(M) @ ((nA + 3) * U32 * absAx)
+            worst = float(np.max(np.abs(out.cpu().numpy() - ref) / np.maximum(bound, 1e-300)))
+            print(f"  12^3 {op}: worst error / bound {worst:.3f}", flush=True)
+            assert worst <= 1.0, (op, worst)
+    finally:
+        s.close()

@@ -21,8 +21,10 @@ Tolerances (derived from the arithmetic, not tuned):
     of the bottom operator on its range, computed from the oracle's matrix;
     ~2e9 for the multiphase Stokes case).  Bottom within 20 kappa eps64; V-cycle
     within 1e-10 (FP64) or 1e-5 (FP32 storage) plus 100 kappa eps64.
-  * Solves: iteration count within +-1 of the oracle; solution within 1e-8
-    relative of the oracle's (Stokes: modulo the constant pressure); CG true
+  * Solves: iteration count within +-1 of the oracle; solution within 1e-9
+    relative of the oracle's in FP64 mode and 1e-8 with FP32 / BF16 storage
+    (Stokes: modulo the constant pressure); the difference of the two
+    solutions has an A-image within the sum of their true residuals; CG true
     FP64 residual <= 2e-10; GMRES (stops on ||V r||) true residual within 10x
     of the oracle's.
 Sizes span several workgroups and ragged tails on every level.
@@ -238,7 +240,18 @@ def test_solve(built):
         x, xr = proj(x), proj(ref.x)
     else:
         xr = ref.x
-    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-8
+    # x - x_ref = A^-1 (r_ref - r): its A-image is bounded by the two true
+    # residuals, whatever the conditioning
+    d = xt.cpu().numpy() - ref.x
+    ares = np.linalg.norm(lv[0].A @ d) / np.linalg.norm(b)
+    rel = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+    print(f"\n[solve {case['id']} {prec}] iters gpu {info['iters']} oracle {ref.iters}; solution rel diff "
+          f"{rel:.2e}; A-residual of the difference {ares:.2e}", flush=True)
+    assert ares <= 1.01 * (info["rel_res_true"] + ref.rel_res_true) + 1e-12
+    # the stated solution tolerance: 1e-9 relative in FP64 mode; with FP32 / BF16
+    # storage the V-cycle is another (fixed) preconditioner, so the two Krylov
+    # iterates reach the 1e-10 residual along different paths: 1e-8
+    assert rel <= (1e-9 if prec == "fp64" else 1e-8), rel
     if krylov == "cg":     # CG stops on the FP64 residual itself
         assert info["rel_res_true"] <= 2e-10
     else:                  # left-preconditioned GMRES stops on ||V r||: compare with the oracle
@@ -246,3 +259,31 @@ def test_solve(built):
         assert info["rel_res_true"] <= 10 * ref.rel_res_true + 1e-12
     if prec == "fp64":
         assert abs(info["eta"] - ref.eta) <= 0.05 * ref.eta
+
+
+@pytest.mark.parametrize("dim,n,p,basis,nq", [(2, 16, 2, "gl_nodal", 6), (3, 6, 3, "legendre", 5),
+                                              (2, 9, 1, "legendre", 4)])
+def test_rhs_volume(dim, n, p, basis, nq):
+    """ldgmg_rhs_volume (the int f v part of b_h, Section 2.1) against the
+    oracle's volume_load on the same sampled source: the manufactured source
+    of the 2D workload, or seeded N(0,1) point values.  Both sides sum nq^d
+    weighted products per entry in FP64: |b - b_ref| <= 1e-13 max |b_ref|."""
+    from paper_2412_12506_amd import ldgmg as L
+    from ldg_inputs import sample_on_elements, mms_source_2d
+    from oracle import ldg
+    if dim == 2 and basis == "gl_nodal":
+        fq = sample_on_elements(dim, n, nq, mms_source_2d)
+    else:
+        fq = np.random.default_rng(5).standard_normal((n ** dim, nq ** dim))
+    s = L.Solver(dim=dim, n=n, p=p, basis=basis, smoother="jacobi", precision="fp64")
+    try:
+        bt = torch.zeros(s.ndofs, dtype=torch.float64, device=_dev())
+        L.ldgmg_rhs_volume(s.handle, fq, nq, bt)
+        torch.cuda.synchronize()
+        em = ldg.ElementMatrices(dim, p, 1.0 / n, basis)
+        ref = ldg.volume_load(em, fq, nq)
+        err = np.max(np.abs(bt.cpu().numpy() - ref)) / np.max(np.abs(ref))
+        print(f"\n[rhs_volume {dim}D n={n} p={p} {basis}] max error / max |b| {err:.2e}", flush=True)
+        assert err <= 1e-13
+    finally:
+        s.close()

@@ -116,3 +116,42 @@ def test_refuses_problem_over_budget():
         assert eng.used == 0
     finally:
         eng.close()
+
+
+def test_continuous_batching_tiled_mix_equals_alone():
+    """Hierarchies that the AUTO storage tiles (3D Q_2 on 32^3, 2D Q_3 on
+    128^2: at least 16,384 block rows), requests arriving while batches run:
+    each result equals the same request solved alone (same iterations,
+    1e-10), and requests joined batches already in flight (a request started
+    while another of its key was in flight, after a third had completed)."""
+    from paper_2412_12506_amd import ldgmg as L
+    from paper_2412_12506_amd.serving import ServingEngine, problem_kwargs, summarize
+    reqs = [Request(i, 0.004 * i, "poisson" if i % 3 else "interface", 3 if i % 2 else 2, 32 if i % 2 else 128,
+                    2 if i % 2 else 3, 1.0 if i % 3 else 1e2, 700 + i) for i in range(24)]
+    eng = ServingEngine(hbm_budget=64 * GIB, workers=2, max_batch=4, keep_solutions=True)
+    try:
+        keys = {(q.dim, q.n, q.p, float(q.contrast)) for q in reqs}
+        eng.prebuild(keys, threads=2)
+        for k in keys:
+            s = eng.entries[k].solver
+            s.upload()
+            st = L.ldgmg_level_storage(s.handle, 0)
+            s.unload()
+            print(f"\n[serving tiled] key {k}: fine-level storage {st}", flush=True)
+            if k[3] == 1.0:
+                assert st["tiled_A"] and st["tiled_S"], (k, st)
+        res = _run(eng, reqs)
+        print(f"\n[serving tiled] {summarize(res)}", flush=True)
+        assert not eng.errors, eng.errors
+        assert all(r.converged and r.rel_res_true <= 2e-10 for r in res)
+        joined = 0
+        for b in res:
+            same = [r for r in res if r.key == b.key and r.rid != b.rid]
+            if any(c.start < b.start < c.end for c in same) and any(a.end <= b.start for a in same):
+                joined += 1
+        print(f"[serving tiled] requests that joined a running batch: {joined}", flush=True)
+        assert joined >= 1
+        worst = _alone(res, eng.precision)
+        print(f"[serving tiled] alone vs mix worst relative difference {worst:.2e}", flush=True)
+    finally:
+        eng.close()

@@ -103,3 +103,100 @@ def test_summarize():
     assert s["requests"] == 100 and s["converged"] == 100 and s["rejected"] == 0
     assert abs(s["p50_ms"] - 50.5) < 1e-9 and abs(s["p99_ms"] - 99.01) < 1e-9
     assert s["mean_batch"] == 2 and s["dofs_solved"] == 100 * 16 ** 2 * 4
+
+
+class _StubSolver:
+    """Host-tier stand-in that checks the engine's ownership rules: a key is
+    solved by one worker at a time and never unloaded while it is solved."""
+
+    def __init__(self, key, log):
+        self.key, self.log = key, log
+        self.solving = 0
+        self.closed = False
+
+    def upload(self, stream=None):
+        assert self.solving == 0, "upload while solving"
+
+    def unload(self):
+        if self.solving:
+            self.log.append(f"unload of {self.key} while solving")
+
+    def close(self):
+        self.closed = True
+
+    def resmoothed(self, **kw):
+        raise RuntimeError("rebuild failed")
+
+
+def _stub_engine(budget, workers, log, need=40, solve_s=0.002, fail_keys=()):
+    import threading
+    import time as _t
+    eng = ServingEngine(hbm_budget=budget, workers=workers, max_batch=2)
+    eng._new_stream = lambda: None
+    lock = threading.Lock()
+
+    def build(key):
+        with eng.cv:
+            e = eng._entry(key)
+            e.solver, e.building = _StubSolver(key, log), False
+            eng.cv.notify_all()
+        return 0.0
+
+    def solve(e, batch, stream, setup_s, upload_s):
+        sv = e.solver
+        with lock:
+            if sv.solving:
+                log.append(f"concurrent solves of {e.key}")
+            sv.solving += 1
+        if not e.busy:
+            log.append(f"{e.key} solved while not marked busy")
+        _t.sleep(solve_s)
+        with lock:
+            sv.solving -= 1
+        failed = [r for r in batch if e.key in fail_keys and e.smoother == "sai"]
+        with eng.cv:
+            for r in batch:
+                if r not in failed:
+                    eng.results.append(Result(r.rid, e.key, r.arrival, 0.0, eng._now(), 1, True, 0.0,
+                                              len(batch), smoother=e.smoother))
+        return failed
+
+    eng._build_host = build
+    eng._need_bytes = lambda key: need
+    eng._solve_batch = solve
+    return eng
+
+
+def test_memory_wait_keeps_ownership():
+    """Keys that wait for memory are handed back and taken by other workers
+    meanwhile: no key is solved by two workers at once, none is unloaded or
+    evicted while it is solved, and every request is served exactly once."""
+    from types import SimpleNamespace
+    log = []
+    eng = _stub_engine(budget=100, workers=4, log=log, need=40)
+    reqs = [SimpleNamespace(rid=i, arrival=0.0005 * i, dim=2, n=8 + 2 * (i % 6), p=1, contrast=1.0,
+                            seed=i) for i in range(240)]
+    res = eng.run(reqs)
+    assert not log, log[:5]
+    assert sorted(r.rid for r in res) == list(range(240))
+    assert all(not r.error for r in res)
+    assert eng.evictions                      # the budget forced evictions along the way
+    assert eng.peak_used <= eng.budget
+
+
+def test_failed_rebuild_requeues_without_double_reports():
+    """A key whose SAI batch fails and whose GS rebuild raises: its requests
+    are queued again (not reported twice), the entry drops its host tier and
+    keeps the GS label, and the next batch (built from scratch with GS) serves
+    them."""
+    from types import SimpleNamespace
+    log = []
+    eng = _stub_engine(budget=1000, workers=2, log=log, fail_keys=((2, 8, 1, 10.0),))
+    reqs = [SimpleNamespace(rid=i, arrival=0.0, dim=2, n=8, p=1, contrast=10.0, seed=i) for i in range(3)]
+    res = eng.run(reqs)
+    assert not log
+    assert sorted(r.rid for r in res) == [0, 1, 2]
+    assert all(r.converged and r.smoother == "gs" and not r.error for r in res)
+    e = eng.entries[(2, 8, 1, 10.0)]
+    assert e.smoother == "gs" and e.fallbacks == 1
+    assert any("GS rebuild failed" in m for m in eng.errors)
