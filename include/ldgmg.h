@@ -104,6 +104,16 @@ typedef struct {
   int nthreads;       /* host threads for the setup; <= 0 -> hardware count      */
   size_t hbm_budget;  /* refuse ldgmg_upload above this many bytes; 0 = no limit */
   int storage;        /* LDGMG_STORE_* (default AUTO)                            */
+  /* Unsteady Stokes (Section 3.4.4, eq:govern1unsteady, eq:blockformunsteady):
+   * delta > 0 adds (1/delta) M_rho to every velocity block on every level
+   * (M_rho: density-weighted block mass, coarsened as I^T M_rho I, delta the
+   * same on every level; the paper takes delta = 0.1 h); delta = 0 (default):
+   * steady.  The pressure penalty then uses mu + rho h^2 / delta in place of
+   * mu, blending c_p h / mu (viscous limit) and c_p delta / (rho h)
+   * (projection limit).  rho: host, n^dim per-element densities, NULL means
+   * all 1; read during setup only.  Stokes only (EINVAL otherwise). */
+  const double* rho;
+  double delta;
   /* Device memory of the handle.  NULL (the default): hipMalloc / hipFree.
    * Otherwise every device buffer the handle owns (what ldgmg_upload
    * allocates, its temporary upload buffers, and the batch and GMRES
@@ -266,8 +276,8 @@ int ldgmg_rhs_check(ldgmg_handle h, double tol);
 /* Kernel of the fine operator found at upload (needs device data): *count
  * unit vectors (0 for a nonsingular operator), each the constant function of
  * one component (the pressure of Stokes; the scalar field, or the velocity
- * components, when no box face is Dirichlet), kept only if A k = 0 to
- * 1e-10 |A||k| row by row.  host_out: NULL, or *count * ndofs doubles,
+ * components, when no box face is Dirichlet), kept only if
+ * max |A k| <= 1e-10 max (|A| |k|) over the rows.  host_out: NULL, or *count * ndofs doubles,
  * receiving the vectors (fine-level layout). */
 int ldgmg_kernel(ldgmg_handle h, int* count, double* host_out);
 

@@ -13,6 +13,7 @@ Section 2.2 ("Multigrid schemes"):
         M_mu^{2h} = I^T M_mu^h I
         E^{2h}    = 1/2 I^T E^h I                      (tau ~ 1/h)
         E_p^{2h}  = 2   I^T E_p^h I                    (pressure tau ~ h)
+        M_rho^{2h} = I^T M_rho^h I                     (unsteady Stokes; delta is kept)
     and A^{2h} is formed from the coarse factors exactly as on the fine grid.
   * levels: halve n while n is even and n > 2; the last level is the bottom.
 """
@@ -43,6 +44,8 @@ class Level:
     gamma: int = 0
     I: Optional[sp.spmatrix] = None   # injection from the next coarser level into this one
     ncomp: int = 1                 # scalar fields per element (Stokes: d+1)
+    Mrho: Optional[sp.spmatrix] = None   # density-weighted mass (unsteady Stokes), else None
+    delta: float = 0.0                    # time-step parameter of eq:blockformunsteady (0: steady)
 
 
 def level_sizes(n: int) -> List[int]:
@@ -93,6 +96,8 @@ def coarsen_factors(lv: Level, tau_scale_E=0.5, tau_scale_Ep=2.0):
     M = sp.block_diag([cem.M] * cg.ne, format="bsr")
     E = to_bsr(tau_scale_E * (It @ lv.E.tocsr() @ I), bsz)
     Ep = None if lv.Ep is None else to_bsr(tau_scale_Ep * (It @ lv.Ep.tocsr() @ I), bsz)
+    if lv.Mrho is not None:      # M_rho^{2h} = I^T M_rho^h I, like the viscosity-weighted mass
+        return cg, cem, G, Mmu, M, E, Ep, to_bsr(It @ lv.Mrho.tocsr() @ I, bsz)
     return cg, cem, G, Mmu, M, E, Ep
 
 
@@ -103,7 +108,7 @@ def scalar_levels(dim: int, n: int, p: int, mu=None, bc=None, basis="legendre",
     lv = Level(op.grid, op.em, op.G, op.Mmu, op.M, op.E, None, op.A, op.em.bs)
     levels = [lv]
     for _ in level_sizes(n)[1:]:
-        cg, cem, G, Mmu, M, E, _ = coarsen_factors(levels[-1])
+        cg, cem, G, Mmu, M, E, _ = coarsen_factors(levels[-1])[:7]
         A = combine(G, Mmu, E, cem.bs)
         levels[-1].I = injection(levels[-1].grid, levels[-1].em, 1)
         levels.append(Level(cg, cem, G, Mmu, M, E, None, A, cem.bs))

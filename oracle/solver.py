@@ -24,13 +24,13 @@ DEFAULT_CP = 0.1
 
 def build(dim, n, p, system="poisson", mu=None, bc=None, basis="legendre",
           gamma=1, smoother="sai", sai_level=1, order="OI", nu1=3, nu2=3,
-          omega=None, zeta=None, tau0=DEFAULT_TAU0, cp=DEFAULT_CP):
+          omega=None, zeta=None, tau0=DEFAULT_TAU0, cp=DEFAULT_CP, rho=None, delta=0.0):
     if system == "poisson":
         levels = hierarchy.scalar_levels(dim, n, p, mu, bc, basis, tau0)
         vc = vcycle.build_mg(levels, smoother, sai_level, order, nu1, nu2, omega,
                              balance="scalar")
     else:
-        levels = stokes.stokes_levels(dim, n, p, mu, bc, gamma, basis, tau0, cp)
+        levels = stokes.stokes_levels(dim, n, p, mu, bc, gamma, basis, tau0, cp, rho, delta)
         if zeta is None:
             zeta = TAB_ZETA[(gamma, dim)][p - 1]
         vc = vcycle.build_mg(levels, smoother, sai_level, order, nu1, nu2, omega,

@@ -40,8 +40,10 @@ def _perm_comp_to_elem(ne: int, bss: int, ncomp: int) -> np.ndarray:
     return (c * ne * bss + e * bss + a).reshape(-1)
 
 
-def stokes_matrix(G, Mmu, M, E, Ep, gamma: int, ne: int, bss: int):
-    """Assemble the element-major saddle-point matrix from scalar factors."""
+def stokes_matrix(G, Mmu, M, E, Ep, gamma: int, ne: int, bss: int, Mrho=None, delta: float = 0.0):
+    """Assemble the element-major saddle-point matrix from scalar factors;
+    with Mrho and delta > 0 the velocity blocks gain (1/delta) M_rho
+    (eq:blockformunsteady)."""
     d = len(G)
     Gc = [g.tocsr() for g in G]
     Mmu = Mmu.tocsr()
@@ -49,6 +51,8 @@ def stokes_matrix(G, Mmu, M, E, Ep, gamma: int, ne: int, bss: int):
     lap = E.tocsr()
     for k in range(d):
         lap = lap + Gc[k].T @ Mmu @ Gc[k]
+    if Mrho is not None and delta > 0:
+        lap = lap + Mrho.tocsr() / delta
     rows = []
     for i in range(d):
         row = []
@@ -66,32 +70,51 @@ def stokes_matrix(G, Mmu, M, E, Ep, gamma: int, ne: int, bss: int):
     return to_bsr(K, (d + 1) * bss)
 
 
-def pressure_penalty(grid: Grid, em: ElementMatrices, mu, cp: float):
+def pressure_penalty(grid: Grid, em: ElementMatrices, mu, cp: float, rho=None, delta: float = 0.0):
+    """E_p with weight c_p h / max(mu_eff,L, mu_eff,R) on interior faces.
+    Steady: mu_eff = mu.  Unsteady (delta > 0; the blending rule of the work
+    the paper cites is not reproduced in it, so this is a reading, parity
+    unpinned in absolute terms): mu_eff = mu + rho h^2 / delta, so that the
+    weight is c_p h / mu where viscosity dominates and c_p delta / (rho h),
+    the penalty of the pressure-Poisson (projection) limit, where rho / delta
+    dominates."""
+    mu = np.asarray(mu, dtype=np.float64)
+    if rho is not None and delta > 0:
+        mu = mu + np.asarray(rho, dtype=np.float64) * grid.h ** 2 / delta
     return assemble_penalty(grid, em, mu, 0.0,
                             interior_tau=lambda ml, mr: cp * grid.h / max(ml, mr),
                             dirichlet=False)
 
 
 def stokes_levels(dim: int, n: int, p: int, mu=None, bc=None, gamma: int = 1,
-                  basis: str = "legendre", tau0: float = 1.0, cp: float = 1.0) -> List[Level]:
+                  basis: str = "legendre", tau0: float = 1.0, cp: float = 1.0,
+                  rho=None, delta: float = 0.0) -> List[Level]:
+    """Stokes hierarchy; with delta > 0 the unsteady operator of
+    eq:blockformunsteady: (1/delta) M_rho added to every velocity block, rho
+    per element (None: 1), delta kept on every level."""
     grid = Grid(dim, n, bc)
     em = ElementMatrices(dim, p, grid.h, basis)
     mu = np.ones(grid.ne) if mu is None else np.asarray(mu, dtype=np.float64)
+    unsteady = delta > 0
+    rho_v = np.ones(grid.ne) if rho is None else np.asarray(rho, dtype=np.float64)
     G = assemble_gradient(grid, em, mu)
     Mmu = block_diag(grid, [mu[e] * em.M for e in range(grid.ne)])
     M = block_diag(grid, [em.M] * grid.ne)
     E = assemble_penalty(grid, em, mu, tau0)
-    Ep = pressure_penalty(grid, em, mu, cp)
+    Ep = pressure_penalty(grid, em, mu, cp, rho_v if unsteady else None, delta)
+    Mrho = block_diag(grid, [rho_v[e] * em.M for e in range(grid.ne)]) if unsteady else None
     ncomp = dim + 1
-    A = stokes_matrix(G, Mmu, M, E, Ep, gamma, grid.ne, em.bs)
-    lv = Level(grid, em, G, Mmu, M, E, Ep, A, ncomp * em.bs, "stokes", gamma, None, ncomp)
+    A = stokes_matrix(G, Mmu, M, E, Ep, gamma, grid.ne, em.bs, Mrho, delta)
+    lv = Level(grid, em, G, Mmu, M, E, Ep, A, ncomp * em.bs, "stokes", gamma, None, ncomp, Mrho, delta)
     levels = [lv]
     for _ in level_sizes(n)[1:]:
-        cg, cem, Gc, Mmuc, Mc, Ec, Epc = coarsen_factors(levels[-1])
-        Ac = stokes_matrix(Gc, Mmuc, Mc, Ec, Epc, gamma, cg.ne, cem.bs)
+        out = coarsen_factors(levels[-1])
+        cg, cem, Gc, Mmuc, Mc, Ec, Epc = out[:7]
+        Mrc = out[7] if unsteady else None
+        Ac = stokes_matrix(Gc, Mmuc, Mc, Ec, Epc, gamma, cg.ne, cem.bs, Mrc, delta)
         levels[-1].I = injection(levels[-1].grid, levels[-1].em, ncomp)
         levels.append(Level(cg, cem, Gc, Mmuc, Mc, Ec, Epc, Ac, ncomp * cem.bs,
-                            "stokes", gamma, None, ncomp))
+                            "stokes", gamma, None, ncomp, Mrc, delta))
     return levels
 
 

@@ -461,6 +461,8 @@ bool fp32_residual_level(const HostHierarchy& H, int l, int prec) {
          use_tiled(L.S, L.bs, elem_bytes_S(prec), storage);
 }
 
+std::vector<std::vector<double>> kernel_patterns(const HostHierarchy& H);
+
 size_t estimate_from_host(const HostHierarchy& H, int prec) {
   const int storage = H.prob.storage;
   const size_t ea = elem_bytes_A(prec), es = elem_bytes_S(prec);
@@ -492,14 +494,15 @@ size_t estimate_from_host(const HostHierarchy& H, int prec) {
       b += static_cast<size_t>(F.A.pool.size()) * tiled_block_elems(F.bs) * 8;
   }
   b += 5 * N * 8 + 64 * 8 + kRedBlocks * 8 * 2;
+  b += 2 * kernel_patterns(H).size() * N * 8;   // kernel vectors and mean weights (singular operators)
   return b;
 }
 
 // Kernel of the fine operator.  Candidates: the constant function in one
 // component (the scalar field of a problem with no Dirichlet face, the
 // pressure of Stokes, the velocity components of Stokes with no Dirichlet
-// face); a candidate k is kept when |A k| <= 1e-10 (|A| |k|) row by row in
-// FP64, evaluated per distinct block of the pooled A.  Per element the
+// face); a candidate k is kept when max_i |(A k)_i| <= 1e-10 max_i (|A| |k|)_i
+// in FP64, evaluated per distinct block of the pooled A.  Per element the
 // constant's coefficients are c1 (x) c1 (x) c1 with c1 = m^-1 (int psi_i),
 // m the 1-D mass matrix.
 std::vector<std::vector<double>> kernel_patterns(const HostHierarchy& H) {
@@ -569,9 +572,9 @@ std::vector<std::vector<double>> kernel_patterns(const HostHierarchy& H) {
         ak[static_cast<size_t>(id) * bs + r] = s2;
       }
     }
-    bool in_kernel = true;
+    double worst = 0.0, scale = 0.0;
     std::vector<double> s1(bs), s2(bs);
-    for (int i = 0; i < A.nbr && in_kernel; ++i) {
+    for (int i = 0; i < A.nbr; ++i) {
       std::fill(s1.begin(), s1.end(), 0.0);
       std::fill(s2.begin(), s2.end(), 0.0);
       for (int sl = A.rp[i]; sl < A.rp[i + 1]; ++sl)
@@ -579,10 +582,12 @@ std::vector<std::vector<double>> kernel_patterns(const HostHierarchy& H) {
           s1[r] += bk[static_cast<size_t>(A.id[sl]) * bs + r];
           s2[r] += ak[static_cast<size_t>(A.id[sl]) * bs + r];
         }
-      for (int r = 0; r < bs; ++r)
-        if (std::fabs(s1[r]) > 1e-10 * s2[r]) in_kernel = false;
+      for (int r = 0; r < bs; ++r) {
+        worst = std::max(worst, std::fabs(s1[r]));
+        scale = std::max(scale, s2[r]);
+      }
     }
-    if (in_kernel) out.push_back(k);
+    if (worst <= 1e-10 * scale) out.push_back(k);
   }
   return out;
 }
@@ -1756,6 +1761,8 @@ int ldgmg_problem_default(ldgmg_problem* p) {
   p->nthreads = 0;
   p->hbm_budget = 0;
   p->storage = LDGMG_STORE_AUTO;
+  p->rho = nullptr;
+  p->delta = 0.0;
   p->dev_alloc = nullptr;
   p->dev_free = nullptr;
   p->alloc_ctx = nullptr;

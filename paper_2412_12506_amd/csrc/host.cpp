@@ -330,6 +330,8 @@ void validate_problem(const ldgmg_problem& p) {
   if (!(p.tau0 > 0) || !(p.cp >= 0)) throw std::invalid_argument("penalty constants must be positive");
   if ((p.dev_alloc == nullptr) != (p.dev_free == nullptr))
     throw std::invalid_argument("dev_alloc and dev_free must be given together");
+  if (!(p.delta >= 0) || !std::isfinite(p.delta)) throw std::invalid_argument("delta must be finite and >= 0");
+  if (p.delta > 0 && p.system != LDGMG_STOKES) throw std::invalid_argument("the density term is for Stokes");
   for (int k = 0; k < p.dim; ++k) {
     const int a = p.bc[2 * k], b = p.bc[2 * k + 1];
     if (a < 0 || a > 2 || b < 0 || b > 2) throw std::invalid_argument("unknown bc");
@@ -341,6 +343,9 @@ void validate_problem(const ldgmg_problem& p) {
   if (p.mu)
     for (long long e = 0; e < ne; ++e)
       if (!(p.mu[e] > 0) || !std::isfinite(p.mu[e])) throw std::invalid_argument("viscosity must be finite and > 0");
+  if (p.rho && p.delta > 0)
+    for (long long e = 0; e < ne; ++e)
+      if (!(p.rho[e] > 0) || !std::isfinite(p.rho[e])) throw std::invalid_argument("density must be finite and > 0");
 }
 
 namespace {
@@ -703,7 +708,7 @@ void compose(PMat& A, const std::vector<Piece>& pieces, int ne, int bss, int nco
              });
 }
 
-void assemble_system(HostLevel& L, int system, int gamma) {
+void assemble_system(HostLevel& L, int system, int gamma, double delta) {
   const int d = L.em.dim, bss = L.bss;
   PMat S;
   std::vector<std::pair<const PMat*, const PMat*>> lap;
@@ -728,6 +733,7 @@ void assemble_system(HostLevel& L, int system, int gamma) {
   for (int i = 0; i < d; ++i) {
     pcs.push_back({&S, i, i, 1.0});
     pcs.push_back({&L.E, i, i, 1.0});
+    if (delta > 0) pcs.push_back({&L.Mrho, i, i, 1.0 / delta});   // eq:blockformunsteady
     if (gamma)
       for (int j = 0; j < d; ++j) pcs.push_back({&C[i * d + j], i, j, static_cast<double>(gamma)});
     pcs.push_back({&GtM[i], i, d, -1.0});
@@ -1047,11 +1053,16 @@ std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const 
   validate_problem(pr);
   const ldgmg_problem& q = src.prob;
   bool same = pr.dim == q.dim && pr.n == q.n && pr.p == q.p && pr.basis == q.basis && pr.system == q.system &&
-              pr.gamma == q.gamma && pr.tau0 == q.tau0 && pr.cp == q.cp;
+              pr.gamma == q.gamma && pr.tau0 == q.tau0 && pr.cp == q.cp && pr.delta == q.delta;
   for (int f = 0; f < 6; ++f) same = same && pr.bc[f] == q.bc[f];
   if (same) {
     for (size_t e = 0; e < src.mu.size(); ++e)
       if ((pr.mu ? pr.mu[e] : 1.0) != src.mu[e]) {
+        same = false;
+        break;
+      }
+    for (size_t e = 0; e < src.rho.size(); ++e)
+      if ((pr.rho ? pr.rho[e] : 1.0) != src.rho[e]) {
         same = false;
         break;
       }
@@ -1062,6 +1073,7 @@ std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const 
   auto H = std::make_unique<HostHierarchy>(src);   // operators, transfers, bottom pseudo-inverse
   H->prob = pr;
   H->prob.mu = nullptr;
+  H->prob.rho = nullptr;
   H->omega = default_omega(pr);
   H->zeta = default_zeta(pr);
   for (size_t l = 0; l + 1 < H->levels.size(); ++l) {
@@ -1091,6 +1103,11 @@ std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
   for (int k = 0; k < d; ++k) ne0 *= pr.n;
   H->mu.assign(ne0, 1.0);
   if (pr.mu) std::copy(pr.mu, pr.mu + ne0, H->mu.begin());
+  H->prob.rho = nullptr;
+  if (pr.delta > 0) {
+    H->rho.assign(ne0, 1.0);
+    if (pr.rho) std::copy(pr.rho, pr.rho + ne0, H->rho.begin());
+  }
   H->omega = default_omega(pr);
   H->zeta = default_zeta(pr);
   const std::vector<int> sizes = level_sizes(pr.n);
@@ -1122,7 +1139,18 @@ std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
       for (int k = 0; k < d; ++k) build_gradient(L.G[k], grids[0], L.em, mu, k);
       build_mu_mass(L.Mmu, grids[0], L.em, mu);
       build_penalty(L.E, grids[0], L.em, mu, pr.tau0, 0);
-      if (ncomp > 1) build_penalty(L.Ep, grids[0], L.em, mu, pr.cp, 1);
+      if (ncomp > 1) {
+        if (pr.delta > 0) {
+          // unsteady: the pressure penalty sees mu + rho h^2 / delta (blending the
+          // viscous and the projection limits); the velocity blocks gain M_rho / delta
+          std::vector<double> mu_eff(H->mu);
+          for (size_t e = 0; e < mu_eff.size(); ++e) mu_eff[e] += H->rho[e] * L.h * L.h / pr.delta;
+          build_penalty(L.Ep, grids[0], L.em, mu_eff.data(), pr.cp, 1);
+          build_mu_mass(L.Mrho, grids[0], L.em, H->rho.data());
+        } else {
+          build_penalty(L.Ep, grids[0], L.em, mu, pr.cp, 1);
+        }
+      }
     } else {
       HostLevel& F = H->levels[l - 1];
       const Family fam = make_family(grids[l - 1], grids[l]);
@@ -1130,8 +1158,9 @@ std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
       coarsen_pmat(L.Mmu, F.Mmu, fam, grids[l], F.em, L.em, 1.0, false);
       coarsen_pmat(L.E, F.E, fam, grids[l], F.em, L.em, 0.5, false);
       if (ncomp > 1) coarsen_pmat(L.Ep, F.Ep, fam, grids[l], F.em, L.em, 2.0, false);
+      if (pr.delta > 0) coarsen_pmat(L.Mrho, F.Mrho, fam, grids[l], F.em, L.em, 1.0, false);
     }
-    assemble_system(L, pr.system, pr.gamma);
+    assemble_system(L, pr.system, pr.gamma, pr.delta);
     const bool bottom = l + 1 == sizes.size();
     if (bottom) {
       build_bottom(L);

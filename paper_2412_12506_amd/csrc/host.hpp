@@ -74,6 +74,7 @@ struct HostLevel {
   ElemOps em;
   std::vector<PMat> G;         // per dimension (scalar blocks)
   PMat Mmu, E, Ep;             // scalar blocks
+  PMat Mrho;                   // density-weighted mass (unsteady Stokes), scalar blocks
   PMat A;                      // system blocks (bs x bs)
   PMat S;                      // smoother matrix: B (SAI) or D^-1 (block diagonal)
   std::vector<int> tpos;       // slot of S(j,i) for each slot (i,j) of S
@@ -89,6 +90,7 @@ struct HostLevel {
 struct HostHierarchy {
   ldgmg_problem prob{};
   std::vector<double> mu;      // fine-level viscosity
+  std::vector<double> rho;     // fine-level density (unsteady Stokes; empty when steady)
   std::vector<HostLevel> levels;
   double omega = 0, zeta = 0;
   double setup_seconds = 0;

@@ -39,7 +39,8 @@ class Problem(C.Structure):
                 ("smoother", C.c_int), ("sai_level", C.c_int), ("order", C.c_int),
                 ("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("zeta", C.c_double),
                 ("precision", C.c_int), ("nthreads", C.c_int), ("hbm_budget", C.c_size_t),
-                ("storage", C.c_int), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
+                ("storage", C.c_int), ("rho", C.POINTER(C.c_double)), ("delta", C.c_double),
+                ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
                 ("alloc_ctx", C.c_void_p)]
 
 
@@ -200,7 +201,8 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
                  gamma: int = 1, bc=None, mu=None, tau0: float = 1.0, cp: float = 0.1,
                  smoother: str = "sai", sai_level: int = 1, order: str = "OI", nu1: int = 3,
                  nu2: int = 3, omega: float = 0.0, zeta: float = 0.0, precision: str = "fp32",
-                 nthreads: int = 0, hbm_budget: int = 0, storage: str = "auto", allocator=None):
+                 nthreads: int = 0, hbm_budget: int = 0, storage: str = "auto", allocator=None,
+                 rho=None, delta: float = 0.0):
     """Problem struct plus the numpy array that backs `mu` (keep both alive).
     allocator: None (hipMalloc) or an object with install(problem), such as
     TorchAllocator (keep it alive as long as the handle)."""
@@ -228,6 +230,13 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
     pr.nthreads = nthreads
     pr.hbm_budget = hbm_budget
     pr.storage = STORAGE[storage]
+    pr.delta = delta
+    if rho is not None:
+        rho_arr = np.ascontiguousarray(rho, dtype=np.float64)
+        if rho_arr.size != n ** dim:
+            raise ValueError("rho must have n^dim entries")
+        pr.rho = rho_arr.ctypes.data_as(C.POINTER(C.c_double))
+        mu_arr = (mu_arr, rho_arr)        # keep both arrays alive with the struct
     if allocator is not None:
         allocator.install(pr)
     return pr, mu_arr

@@ -7,26 +7,38 @@ from ldg_inputs import mu_field, mu_box
 from oracle import solver as osolver
 
 
-def mu_of(case):
-    spec = case.get("mu")
+def field_of(case, name="mu"):
+    """Per-element field of a case: None, ("box", _, inner) (inner value inside
+    (1/4,3/4)^d, 1 outside), ("uniform", _, value), or a ball / disc spec."""
+    spec = case.get(name)
     if spec is None:
         return None
     kind, radius, contrast = spec
     if kind == "box":
         return mu_box(case["dim"], case["n"], contrast)
+    if kind == "uniform":
+        return np.full(case["n"] ** case["dim"], float(contrast))
     return mu_field(case["dim"], case["n"], kind, radius, contrast)
 
 
+def mu_of(case):
+    return field_of(case, "mu")
+
+
 def lib_kwargs(case, precision):
-    kw = {k: v for k, v in case.items() if k not in ("mu", "id", "krylov")}
+    kw = {k: v for k, v in case.items() if k not in ("mu", "rho", "id", "krylov")}
     kw["mu"] = mu_of(case)
+    if "rho" in case:
+        kw["rho"] = field_of(case, "rho")
     kw["precision"] = precision
     return kw
 
 
 def oracle_build(case):
-    kw = {k: v for k, v in case.items() if k not in ("mu", "id", "krylov", "nthreads")}
+    kw = {k: v for k, v in case.items() if k not in ("mu", "rho", "id", "krylov", "nthreads")}
     kw["mu"] = mu_of(case)
+    if "rho" in case:
+        kw["rho"] = field_of(case, "rho")
     return osolver.build(**kw)
 
 

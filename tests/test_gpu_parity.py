@@ -53,6 +53,10 @@ CASES = [
          smoother="sai", mu=("disc", 0.25, 1e3), krylov="gmres"),
     dict(id="s2d-p1-std-gs", dim=2, n=8, p=1, system="stokes", gamma=0, smoother="gs",
          order="OO", krylov="gmres"),
+    # unsteady stress-form Stokes (eq:blockformunsteady): a gas bubble (rho 1e-3, mu 2e-4) in
+    # water, delta = 0.1 h
+    dict(id="s2d-p2-unsteady-gas-in-water", dim=2, n=8, p=2, system="stokes", gamma=1, smoother="sai",
+         mu=("box", 0.0, 2e-4), rho=("box", 0.0, 1e-3), delta=0.1 / 8, krylov="gmres"),
 ]
 
 

@@ -29,6 +29,12 @@ CASES = [
     dict(id="p2d-p3-n10-threaded-bottom", dim=2, n=10, p=3, smoother="jacobi", nthreads=4),
     dict(id="s2d-p2-n10-threaded-bottom", dim=2, n=10, p=2, system="stokes", gamma=1, smoother="sai",
          mu=("disc", 0.25, 1e3), nthreads=3),
+    # unsteady Stokes (eq:blockformunsteady, delta = 0.1 h): a gas bubble in water, stress form;
+    # single phase, standard form, periodic, mu = 1e-2
+    dict(id="s2d-p2-unsteady-gas-in-water", dim=2, n=8, p=2, system="stokes", gamma=1, smoother="sai",
+         mu=("box", 0.0, 2e-4), rho=("box", 0.0, 1e-3), delta=0.1 / 8),
+    dict(id="s2d-p1-unsteady-periodic-std", dim=2, n=8, p=1, system="stokes", gamma=0, smoother="gs",
+         mu=("uniform", 0.0, 1e-2), delta=0.1 / 8, bc=["P"] * 4),
 ]
 
 

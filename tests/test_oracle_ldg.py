@@ -252,3 +252,67 @@ def test_factor_coarsening_variable_mu_aligned_box(system, dim, p, ratio):
         direct = stokes.stokes_levels(dim, n // 2, p, mu=mu_c, gamma=1, cp=0.1)[0].A
     D = direct.toarray()
     assert np.abs(lv[1].A.toarray() - D).max() <= 1e-13 * np.abs(D).max()
+
+
+def _unsteady_residual(dim, n, p, gamma, mu, rho, delta, u, pres, f, nq, cp=0.1):
+    lv = stokes.stokes_levels(dim, n, p, mu=mu, gamma=gamma, cp=cp, rho=rho, delta=delta)[0]
+    fq = [sample_on_elements(dim, n, nq, fi) for fi in f]
+    b = stokes.stokes_rhs(lv, mu, fq, nq, u)
+    x = _l2_coefficients(lv, list(u) + [pres], nq)
+    A = lv.A.tocsr()
+    return np.abs(A @ x - b).max() / (abs(A) @ np.abs(x) + np.abs(b)).max()
+
+
+@pytest.mark.parametrize("gamma", [0, 1])
+def test_unsteady_stokes_polynomial_reproduction(gamma):
+    """eq:govern1unsteady with delta = 0.1 h, rho = 3: the discrete system of
+    eq:blockformunsteady reproduces u = curl(x^2 y^2), p = x y with
+    f = (rho / delta) u - Lap u + grad p, in standard and stress form."""
+    n, p, nq = 3, 2, 5
+    rho, delta = 3.0, 0.1 / n
+    u = [lambda x, y: 2 * x ** 2 * y, lambda x, y: -2 * x * y ** 2]
+    pres = lambda x, y: x * y
+    f = [lambda x, y: rho / delta * 2 * x ** 2 * y - 4 * y + y,
+         lambda x, y: -rho / delta * 2 * x * y ** 2 + 4 * x + x]
+    res = _unsteady_residual(2, n, p, gamma, np.ones(n * n), np.full(n * n, rho), delta, u, pres, f, nq)
+    assert res < 1e-13
+    # the density term belongs to the velocity rows only: the steady operator
+    # with the same data leaves an O(1) residual
+    res_s = _unsteady_residual(2, n, p, gamma, np.ones(n * n), None, 0.0, u, pres, f, nq)
+    assert res_s > 1e-3
+
+
+def test_unsteady_stokes_water_gas_planar_interface():
+    """Water (rho 1, mu 1) left of x = 1/2, gas (rho 1e-3, mu 2e-4) right, stress
+    form, delta = 0.1 h: u = (c y, b(x)) with the stress-form traction
+    condition and f = (rho / delta) u, piecewise by phase, is reproduced
+    exactly (the density jumps with the phase, element by element)."""
+    dim, n, p, nq = 2, 4, 2, 5
+    left = np.array([(e % n) < n // 2 for e in range(n * n)])
+    mu = np.where(left, 1.0, 2e-4)
+    rho = np.where(left, 1.0, 1e-3)
+    delta = 0.1 / n
+    c, sR = 1.0, 1.0
+    sL = 2e-4 * (sR + c) / 1.0 - c
+    b_of = lambda x: np.where(x < 0.5, sL * x, sL * 0.5 + sR * (x - 0.5))
+    u = [lambda x, y: c * y + 0 * x, lambda x, y: b_of(x) + 0 * y]
+    r_of = lambda x: np.where(x < 0.5, 1.0, 1e-3)
+    f = [lambda x, y: r_of(x) / delta * c * y, lambda x, y: r_of(x) / delta * b_of(x) + 0 * y]
+    res = _unsteady_residual(dim, n, p, 1, mu, rho, delta, u, lambda x, y: 0 * x, f, nq)
+    assert res < 1e-12
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (3, 1)])
+def test_unsteady_density_mass_coarsening(dim, p):
+    """The coarsened density mass I^T M_rho I with delta kept equals the term
+    assembled directly on the coarse grid (box of densities 1e-3 / 1 aligned
+    with the n = 4 grid; the pressure penalty, which depends on h through its
+    blending, is switched off on both sides)."""
+    n = 8
+    delta = 0.1 / n
+    lv = stokes.stokes_levels(dim, n, p, mu=mu_box(dim, n, 2e-4), rho=mu_box(dim, n, 1e-3), delta=delta,
+                              gamma=1, cp=0.0)
+    direct = stokes.stokes_levels(dim, n // 2, p, mu=mu_box(dim, n // 2, 2e-4), rho=mu_box(dim, n // 2, 1e-3),
+                                  delta=delta, gamma=1, cp=0.0)[0].A
+    D = direct.toarray()
+    assert np.abs(lv[1].A.toarray() - D).max() <= 1e-13 * np.abs(D).max()
