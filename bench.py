@@ -72,25 +72,28 @@ def run_path(L, torch, args, precision, rhs, prof, storage="auto", fp32_products
     return out
 
 
-def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_products):
-    """Warm up and time args.steps solves on handle s (storage precision
-    `precision`, logged as `label`)."""
+def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_products, krylov="cg",
+                maxit=200, steps=None, warmup=None):
+    """Warm up and time `steps` (default args.steps) solves on handle s
+    (storage precision `precision`, logged as `label`)."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     x = torch.empty_like(rhs[0])
-    for i in range(args.warmup):
-        info = s.solve(rhs[i], x, "cg", 1e-10, 200)
+    for i in range(warmup):
+        info = s.solve(rhs[i], x, krylov, 1e-10, maxit)
         log(f"[{label}] warmup {i}: iters {info['iters']}")
     stream = torch.cuda.current_stream()
     if prof:
         L.ldgmg_profile(s.handle, True)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+          for _ in range(steps)]
     infos = []
     t0 = time.time()
-    for k in range(args.steps):
-        b = rhs[args.warmup + k]
+    for k in range(steps):
+        b = rhs[warmup + k]
         ev[k][0].record(stream)
-        info = s.solve(b, x, "cg", 1e-10, 200, stream=stream)
+        info = s.solve(b, x, krylov, 1e-10, maxit, stream=stream)
         ev[k][1].record(stream)
         infos.append(info)
         log(f"[{label}] step {k}: iters {info['iters']} rel_res {info['rel_res_true']:.2e}")
@@ -103,12 +106,13 @@ def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_pr
         "setup_s": setup_s,
         "total_ms": total_ms,
         "wall_s": wall,
-        "ms_per_solve": total_ms / args.steps,
-        "solves_per_s": 1000.0 * args.steps / total_ms,
+        "ms_per_solve": total_ms / steps,
+        "solves_per_s": 1000.0 * steps / total_ms,
         "vcycle_dof_per_s": s.ndofs * vcycles / (total_ms / 1000.0),
         "p50_ms": percentile(lat, 50),
         "p99_ms": percentile(lat, 99),
         "iters": [i["iters"] for i in infos],
+        "converged": all(i["converged"] for i in infos),
         "eta": float(sum(i["eta"] for i in infos) / len(infos)),
         "rel_res_true_max": max(i["rel_res_true"] for i in infos),
         "vcycles": vcycles,
@@ -127,6 +131,8 @@ def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_pr
         kinds = {}
         for kind in ("A", "S", "ST", "A64"):
             cnt, ms = L.ldgmg_profile_read(s.handle, kind)
+            if kind != "A" and not cnt:
+                continue
             nnzb = info0["nnzb_A"] if kind in ("A", "A64") else info0["nnzb_S"]
             ebk = 8 if kind == "A64" else eb_a if kind == "A" else eb_s
             pool = storage["pool_A"] if kind in ("A", "A64") else storage["pool_S"]
@@ -229,13 +235,16 @@ CATALOGUES = {
 }
 
 
-def run_serving(args, torch):
+def run_serving(args, torch, nested=False):
     """Replay the seeded request stream through the serving engine; one JSON
-    line with solves/s and p50/p99 latency (arrival to completion)."""
+    line with solves/s and p50/p99 latency (arrival to completion).  nested:
+    the reduced replay of the main line (the lite catalogue, --replay-requests
+    requests), returned instead of printed."""
     from ldg_inputs import serving_requests
     from paper_2412_12506_amd.serving import ServingEngine, problem_key, summarize
-    cat = CATALOGUES[args.serving_catalogue]
-    reqs = serving_requests(count=args.serving_requests, **cat)
+    catalogue = "lite" if nested else args.serving_catalogue
+    cat = CATALOGUES[catalogue]
+    reqs = serving_requests(count=args.replay_requests if nested else args.serving_requests, **cat)
     free, total = torch.cuda.mem_get_info()
     budget = int(args.serving_budget_gib * (1 << 30)) if args.serving_budget_gib else int(free * 0.9)
     eng = ServingEngine(budget, workers=args.serving_workers)
@@ -278,15 +287,104 @@ def run_serving(args, torch):
         "metric": METRIC, "value": sat["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": sat["wall_s"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "block_storage": "f32", "data": "synthetic",
-        "config": {"workload": f"serving_{len(reqs)}_mixed_{args.serving_catalogue}",
+        "config": {"workload": f"serving_{len(reqs)}_mixed_{catalogue}",
                    "requests": len(reqs), "hierarchies": len(keys),
                    "offered_rate_per_s": out["offered"]["rate_per_s"],
-                   "rtol": 1e-10, "smoother": "SAI_1 OI", "outer": "FP64 CG (batched, k<=8)",
+                   "rtol": 1e-10, "smoother": "SAI_1 OI",
+                   "outer": f"FP64 CG, continuous batching (ldgmg_solve_stream, {eng.max_batch} slots)",
                    "workers": args.serving_workers, "hbm_budget_gib": budget / 2 ** 30},
         "p50_ms": out["offered"]["p50_ms"], "p99_ms": out["offered"]["p99_ms"],
         "offered": out["offered"], "saturated": sat, "host_setup_s": setup_s,
     }
+    if nested:
+        return {k: line[k] for k in ("value", "unit", "config", "p50_ms", "p99_ms", "offered", "saturated",
+                                     "host_setup_s")}
     print(json.dumps(line), flush=True)
+
+
+def kernel_summary(kinds, kind):
+    v = kinds.get(kind)
+    if not v or not v["count"]:
+        return None
+    return {kk: v[kk] for kk in ("count", "mean_ms", "gbs", "tflops", "bytes_per_launch", "flops_per_launch",
+                                 "pooled", "tiled")}
+
+
+def run_interface_config(L, torch, args, BASE_SEED):
+    """96^3 elliptic interface, Q_2, viscosity 1e4 inside the sphere r = 0.3
+    (element-centre test), FP32 storage, FP64 CG to 1e-10.  The coloured
+    Gauss-Seidel OI V-cycle converges and is timed; the SAI_1 OI V-cycle does
+    not converge on this curved interface (Section 3 of the design notes): it
+    runs a bounded number of iterations, which times its fine-level B applies
+    (expanded storage: the distinct columns of a curved interface are too many
+    to pool), the HBM-bound kernel of this workload."""
+    from ldg_inputs import mu_field, rhs_normal
+    n, p = args.cfg3_n, 2
+    mu = mu_field(3, n, "sphere", 0.3, 1e4)
+    ndofs = n ** 3 * (p + 1) ** 3
+    rhs = [torch.from_numpy(rhs_normal(ndofs, BASE_SEED + i)).cuda() for i in range(2)]
+    out = {"workload": f"interface3d_p2_n{n}_sphere1e4", "fine_dofs": ndofs}
+    for sm, label, maxit, steps, warm in (("gs", "gs_oi", 200, 1, 1), ("sai", "sai1_oi", args.cfg3_sai_maxit, 1, 0)):
+        t0 = time.time()
+        sv = L.Solver(dim=3, n=n, p=p, mu=mu, smoother=sm, sai_level=1, order="OI", precision="fp32")
+        torch.cuda.synchronize()
+        setup = time.time() - t0
+        log(f"[interface {label}] setup {setup:.1f}s")
+        r = time_solves(L, torch, args, sv, "fp32", f"interface {label}", rhs, True, setup, False,
+                        maxit=maxit, steps=steps, warmup=warm)
+        st = L.ldgmg_level_storage(sv.handle, 0)
+        sv.close()
+        keep = ("setup_s", "ms_per_solve", "solves_per_s", "vcycle_dof_per_s", "iters", "converged",
+                "rel_res_true_max", "eta")
+        out[label] = {k: r[k] for k in keep}
+        out[label]["fine_storage"] = st
+        out[label]["kernels"] = {kk: kernel_summary(r["kernels"], kk) for kk in ("A", "S", "ST", "A64")}
+    b = out["sai1_oi"]["kernels"].get("S")
+    if b and not b["pooled"]:
+        out["roofline"] = {"bound": "hbm", "kernel": "k_bsr_fwd<fp32 blocks, fp64 vectors, bs=27, expanded> "
+                                                     "(fine-level SAI_1 B apply)",
+                           "achieved": b["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": b["gbs"] / HBM_PEAK_GBS, "traffic": None, "mean_ms": b["mean_ms"],
+                           "bytes_per_launch": b["bytes_per_launch"]}
+    return out
+
+
+def run_stokes_config(L, torch, args, BASE_SEED):
+    """256^2 multiphase stress-form Stokes, Q_2, viscosity 1e3 inside the disc
+    r = 0.25, velocity Dirichlet, balanced SAI_1 OO V-cycle in FP64 left GMRES
+    to ||V r|| <= 1e-10 ||V b||, FP32 storage; seeded N(0,1) body force."""
+    from ldg_inputs import mu_field, stokes_body_force
+    n, p = args.cfg4_n, 2
+    mu = mu_field(2, n, "disc", 0.25, 1e3)
+    rhs = [torch.from_numpy(stokes_body_force(2, n, 9, BASE_SEED + i)).cuda() for i in range(3)]
+    t0 = time.time()
+    sv = L.Solver(dim=2, n=n, p=p, system="stokes", gamma=1, mu=mu, smoother="sai", sai_level=1, order="OO",
+                  precision="fp32")
+    torch.cuda.synchronize()
+    setup = time.time() - t0
+    log(f"[stokes] setup {setup:.1f}s")
+    r = time_solves(L, torch, args, sv, "fp32", "stokes sai1_oo", rhs, True, setup, False, krylov="gmres",
+                    maxit=200, steps=2, warmup=1)
+    st = L.ldgmg_level_storage(sv.handle, 0)
+    nker = L.ldgmg_kernel(sv.handle)
+    sv.close()
+    keep = ("setup_s", "ms_per_solve", "solves_per_s", "vcycle_dof_per_s", "iters", "converged",
+            "rel_res_true_max", "eta", "p50_ms", "p99_ms")
+    out = {"workload": f"stokes2d_stress_p2_n{n}_disc1e3", "fine_dofs": sv.ndofs, "krylov": "left GMRES",
+           "smoother": "SAI_1 OO", "kernel_dim": nker, **{k: r[k] for k in keep}}
+    out["fine_storage"] = st
+    out["kernels"] = {kk: kernel_summary(r["kernels"], kk) for kk in ("A", "S", "ST", "A64")}
+    a = out["kernels"]["A"]
+    if a:
+        if a["tiled"] or a["pooled"]:
+            out["roofline"] = {"bound": "mfma" if a["tiled"] else "alu", "kernel": "fine-level A apply (bs=27)",
+                               "achieved": a["tflops"], "peak": FP64_MFMA_PEAK_TF, "unit": "TFLOP/s",
+                               "frac": a["tflops"] / FP64_MFMA_PEAK_TF, "traffic": None, "mean_ms": a["mean_ms"]}
+        else:
+            out["roofline"] = {"bound": "hbm", "kernel": "fine-level A apply (bs=27, expanded)",
+                               "achieved": a["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": a["gbs"] / HBM_PEAK_GBS, "traffic": None, "mean_ms": a["mean_ms"]}
+    return out
 
 
 def main():
@@ -315,6 +413,15 @@ def main():
                     help="mean arrivals per second of the offered replay (0: 70%% of the saturated throughput)")
     ap.add_argument("--serving-workers", type=int, default=4)
     ap.add_argument("--serving-budget-gib", type=float, default=0.0, help="0: 90%% of free HBM")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the interface (96^3) and Stokes (256^2) workloads nested in the line")
+    ap.add_argument("--cfg3-n", type=int, default=96, help="grid of the interface workload")
+    ap.add_argument("--cfg3-sai-maxit", type=int, default=30,
+                    help="CG iterations of the (non-converging) SAI_1 run of the interface workload")
+    ap.add_argument("--cfg4-n", type=int, default=256, help="grid of the Stokes workload")
+    ap.add_argument("--no-serving-replay", action="store_true",
+                    help="skip the reduced serving replay nested in the line")
+    ap.add_argument("--replay-requests", type=int, default=96, help="requests of the nested serving replay")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
@@ -357,6 +464,12 @@ def main():
     expanded = None if args.no_expanded else run_path(L, torch, args, "bf16s" if "bf16s" in paths else "fp32",
                                                       rhs, prof=True, storage="expanded")
     del rhs
+    cfg3 = cfg4 = replay = None
+    if not args.no_configs:
+        cfg3 = run_interface_config(L, torch, args, BASE_SEED)
+        cfg4 = run_stokes_config(L, torch, args, BASE_SEED)
+    if not args.no_serving_replay:
+        replay = run_serving(args, torch, nested=True)
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_n)
 
     # headline path: the fastest of FP32 / BF16-SAI storage, each with FP64 or
@@ -454,6 +567,9 @@ def main():
             frac_hbm=expanded["kernels"]["A"]["gbs"] / HBM_PEAK_GBS if expanded["kernels"]["A"]["gbs"] else None),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "interface_path": cfg3,
+        "stokes_path": cfg4,
+        "serving_replay": replay,
     }
     print(json.dumps(line), flush=True)
 
