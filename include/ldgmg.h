@@ -329,6 +329,21 @@ int ldgmg_solve_stream(ldgmg_handle h, int slots, double rtol, int maxit,
 int ldgmg_vcycle_batch(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batched V-cycle as ldgmg_vcycle_batch (same kernels, same results), with
+ * its per-level batch vectors taken from a static device array of 128 MiB
+ * that the library holds on each GPU until the process ends, instead of the
+ * handle's batch workspace (which ldgmg_vcycle_batch allocates on its first
+ * call).  Allocates nothing: no hipMalloc / hipFree, no allocator callback.
+ * Needs 4 k sum_l N_l doubles (N_l the unknowns of level l), at most 16M;
+ * larger requests fail with LDGMG_EINVAL.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other streams, other handles, other
+ * threads) race and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero (every vector is written before it is read). */
+int ldgmg_vcycle_batch_noalloc(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k,
+                               void* stream);
+
 /* Single operations of the V-cycle on one level, for checking each kernel.
  * in1/in2/out are device FP64 vectors of the level (ne*bs entries; the
  * coarse vector of RESTRICT / PROLONG_ADD has the next level's size).

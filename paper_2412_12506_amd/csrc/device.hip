@@ -12,11 +12,18 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ldgmg.h"
 #include "host.hpp"
 #include "launch.hpp"
+
+// Scratch for ldgmg_vcycle_batch_noalloc: 16M doubles (128 MiB) of device
+// memory that each GPU holds from module load to process end; host code
+// reaches it only through the address hipGetSymbolAddress gives per device.
+constexpr long long kScratchDoubles = 16ll << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace ldgmg {
 
@@ -1688,6 +1695,53 @@ int solve_cg_stream(ldgmg_hier* h, int slots, double rtol, int maxit,
   return worst;
 }
 
+// device address of `scratch` on the current device, looked up once per device
+double* scratch_address() {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<int>(addr.size()) <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = p;
+  }
+  return static_cast<double*>(addr[dev]);
+}
+
+// k V-cycles with the batch level vectors (x, b, r, t of k vectors per level)
+// in the caller-given workspace ws; the handle's own batch vectors are not
+// touched.  Every workspace vector is written before it is read.
+void vcycle_batch_in(const Ctx& c, const double* const* b, double* const* x, int k, double* ws) {
+  DevHier& D = c.D;
+  std::vector<DevHier::BatchLevel> mine(D.L.size());
+  size_t off = 0;
+  for (size_t l = 0; l < D.L.size(); ++l) {
+    const size_t n = static_cast<size_t>(D.L[l].N) * k;
+    mine[l].x = ws + off;
+    mine[l].b = ws + off + n;
+    mine[l].r = ws + off + 2 * n;
+    mine[l].t = ws + off + 3 * n;
+    off += 4 * n;
+  }
+  std::swap(D.BL, mine);
+  struct Restore {   // the handle's batch vectors come back whatever happens
+    DevHier& D;
+    std::vector<DevHier::BatchLevel>& v;
+    ~Restore() { std::swap(D.BL, v); }
+  } restore{D, mine};
+  const long long N = D.L[0].N;
+  for (int q = 0; q < k; ++q)
+    HIPCHK(hipMemcpyAsync(D.BL[0].b + q * N, b[q], N * 8, hipMemcpyDeviceToDevice, c.st));
+  if (D.prec == LDGMG_FP64) vcycle_level_multi<double, double>(c, 0, k);
+  else if (D.prec == LDGMG_BF16S) vcycle_level_multi<float, bf16s>(c, 0, k);
+  else vcycle_level_multi<float, float>(c, 0, k);
+  for (int q = 0; q < k; ++q)
+    HIPCHK(hipMemcpyAsync(x[q], D.BL[0].x + q * N, N * 8, hipMemcpyDeviceToDevice, c.st));
+}
+
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -2030,6 +2084,25 @@ int ldgmg_vcycle_batch(ldgmg_handle h, const double* const* b_dev, double* const
     vcycle64_multi(c, h->dev->br, h->dev->bz, k);
     for (int q = 0; q < k; ++q)
       HIPCHK(hipMemcpyAsync(x_dev[q], h->dev->bz + q * N, N * 8, hipMemcpyDeviceToDevice, c.st));
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_vcycle_batch_noalloc(ldgmg_handle h, const double* const* b_dev, double* const* x_dev, int k,
+                               void* stream) {
+  return guarded([&] {
+    need_dev(h);
+    if (!b_dev || !x_dev || k < 1 || k > kMaxRhs) throw std::invalid_argument("bad batch arguments");
+    for (int q = 0; q < k; ++q)
+      if (!b_dev[q] || !x_dev[q]) throw std::invalid_argument("null vector in batch");
+    long long need = 0;
+    for (const DevLevel& L : h->dev->L) need += 4 * L.N * k;
+    if (need > kScratchDoubles)
+      throw std::invalid_argument("ldgmg_vcycle_batch_noalloc: " + std::to_string(k) + " right-hand sides need " +
+                                  std::to_string(need * 8) + " bytes of scratch, more than its " +
+                                  std::to_string(kScratchDoubles * 8) + " bytes");
+    Ctx c{*h->host, *h->dev, static_cast<hipStream_t>(stream)};
+    vcycle_batch_in(c, b_dev, x_dev, k, scratch_address());
     return LDGMG_OK;
   });
 }

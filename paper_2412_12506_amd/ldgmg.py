@@ -108,7 +108,7 @@ SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", 
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
            "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_fp32_products", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage",
-           "ldgmg_rhs_check", "ldgmg_kernel", "ldgmg_solve_stream", "ldgmg_destroy",
+           "ldgmg_rhs_check", "ldgmg_kernel", "ldgmg_solve_stream", "ldgmg_vcycle_batch_noalloc", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -141,6 +141,7 @@ def lib():
     L.ldgmg_solve_stream.argtypes = [H, C.c_int, C.c_double, C.c_int, NEXT_FN, DONE_FN, vp, vp]
     L.ldgmg_kernel.argtypes = [H, ip, dp]
     L.ldgmg_vcycle_batch.argtypes = [H, C.POINTER(vp), C.POINTER(vp), C.c_int, vp]
+    L.ldgmg_vcycle_batch_noalloc.argtypes = [H, C.POINTER(vp), C.POINTER(vp), C.c_int, vp]
     L.ldgmg_export.argtypes = [H, C.c_int, C.c_int, ip, ip, dp, ip, ip]
     L.ldgmg_export_colours.argtypes = [H, C.c_int, ip]
     L.ldgmg_setup_stats.argtypes = [H, C.c_int, ip, dp]
@@ -403,6 +404,11 @@ def ldgmg_kernel(h: int, with_vectors: bool = False):
 
 def ldgmg_vcycle_batch(h: int, bs, xs, stream=None):
     _check(lib().ldgmg_vcycle_batch(h, _ptr_array(bs), _ptr_array(xs), len(bs), _stream(stream, *bs)))
+
+
+def ldgmg_vcycle_batch_noalloc(h: int, bs, xs, stream=None):
+    """ldgmg_vcycle_batch with the library's static scratch array (no allocation)."""
+    _check(lib().ldgmg_vcycle_batch_noalloc(h, _ptr_array(bs), _ptr_array(xs), len(bs), _stream(stream, *bs)))
 
 
 def ldgmg_level_op(h: int, level: int, op: str, in1, in2, out, stream=None):
