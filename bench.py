@@ -387,6 +387,48 @@ def run_stokes_config(L, torch, args, BASE_SEED):
     return out
 
 
+def run_batched(L, torch, args, BASE_SEED):
+    """Batched CG of K right-hand sides on one hierarchy (the serving step):
+    3D Poisson Q_p on n^3, SAI_1 OI, BF16-SAI tiled storage (the batched
+    products on the matrix cores, (row, right-hand side) pairs as MFMA
+    columns), FP64 products.  One JSON line: V-cycle DOF/s over the batch,
+    ms per batch, iterations per right-hand side, and the same K right-hand
+    sides solved one at a time for comparison."""
+    from ldg_inputs import rhs_normal
+    k = args.batch_k
+    s = L.Solver(dim=3, n=args.n, p=args.p, smoother="sai", sai_level=1, order="OI", precision="bf16s",
+                 storage="tiled")
+    bs = [torch.from_numpy(rhs_normal(s.ndofs, BASE_SEED + q)).cuda() for q in range(k)]
+    xs = [torch.empty_like(b) for b in bs]
+    L.ldgmg_solve_batch(s.handle, bs, xs)                   # warm-up (allocates the batch workspace)
+    torch.cuda.synchronize()
+    times, infos = [], None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        infos = L.ldgmg_solve_batch(s.handle, bs, xs)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"[batch k={k}] {times[-1] * 1e3:.1f} ms, iters {[i['iters'] for i in infos]}")
+    single = []
+    for q in range(k):
+        t0 = time.perf_counter()
+        s.solve(bs[q], xs[q])
+        torch.cuda.synchronize()
+        single.append(time.perf_counter() - t0)
+    import numpy as np
+    t = float(np.median(times))
+    vc = sum(i["vcycles"] for i in infos)
+    line = {"metric": "batched V-cycle DOF/s (serving step)", "value": s.ndofs * vc / t, "unit": "DOF/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t * 1e3, "higher_is_better": True,
+            "dtype": "f64", "block_storage": "A f32, SAI B bf16, tiled", "data": "synthetic",
+            "config": {"workload": f"poisson3d_p{args.p}_n{args.n}_sai1_oi_cg_batch{k}", "k": k,
+                       "fine_dofs": s.ndofs},
+            "iters": [i["iters"] for i in infos], "single_solve_ms_sum": sum(single) * 1e3,
+            "speedup_vs_single": sum(single) / t}
+    s.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,6 +464,9 @@ def main():
     ap.add_argument("--no-serving-replay", action="store_true",
                     help="skip the reduced serving replay nested in the line")
     ap.add_argument("--replay-requests", type=int, default=96, help="requests of the nested serving replay")
+    ap.add_argument("--batch-k", type=int, default=0, metavar="K",
+                    help="only time batched CG (ldgmg_solve_batch) of K right-hand sides on the --n / --p "
+                         "Poisson workload, BF16-SAI tiled storage (a separate JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
@@ -447,6 +492,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.serving:
         run_serving(args, torch)
+        return
+    if args.batch_k:
+        run_batched(L, torch, args, BASE_SEED)
         return
     ndofs = args.n ** 3 * (args.p + 1) ** 3
     nrhs = args.warmup + args.steps

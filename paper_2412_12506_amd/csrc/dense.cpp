@@ -534,7 +534,10 @@ void sym_eig(int n, const double* Ain, double* w, double* Vout, int nthreads) {
       }
     }
   });
-  // 3. implicit QL iterations with shifts on (d, e), recording the rotations
+  // 3. implicit QL iterations with Wilkinson-type shifts on (d, e), recording
+  //    the rotations: the published tql2 procedure of Bowdler, Martin, Reinsch
+  //    and Wilkinson (Handbook for Automatic Computation II, 1971) in its
+  //    textbook form
   std::vector<Rotation> rot;
   for (int l = 0; l < n; ++l) {
     int iter = 0;

@@ -38,10 +38,12 @@ def test_stream_admits_while_running(storage):
         stage = [0]
         fed = []
         log = []
-        # offer 3 at once, then one more every other stage, with pauses
+        # offer 3 at once, then one more every other stage while others are in
+        # flight (with nothing in flight, nothing offered ends the call)
         def next_rhs():
             stage[0] += 1
-            if len(fed) < 3 or (stage[0] % 2 == 0 and len(fed) < nrhs):
+            in_flight = len(fed) - sum(1 for e in log if e[0] == "out")
+            if len(fed) < nrhs and (len(fed) < 3 or stage[0] % 2 == 0 or in_flight == 0):
                 q = len(fed)
                 fed.append(stage[0])
                 log.append(("in", q, len(fed) - sum(1 for e in log if e[0] == "out")))
