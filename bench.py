@@ -247,8 +247,18 @@ def run_serving(args, torch, nested=False):
     reqs = serving_requests(count=args.replay_requests if nested else args.serving_requests, **cat)
     free, total = torch.cuda.mem_get_info()
     budget = int(args.serving_budget_gib * (1 << 30)) if args.serving_budget_gib else int(free * 0.9)
-    eng = ServingEngine(budget, workers=args.serving_workers)
     keys = sorted({problem_key(r) for r in reqs})
+    setup_cmp = None
+    if nested:
+        # cache-miss cost: the host tier of the replay's keys built with the SAI
+        # least-squares problems solved on the host, then on the GPU
+        setup_cmp = {}
+        for dev in (False, True):
+            e2 = ServingEngine(budget, workers=args.serving_workers, setup_device=dev)
+            setup_cmp["gpu" if dev else "host"] = e2.prebuild(keys, threads=4)
+            e2.close()
+        log(f"[serving] host tier: SAI solves on the host {setup_cmp['host']:.1f} s, on the GPU {setup_cmp['gpu']:.1f} s")
+    eng = ServingEngine(budget, workers=args.serving_workers, setup_device=args.serving_setup_device or nested)
     log(f"[serving] {len(reqs)} requests, {len(keys)} hierarchies, budget {budget / 2**30:.1f} GiB")
     setup_s = eng.prebuild(keys, threads=4)
     log(f"[serving] host tier built in {setup_s:.1f} s")
@@ -295,10 +305,11 @@ def run_serving(args, torch, nested=False):
                    "workers": args.serving_workers, "hbm_budget_gib": budget / 2 ** 30},
         "p50_ms": out["offered"]["p50_ms"], "p99_ms": out["offered"]["p99_ms"],
         "offered": out["offered"], "saturated": sat, "host_setup_s": setup_s,
+        "host_tier_build_s": setup_cmp,
     }
     if nested:
         return {k: line[k] for k in ("value", "unit", "config", "p50_ms", "p99_ms", "offered", "saturated",
-                                     "host_setup_s")}
+                                     "host_setup_s", "host_tier_build_s")}
     print(json.dumps(line), flush=True)
 
 
@@ -455,6 +466,8 @@ def main():
                     help="mean arrivals per second of the offered replay (0: 70%% of the saturated throughput)")
     ap.add_argument("--serving-workers", type=int, default=4)
     ap.add_argument("--serving-budget-gib", type=float, default=0.0, help="0: 90%% of free HBM")
+    ap.add_argument("--serving-setup-device", action="store_true",
+                    help="solve the SAI least-squares problems of cache misses on the GPU")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the interface (96^3) and Stokes (256^2) workloads nested in the line")
     ap.add_argument("--cfg3-n", type=int, default=96, help="grid of the interface workload")

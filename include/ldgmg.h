@@ -114,6 +114,14 @@ typedef struct {
    * all 1; read during setup only.  Stokes only (EINVAL otherwise). */
   const double* rho;
   double delta;
+  /* Where the setup solves the balanced SAI least-squares problems (Section
+   * 2.3.3; its cache of identical problems, Section 4): 0 (default) on the
+   * host; 1 on the current HIP device, in FP64, batched by shape (normal
+   * equations with one refinement step, rocBLAS / rocSOLVER), the host taking
+   * any problem the device declines (failed Cholesky, non-finite solution,
+   * refinement step above 1e-8 of the solution).  With 1, ldgmg_setup_host
+   * and ldgmg_rebuild_smoother need a GPU. */
+  int setup_device;
   /* Device memory of the handle.  NULL (the default): hipMalloc / hipFree.
    * Otherwise every device buffer the handle owns (what ldgmg_upload
    * allocates, its temporary upload buffers, and the batch and GMRES
@@ -380,8 +388,15 @@ int ldgmg_export(ldgmg_handle h, int level, int what, int* row_ptr, int* col,
 int ldgmg_export_colours(ldgmg_handle h, int level, int* colours);
 
 /* Setup statistics: unique SAI least-squares problems solved on the level and
- * the host setup time in seconds. */
+ * the level's setup time in seconds (with setup_device = 1, the problems that
+ * the device solved are reported by ldgmg_setup_stats_device). */
 int ldgmg_setup_stats(ldgmg_handle h, int level, int* sai_unique, double* seconds);
+
+/* Unique SAI least-squares problems of the level solved on the device
+ * (setup_device = 1) and by Householder QR on the host (declined by the
+ * normal equations), and the seconds the level's SAI least-squares solves
+ * took (device and host together). */
+int ldgmg_setup_stats_device(ldgmg_handle h, int level, int* sai_device, int* sai_qr, double* sai_seconds);
 
 /* Kernel timing of the fine level (diagnostics, for roofline measurements).
  * While enabled, every block-sparse launch on level 0 is bracketed by HIP

@@ -24,7 +24,7 @@ CXX = shutil.which("g++") or "g++"
 ARCH = os.environ.get("LDGMG_ARCH", "gfx950")
 
 HOST_SOURCES = ["host.cpp", "dense.cpp"]
-HIP_SOURCES = ["kernels.hip", "device.hip"]
+HIP_SOURCES = ["kernels.hip", "device.hip", "setup.hip"]
 
 CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3", "-Wall", "-Wextra"]
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -55,7 +55,8 @@ def build(verbose: bool = False) -> str:
                 print(out)
     objs = [os.path.join(BUILD, s + ".o") for s in HOST_SOURCES + HIP_SOURCES]
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread",
+          f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"])
     os.replace(tmp, LIB)
     return LIB
 

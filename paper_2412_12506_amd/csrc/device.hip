@@ -18,6 +18,7 @@
 #include "../../include/ldgmg.h"
 #include "host.hpp"
 #include "launch.hpp"
+#include "setup.hpp"
 
 // Scratch for ldgmg_vcycle_batch_noalloc: 16M doubles (128 MiB) of device
 // memory that each GPU holds from module load to process end; host code
@@ -1817,6 +1818,7 @@ int ldgmg_problem_default(ldgmg_problem* p) {
   p->storage = LDGMG_STORE_AUTO;
   p->rho = nullptr;
   p->delta = 0.0;
+  p->setup_device = 0;
   p->dev_alloc = nullptr;
   p->dev_free = nullptr;
   p->alloc_ctx = nullptr;
@@ -1863,7 +1865,12 @@ int ldgmg_setup_host(const ldgmg_problem* p, ldgmg_handle* out) {
     if (!p || !out) throw std::invalid_argument("null argument");
     *out = nullptr;
     auto h = std::make_unique<ldgmg_hier>();
-    h->host = build_host(*p);
+    if (p->setup_device) {
+      const SaiBatchSolver gpu = gpu_sai_solve;
+      h->host = build_host(*p, &gpu);
+    } else {
+      h->host = build_host(*p);
+    }
     *out = h.release();
     return LDGMG_OK;
   });
@@ -1874,7 +1881,12 @@ int ldgmg_rebuild_smoother(ldgmg_handle src, const ldgmg_problem* p, ldgmg_handl
     if (!src || !src->host || !p || !out) throw std::invalid_argument("null argument");
     *out = nullptr;
     auto h = std::make_unique<ldgmg_hier>();
-    h->host = rebuild_smoother(*src->host, *p);
+    if (p->setup_device) {
+      const SaiBatchSolver gpu = gpu_sai_solve;
+      h->host = rebuild_smoother(*src->host, *p, &gpu);
+    } else {
+      h->host = rebuild_smoother(*src->host, *p);
+    }
     *out = h.release();
     return LDGMG_OK;
   });
@@ -2240,6 +2252,17 @@ int ldgmg_setup_stats(ldgmg_handle h, int level, int* sai_unique, double* second
     const HostLevel& L = h->host->levels[level];
     if (sai_unique) *sai_unique = L.sai_unique;
     if (seconds) *seconds = L.setup_seconds;
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_setup_stats_device(ldgmg_handle h, int level, int* sai_device, int* sai_qr, double* sai_seconds) {
+  return guarded([&] {
+    check_level(h, level);
+    const HostLevel& L = h->host->levels[level];
+    if (sai_device) *sai_device = L.sai_device;
+    if (sai_qr) *sai_qr = L.sai_qr;
+    if (sai_seconds) *sai_seconds = L.sai_seconds;
     return LDGMG_OK;
   });
 }

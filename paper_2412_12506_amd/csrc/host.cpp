@@ -331,6 +331,7 @@ void validate_problem(const ldgmg_problem& p) {
   if ((p.dev_alloc == nullptr) != (p.dev_free == nullptr))
     throw std::invalid_argument("dev_alloc and dev_free must be given together");
   if (!(p.delta >= 0) || !std::isfinite(p.delta)) throw std::invalid_argument("delta must be finite and >= 0");
+  if (p.setup_device != 0 && p.setup_device != 1) throw std::invalid_argument("setup_device must be 0 or 1");
   if (p.delta > 0 && p.system != LDGMG_STOKES) throw std::invalid_argument("the density term is for Stokes");
   for (int k = 0; k < p.dim; ++k) {
     const int a = p.bc[2 * k], b = p.bc[2 * k + 1];
@@ -857,7 +858,7 @@ std::vector<std::vector<int>> pattern_rows(const PMat& A, int ell) {
   return P;
 }
 
-void build_sai(HostLevel& L, int ell, int system, double zeta) {
+void build_sai(HostLevel& L, int ell, int system, double zeta, const SaiBatchSolver* sai) {
   const int bs = L.bs, ne = L.ne;
   const PMat& A = L.A;
   const std::vector<int> did = diag_ids(A);
@@ -899,10 +900,49 @@ void build_sai(HostLevel& L, int ell, int system, double zeta) {
   keys.shrink_to_fit();
   L.sai_unique = static_cast<int>(rep.size());
   // solve the representative problems: X = argmin || A~[I,J] X - E[I,i] ||
+  const auto t_ls = std::chrono::steady_clock::now();
   std::vector<Vec> sol(rep.size());
+  std::vector<char> solved(rep.size(), 0);
+  if (sai && !rep.empty()) {   // the batch solver first (e.g. on the GPU); the host takes what it declines
+    SaiBatch batch;
+    batch.bs = bs;
+    batch.pool = A.pool.data.data();
+    batch.npool = A.pool.size();
+    std::vector<double> al(alpha.size() * static_cast<size_t>(bs));
+    for (size_t d = 0; d < alpha.size(); ++d)
+      if (alpha[d].size() == static_cast<size_t>(bs)) std::copy(alpha[d].begin(), alpha[d].end(), al.begin() + d * bs);
+    batch.alpha = al.data();
+    batch.nalpha = static_cast<int>(alpha.size());
+    batch.probs.resize(rep.size());
+    parallel_for(static_cast<int>(rep.size()), [&](int u) {
+      const int i = rep[u];
+      const auto& I = Isets[i];
+      const auto& Jc = J[i];
+      SaiProblem& pb = batch.probs[u];
+      pb.mb = static_cast<int>(I.size());
+      pb.nb = static_cast<int>(Jc.size());
+      pb.pos = static_cast<int>(std::lower_bound(I.begin(), I.end(), i) - I.begin());
+      for (size_t a = 0; a < I.size(); ++a)
+        for (size_t b = 0; b < Jc.size(); ++b) {
+          const int s = A.slot(I[a], Jc[b]);
+          if (s < 0) continue;
+          pb.brow.push_back(static_cast<int>(a));
+          pb.bcol.push_back(static_cast<int>(b));
+          pb.bid.push_back(A.id[s]);
+          pb.arow.push_back(did[I[a]]);
+          pb.acol.push_back(did[Jc[b]]);
+        }
+      sol[u].assign(static_cast<size_t>(pb.nb) * bs * bs, 0.0);
+      pb.X = sol[u].data();
+    });
+    const std::vector<char> ok = (*sai)(batch);
+    for (size_t u = 0; u < rep.size() && u < ok.size(); ++u) solved[u] = ok[u];
+    L.sai_device = static_cast<int>(std::count(solved.begin(), solved.end(), 1));
+  }
   std::atomic<bool> singular{false};
   std::atomic<int> qr_fallback{0};
   parallel_for(static_cast<int>(rep.size()), [&](int u) {
+    if (solved[u]) return;
     const int i = rep[u];
     const auto& I = Isets[i];
     const auto& Jc = J[i];
@@ -957,6 +997,7 @@ void build_sai(HostLevel& L, int ell, int system, double zeta) {
   });
   if (singular) throw std::runtime_error("rank-deficient SAI least-squares problem");
   L.sai_qr = qr_fallback.load();
+  L.sai_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_ls).count();
   // B(j, i) = diag(alpha_j) X_b diag(alpha_i), stored row-wise with the pattern of A^ell
   std::vector<std::vector<std::pair<int, std::string>>> rows(ne);   // row j: (col i, key)
   for (int i = 0; i < ne; ++i)
@@ -1027,9 +1068,9 @@ void build_bottom(HostLevel& L) {
 namespace {
 
 // smoother of one non-bottom level from its assembled A (Sections 2.3, 3.3)
-void build_smoother(HostLevel& L, const ldgmg_problem& pr, double zeta) {
+void build_smoother(HostLevel& L, const ldgmg_problem& pr, double zeta, const SaiBatchSolver* sai) {
   if (pr.smoother == LDGMG_SMOOTH_SAI) {
-    build_sai(L, pr.sai_level, pr.system, zeta);
+    build_sai(L, pr.sai_level, pr.system, zeta, sai);
   } else {
     build_block_inverse(L);
     if (pr.smoother == LDGMG_SMOOTH_GS) build_colours(L);
@@ -1049,7 +1090,8 @@ double default_zeta(const ldgmg_problem& pr) {
 
 }  // namespace
 
-std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const ldgmg_problem& pr) {
+std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const ldgmg_problem& pr,
+                                               const SaiBatchSolver* sai) {
   validate_problem(pr);
   const ldgmg_problem& q = src.prob;
   bool same = pr.dim == q.dim && pr.n == q.n && pr.p == q.p && pr.basis == q.basis && pr.system == q.system &&
@@ -1083,15 +1125,16 @@ std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const 
     L.tpos.clear();
     L.colour_rows.clear();
     L.ncolours = 0;
-    L.sai_unique = L.sai_qr = 0;
-    build_smoother(L, pr, H->zeta);
+    L.sai_unique = L.sai_qr = L.sai_device = 0;
+    L.sai_seconds = 0;
+    build_smoother(L, pr, H->zeta, sai);
     L.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
   }
   H->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return H;
 }
 
-std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
+std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr, const SaiBatchSolver* sai) {
   validate_problem(pr);
   const auto t0 = std::chrono::steady_clock::now();
   g_threads = pr.nthreads > 0 ? pr.nthreads : std::max(1u, std::thread::hardware_concurrency());
@@ -1165,7 +1208,7 @@ std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& pr) {
     if (bottom) {
       build_bottom(L);
     } else {
-      build_smoother(L, pr, H->zeta);
+      build_smoother(L, pr, H->zeta, sai);
     }
     L.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
   }

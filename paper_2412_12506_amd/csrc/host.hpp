@@ -9,6 +9,7 @@
 #pragma once
 
 #include <array>
+#include <functional>
 #include <cstdint>
 #include <memory>
 #include <string>
@@ -84,6 +85,8 @@ struct HostLevel {
   std::vector<double> pinv;    // bottom pseudo-inverse, dense (ne*bs)^2
   int sai_unique = 0;
   int sai_qr = 0;               // of those, solved by Householder QR (normal equations declined)
+  int sai_device = 0;           // of those, solved by the batch solver (GPU setup)
+  double sai_seconds = 0;       // time of the level's SAI least-squares solves
   double setup_seconds = 0;
 };
 
@@ -96,14 +99,39 @@ struct HostHierarchy {
   double setup_seconds = 0;
 };
 
-// Throws std::runtime_error / std::invalid_argument on failure.
-std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& prob);
+// One balanced SAI least-squares problem of a representative column (Section
+// 2.3.3): min || C X - E ||_F with C = A~[I, J], mb x nb blocks of bs x bs given
+// by its nonzero blocks, and E the identity block at block row pos.  X is
+// (nb bs) x bs, column-major.
+// Block (a, b) of C is diag(alpha[arow]) A_pool[bid] diag(alpha[acol]).
+struct SaiProblem {
+  int mb = 0, nb = 0, pos = 0;
+  std::vector<int> brow, bcol;       // block coordinates of the nonzero blocks of C
+  std::vector<int> bid, arow, acol;  // their pool block of A and balancing vectors
+  double* X = nullptr;               // the solution (filled by the solver)
+};
+struct SaiBatch {
+  int bs = 0;
+  const double* pool = nullptr;      // A's distinct blocks, row-major bs x bs each
+  int npool = 0;
+  const double* alpha = nullptr;     // balancing vectors, bs each
+  int nalpha = 0;
+  std::vector<SaiProblem> probs;
+};
+// Solves a batch of SAI problems (e.g. on a GPU); returns, per problem,
+// whether its X was written (the host solves the others).
+using SaiBatchSolver = std::function<std::vector<char>(SaiBatch& batch)>;
+
+// Throws std::runtime_error / std::invalid_argument on failure.  With `sai`,
+// the SAI least-squares problems of every level go to that solver first.
+std::unique_ptr<HostHierarchy> build_host(const ldgmg_problem& prob, const SaiBatchSolver* sai = nullptr);
 
 // A hierarchy for prob that keeps src's operators, transfers and bottom
 // pseudo-inverse and builds only the smoother of prob; prob must describe the
 // same discrete problem as src (geometry, basis, system, penalties and the same
 // viscosity values), else std::invalid_argument.
-std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const ldgmg_problem& prob);
+std::unique_ptr<HostHierarchy> rebuild_smoother(const HostHierarchy& src, const ldgmg_problem& prob,
+                                               const SaiBatchSolver* sai = nullptr);
 
 // q-point Gauss-Legendre rule on [-1, 1] (ascending nodes)
 void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w);

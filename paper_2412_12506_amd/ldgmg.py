@@ -40,6 +40,7 @@ class Problem(C.Structure):
                 ("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("zeta", C.c_double),
                 ("precision", C.c_int), ("nthreads", C.c_int), ("hbm_budget", C.c_size_t),
                 ("storage", C.c_int), ("rho", C.POINTER(C.c_double)), ("delta", C.c_double),
+                ("setup_device", C.c_int),
                 ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
                 ("alloc_ctx", C.c_void_p)]
 
@@ -108,7 +109,8 @@ SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", 
            "ldgmg_setup", "ldgmg_sizes", "ldgmg_level_info", "ldgmg_rhs_volume", "ldgmg_vcycle",
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
            "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_fp32_products", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage",
-           "ldgmg_rhs_check", "ldgmg_kernel", "ldgmg_solve_stream", "ldgmg_vcycle_batch_noalloc", "ldgmg_destroy",
+           "ldgmg_rhs_check", "ldgmg_kernel", "ldgmg_solve_stream", "ldgmg_vcycle_batch_noalloc",
+           "ldgmg_setup_stats_device", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -145,6 +147,7 @@ def lib():
     L.ldgmg_export.argtypes = [H, C.c_int, C.c_int, ip, ip, dp, ip, ip]
     L.ldgmg_export_colours.argtypes = [H, C.c_int, ip]
     L.ldgmg_setup_stats.argtypes = [H, C.c_int, ip, dp]
+    L.ldgmg_setup_stats_device.argtypes = [H, C.c_int, ip, ip, dp]
     L.ldgmg_profile.argtypes = [H, C.c_int]
     L.ldgmg_profile_read.argtypes = [H, C.c_int, ip, dp]
     L.ldgmg_unload.argtypes = [H]
@@ -203,7 +206,7 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
                  smoother: str = "sai", sai_level: int = 1, order: str = "OI", nu1: int = 3,
                  nu2: int = 3, omega: float = 0.0, zeta: float = 0.0, precision: str = "fp32",
                  nthreads: int = 0, hbm_budget: int = 0, storage: str = "auto", allocator=None,
-                 rho=None, delta: float = 0.0):
+                 rho=None, delta: float = 0.0, setup_device: bool = False):
     """Problem struct plus the numpy array that backs `mu` (keep both alive).
     allocator: None (hipMalloc) or an object with install(problem), such as
     TorchAllocator (keep it alive as long as the handle)."""
@@ -232,6 +235,7 @@ def make_problem(dim: int, n: int, p: int, system: str = "poisson", basis: str =
     pr.hbm_budget = hbm_budget
     pr.storage = STORAGE[storage]
     pr.delta = delta
+    pr.setup_device = 1 if setup_device else 0
     if rho is not None:
         rho_arr = np.ascontiguousarray(rho, dtype=np.float64)
         if rho_arr.size != n ** dim:
@@ -451,6 +455,13 @@ def ldgmg_setup_stats(h: int, level: int):
     u, s = C.c_int(), C.c_double()
     _check(lib().ldgmg_setup_stats(h, level, C.byref(u), C.byref(s)))
     return u.value, s.value
+
+
+def ldgmg_setup_stats_device(h: int, level: int):
+    """(SAI problems solved on the device, by host QR, seconds of the level's SAI solves)."""
+    d, q, t = C.c_int(), C.c_int(), C.c_double()
+    _check(lib().ldgmg_setup_stats_device(h, level, C.byref(d), C.byref(q), C.byref(t)))
+    return d.value, q.value, t.value
 
 
 PROFILE_KIND = {"A": 0, "S": 1, "ST": 2, "A64": 3, "FUSED": 4}

@@ -58,14 +58,14 @@ def problem_key(req) -> tuple:
     return (req.dim, req.n, req.p, float(req.contrast))
 
 
-def problem_kwargs(key, precision="fp32", smoother="sai"):
+def problem_kwargs(key, precision="fp32", smoother="sai", setup_device=False):
     from ldg_inputs import mu_box
     dim, n, p, contrast = key
     mu = None if contrast == 1.0 else mu_box(dim, n, contrast)
     if smoother != "sai" and precision == "bf16s":     # BF16 storage is for the SAI matrices
         precision = "fp32"
     return dict(dim=dim, n=n, p=p, mu=mu, smoother=smoother, sai_level=1, order="OI",
-                precision=precision)
+                precision=precision, setup_device=setup_device)
 
 
 def batch_workspace_bytes(ndofs_fine: int, dim: int, max_batch: int = 8) -> int:
@@ -122,7 +122,7 @@ class Result:
 class ServingEngine:
     def __init__(self, hbm_budget: int, workers: int = 4, max_batch: int = 8, precision: str = "bf16s",
                  smoother: str = "sai", rtol: float = 1e-10, maxit: int = 200, keep_solutions: bool = False,
-                 setup_threads: int = 0, allocator: str = "torch"):
+                 setup_threads: int = 0, allocator: str = "torch", setup_device: bool = False):
         import torch
         self.torch = torch
         self.budget = int(hbm_budget)
@@ -135,6 +135,8 @@ class ServingEngine:
         # eviction hands memory back without a device-wide synchronisation);
         # "hip": the library's own hipMalloc / hipFree
         self.allocator = allocator
+        # cache misses solve their SAI least-squares problems on the GPU (setup_device)
+        self.setup_device = setup_device
         # host setup threads per worker: the host's share of cores split over the workers
         self.setup_threads = setup_threads or max(1, min(16, os.cpu_count() or 1) // workers)
         self.entries: "OrderedDict[tuple, Entry]" = OrderedDict()   # LRU order of use
@@ -164,7 +166,7 @@ class ServingEngine:
         ts = time.perf_counter()
         with self.cv:
             smoother = self._entry(key).smoother
-        kw = problem_kwargs(key, self.precision, smoother)
+        kw = problem_kwargs(key, self.precision, smoother, self.setup_device)
         solver = L.Solver(host_only=True, nthreads=self.setup_threads, allocator=self._new_allocator(), **kw)
         L.ldgmg_cg_guard(solver.handle, True)     # fail fast when the V-cycle is not SPD
         with self.cv:
@@ -336,7 +338,7 @@ class ServingEngine:
             self.fallback_keys.append(key)
         try:
             new = old.resmoothed(nthreads=self.setup_threads, allocator=self._new_allocator(),
-                                 **problem_kwargs(key, self.precision, "gs"))
+                                 **problem_kwargs(key, self.precision, "gs", self.setup_device))
             L.ldgmg_cg_guard(new.handle, True)
         except Exception as ex:
             with self.cv:
