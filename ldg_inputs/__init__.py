@@ -136,6 +136,16 @@ def rhs_normal(ndofs: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(ndofs)
 
 
+def rhs_normal_device(ndofs: int, seed: int, device="cuda"):
+    """Seeded N(0,1) coefficients, float64, drawn by torch's generator on
+    `device` (a request's right-hand side already resident in device memory;
+    not the same numbers as rhs_normal)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn(ndofs, generator=g, device=device, dtype=torch.float64)
+
+
 def rhs_uniform(ndofs: int, seed: int) -> np.ndarray:
     """Seeded U[-1,1] coefficients (the distribution the paper draws from)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, ndofs)

@@ -5,6 +5,7 @@
 #include "launch.hpp"
 
 #include <stdexcept>
+#include <cstdint>
 #include <type_traits>
 #include <string>
 
@@ -455,6 +456,48 @@ __device__ __forceinline__ v4f mfma_step(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// the KS operands of the x block at xp for k lane kq (zero when !use), in the
+// k mapping of the pool layout
+template <int BS, int KS, bool QUAD, typename XT, typename OP>
+__device__ __forceinline__ void load_x(const XT* xp, int kq, bool use, OP (&xb)[KS]) {
+  if constexpr (QUAD && std::is_same<XT, float>::value) {   // steps 4j..4j+3: one 16-byte load
+    const float4* x4 = reinterpret_cast<const float4*>(xp + 4 * kq);
+#pragma unroll
+    for (int j = 0; j < KS / 4; ++j) {
+      const float4 v = x4[4 * j];
+      xb[4 * j] = use ? v.x : OP(0);
+      xb[4 * j + 1] = use ? v.y : OP(0);
+      xb[4 * j + 2] = use ? v.z : OP(0);
+      xb[4 * j + 3] = use ? v.w : OP(0);
+    }
+  } else if constexpr (QUAD) {   // steps 4j..4j+3: columns 16j + 4 kq + {0..3}, two 16-byte loads
+    const double2* x2 = reinterpret_cast<const double2*>(xp + 4 * kq);
+#pragma unroll
+    for (int j = 0; j < KS / 4; ++j) {
+      const double2 v0 = x2[8 * j], v1 = x2[8 * j + 1];
+      xb[4 * j] = use ? static_cast<OP>(v0.x) : OP(0);
+      xb[4 * j + 1] = use ? static_cast<OP>(v0.y) : OP(0);
+      xb[4 * j + 2] = use ? static_cast<OP>(v1.x) : OP(0);
+      xb[4 * j + 3] = use ? static_cast<OP>(v1.y) : OP(0);
+    }
+  } else if constexpr (BS % 8 == 0) {    // steps 2j, 2j+1: columns 8j + 2 kq + {0, 1}, one 16-byte load
+    const double2* x2 = reinterpret_cast<const double2*>(xp + 2 * kq);
+#pragma unroll
+    for (int q = 0; q < KS / 2; ++q) {
+      const double2 v = x2[4 * q];
+      xb[2 * q] = use ? static_cast<OP>(v.x) : OP(0);
+      xb[2 * q + 1] = use ? static_cast<OP>(v.y) : OP(0);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int c = tile_k(BS, KS, s, kq, QUAD);
+      const double v = xp[c < BS ? c : 0];
+      xb[s] = (use && c < BS) ? static_cast<OP>(v) : OP(0);
+    }
+  }
+}
+
 // P32: FP32 products (operands rounded to FP32: the stored FP32 / BF16 entries
 // exactly, the vector entries to nearest) accumulated in FP32; the result is
 // combined with z in FP64.  XT / OT: element type of x / out; FP32 x (already
@@ -487,14 +530,13 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   const int q = col & ((1 << LKP) - 1);     // right-hand side of this column
   const bool rv = e0 + (col >> LKP) < nrows && q < nk;
   const int row = perm[rv ? e0 + (col >> LKP) : e0];
-  const int rowc = row;
   const size_t qoff = static_cast<size_t>(rv ? q : 0) * stride;
   ACC acc[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) acc[m] = ACC{0, 0, 0, 0};
   for (int d = 0; d < noff; ++d) {
     const int o = off[d];
-    const int t = tab[static_cast<size_t>(rowc) * noff + d];
+    const int t = tab[static_cast<size_t>(row) * noff + d];
     const int myid = rv ? t : -1;
     unsigned long long rem = __ballot(myid >= 0) & 0xFFFFull;
     while (rem) {                           // one MFMA pass per distinct block of this offset
@@ -502,44 +544,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const int id = __shfl(myid, c0);
       const unsigned long long sel = __ballot(myid == id) & 0xFFFFull;
       const bool use = (sel >> col) & 1ull;
-      const XT* xp = x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0);
       OP xb[KS];
-      if constexpr (QUAD && std::is_same<XT, float>::value) {   // steps 4j..4j+3: one 16-byte load
-        const float4* x4 = reinterpret_cast<const float4*>(xp + 4 * kq);
-#pragma unroll
-        for (int j = 0; j < KS / 4; ++j) {
-          const float4 v = x4[4 * j];
-          xb[4 * j] = use ? v.x : OP(0);
-          xb[4 * j + 1] = use ? v.y : OP(0);
-          xb[4 * j + 2] = use ? v.z : OP(0);
-          xb[4 * j + 3] = use ? v.w : OP(0);
-        }
-      } else if constexpr (QUAD) {   // steps 4j..4j+3: columns 16j + 4 kq + {0..3}, two 16-byte loads
-        const double2* x2 = reinterpret_cast<const double2*>(xp + 4 * kq);
-#pragma unroll
-        for (int j = 0; j < KS / 4; ++j) {
-          const double2 v0 = x2[8 * j], v1 = x2[8 * j + 1];
-          xb[4 * j] = use ? static_cast<OP>(v0.x) : OP(0);
-          xb[4 * j + 1] = use ? static_cast<OP>(v0.y) : OP(0);
-          xb[4 * j + 2] = use ? static_cast<OP>(v1.x) : OP(0);
-          xb[4 * j + 3] = use ? static_cast<OP>(v1.y) : OP(0);
-        }
-      } else if constexpr (BS % 8 == 0) {    // steps 2j, 2j+1: columns 8j + 2 kq + {0, 1}, one 16-byte load
-        const double2* x2 = reinterpret_cast<const double2*>(xp + 2 * kq);
-#pragma unroll
-        for (int q = 0; q < KS / 2; ++q) {
-          const double2 v = x2[4 * q];
-          xb[2 * q] = use ? static_cast<OP>(v.x) : OP(0);
-          xb[2 * q + 1] = use ? static_cast<OP>(v.y) : OP(0);
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const int c = tile_k(BS, KS, s, kq, QUAD);
-          const double v = xp[c < BS ? c : 0];
-          xb[s] = (use && c < BS) ? static_cast<OP>(v) : OP(0);
-        }
-      }
+      load_x<BS, KS, QUAD>(x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0), kq, use, xb);
       const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS);
       // MG row tiles at a time: their operands are loaded first and their
       // independent accumulations interleaved, so no MFMA waits on the last
@@ -559,6 +565,48 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
     }
   }
   if (!rv) return;
+  const size_t rb = qoff + static_cast<size_t>(row) * BS;
+  if constexpr (P32 && BS % 16 == 0) {
+    // FP32 result layout: lane l holds rows 16 m + 4 (l/16) + i, four
+    // consecutive entries per row tile: with 16-byte aligned out and z (a
+    // wavefront-uniform test) every z load is issued before the first use and
+    // the results leave in 16-byte stores
+    if (((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(z)) & 15) == 0) {
+      double y[MT][4];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[m][i] = alpha * static_cast<double>(acc[m][i]);
+      if (beta != 0.0) {
+        double2 zv[MT][2];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const double2* zp = reinterpret_cast<const double2*>(z + rb + 16 * m + 4 * kq);
+          zv[m][0] = zp[0];
+          zv[m][1] = zp[1];
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          y[m][0] = __builtin_fma(beta, zv[m][0].x, y[m][0]);
+          y[m][1] = __builtin_fma(beta, zv[m][0].y, y[m][1]);
+          y[m][2] = __builtin_fma(beta, zv[m][1].x, y[m][2]);
+          y[m][3] = __builtin_fma(beta, zv[m][1].y, y[m][3]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        OT* op = out + rb + 16 * m + 4 * kq;
+        if constexpr (std::is_same<OT, float>::value) {
+          *reinterpret_cast<float4*>(op) = float4{static_cast<float>(y[m][0]), static_cast<float>(y[m][1]),
+                                                  static_cast<float>(y[m][2]), static_cast<float>(y[m][3])};
+        } else {
+          reinterpret_cast<double2*>(op)[0] = double2{y[m][0], y[m][1]};
+          reinterpret_cast<double2*>(op)[1] = double2{y[m][2], y[m][3]};
+        }
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -566,9 +614,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       // result layout: FP64 lane l holds rows l/16 + 4i, FP32 rows 4(l/16) + i
       const int r = 16 * m + (P32 ? 4 * kq + i : kq + 4 * i);
       if (r < BS) {
-        const size_t o = qoff + static_cast<size_t>(row) * BS + r;
-        const double y = static_cast<double>(acc[m][i]);
-        out[o] = static_cast<OT>(beta != 0.0 ? alpha * y + beta * z[o] : alpha * y);
+        const double y = alpha * static_cast<double>(acc[m][i]);
+        out[rb + r] = static_cast<OT>(beta != 0.0 ? __builtin_fma(beta, z[rb + r], y) : y);
       }
     }
 }

@@ -369,7 +369,7 @@ class ServingEngine:
         to retry (not converged with the SAI smoother).  Admission stops after
         4 x max_batch requests when another key is waiting, so that a busy key
         does not hold a worker forever."""
-        from ldg_inputs import rhs_normal
+        from ldg_inputs import rhs_normal_device
         torch = self.torch
         n = e.solver.ndofs
         first = deque(batch)
@@ -389,8 +389,8 @@ class ServingEngine:
                         return None
                     r = q.popleft()
                 admitted[0] += 1
-            with torch.cuda.stream(stream):
-                b = torch.from_numpy(rhs_normal(n, r.seed)).to("cuda")
+            with torch.cuda.stream(stream):        # the request's right-hand side, resident on the device
+                b = rhs_normal_device(n, r.seed)
                 x = torch.empty_like(b)
             inflight[r.rid] = (r, self._now(), len(inflight) + 1, x)
             return b, x, r.rid

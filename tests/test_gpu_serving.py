@@ -14,7 +14,7 @@ hierarchies admitted by HBM budget and kept resident.
 import numpy as np
 import pytest
 
-from ldg_inputs import Request, rhs_normal, serving_requests
+from ldg_inputs import Request, rhs_normal_device, serving_requests
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -33,7 +33,7 @@ def _alone(results, precision):
         s = L.Solver(**problem_kwargs(key, precision, smoother))
         try:
             for r in rs:
-                b = torch.from_numpy(rhs_normal(s.ndofs, r.seed_used)).cuda()
+                b = rhs_normal_device(s.ndofs, r.seed_used)
                 x = torch.empty_like(b)
                 info = L.ldgmg_solve(s.handle, b, x, "cg", 1e-10, 200)
                 torch.cuda.synchronize()
