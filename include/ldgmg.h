@@ -201,6 +201,25 @@ int ldgmg_unload(ldgmg_handle h);
  * failure (serving).  Kept across ldgmg_unload / ldgmg_upload. */
 int ldgmg_cg_guard(ldgmg_handle h, int enable);
 
+/* CG solves of this handle (ldgmg_solve with LDGMG_CG) replayed from a HIP
+ * graph: check_every = 0 (the default) launches every kernel of every
+ * iteration from the host and synchronises once per iteration to test
+ * convergence; check_every = k >= 1 captures one iteration of the recurrence
+ * of Section 2.2 (the operator apply, the updates, the V-cycle of Algorithm 1
+ * and the inner products) in a graph on the first such solve and replays it k
+ * times between host synchronisations.  The convergence test runs on the
+ * device: once the recurrence stops (||r|| <= rtol ||b||, maxit, the guard of
+ * ldgmg_cg_guard, or a non-finite residual) the step length is 0, so the up to
+ * k - 1 replays left leave x and r unchanged.  The results (iterations,
+ * solution, residual history) equal those of the eager recurrence; the
+ * replays after the stop cost device time only.  For right-hand sides whose
+ * solves are bound by launch latency (small grids).  The graph uses the
+ * handle's own vectors and is captured again after ldgmg_fp32_products,
+ * ldgmg_cg_guard or ldgmg_upload; solves with ldgmg_profile on, maxit above
+ * 4096 or GMRES stay eager.  Solves of one handle must not overlap (as for
+ * every solve).  Batched and streamed solves are not affected. */
+int ldgmg_cg_graph(ldgmg_handle h, int check_every);
+
 /* FP32 products for the V-cycle of this handle: where a level is tiled
  * (ldgmg_level_storage), its operator and smoother applies (A, B, B^T, and the
  * block inverses of Jacobi) multiply on the FP32 matrix cores: the stored FP32

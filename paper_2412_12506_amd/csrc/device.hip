@@ -132,6 +132,14 @@ struct DevHier {
   double *bx = nullptr, *br = nullptr, *bp = nullptr, *bq = nullptr, *bz = nullptr;
   double* bscal = nullptr;          // per right-hand side scalars [kMaxRhs][8]
   double* hbscal = nullptr;         // pinned host mirror
+  // CG iteration captured in a graph (ldgmg_cg_graph): the executable graph,
+  // the handle generation it was captured at, its capture stream and the
+  // device residual history
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int ggen = -1;
+  hipStream_t capst = nullptr;
+  double* ghist = nullptr;
   // fine-level launch timing (ldgmg_profile)
   bool prof = false;
   std::vector<hipEvent_t> evpool;
@@ -190,6 +198,9 @@ struct DevHier {
     HIPCHK(hipFreeAsync(p, st));   // stream-ordered: no device-wide synchronisation
   }
   ~DevHier() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capst) (void)hipStreamDestroy(capst);
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     for (void* p : allocs) {
       if (ufree) ufree(p, uctx);
@@ -209,12 +220,16 @@ struct ldgmg_hier {
   bool cg_guard = false;            // ldgmg_cg_guard
   bool fp32_products = false;       // ldgmg_fp32_products
   double rhs_check = 0.0;           // ldgmg_rhs_check tolerance (0: off)
+  int graph_every = 0;              // ldgmg_cg_graph: replays between host checks (0: eager CG)
+  int gen = 0;                      // bumped by every setting a captured graph depends on
 };
 
 namespace ldgmg {
 namespace {
 
 enum { S_BB = 0, S_RZ = 1, S_ALPHA = 2, S_RR = 3, S_BETA = 4, S_PQ = 5, S_TMP = 6, S_W = 7, S_K = 8 };
+static_assert(kScalFrozen > S_K && kScalRRFinal < 64, "graph CG slots follow the others in the 64-entry table");
+constexpr int kGraphHist = 4096;   // residual history entries of a replayed CG solve
 
 // bytes per stored entry of the operators A and of the smoother S
 size_t elem_bytes_A(int prec) { return prec == LDGMG_FP64 ? 8 : 4; }
@@ -880,7 +895,7 @@ Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, boo
     return x;
   }
   // multi-coloured Gauss-Seidel: colours in order (forward) or reversed
-  if (zero_x) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(Vd), c.st));
+  if (zero_x) fill_zero(x, L.N, c.st);     // a kernel, not a memset: the V-cycle may be captured in a graph
   const int nc = static_cast<int>(L.colour_rows.size());
   for (int k = 0; k < nc; ++k) {
     const int col = forward ? k : nc - 1 - k;
@@ -942,7 +957,7 @@ void vcycle_level(const Ctx& c, int l) {
       x = L.x;
     }
   };
-  if (P.nu1 == 0) HIPCHK(hipMemsetAsync(x, 0, static_cast<size_t>(L.N) * sizeof(Vd), c.st));
+  if (P.nu1 == 0) fill_zero(x, L.N, c.st);
   for (int s = 0; s < P.nu1; ++s) keep(smooth_step<T, TS>(c, L, x, b, pre_fwd, s == 0));
   residual<T>(c.D, L, x, b, L.r, c.st);
   DevLevel& Lc = c.D.L[l + 1];
@@ -1086,6 +1101,95 @@ int solve_cg(const Ctx& c, const double* b, double* x, double rtol, int maxit, l
     finalize(D.partial, D.scal, 2, S_BETA, S_RZ, c.st);           // beta = rz_new / rz; rz = rz_new
     cg_dir(N, D.kp, D.kz, D.scal, S_BETA, c.st);
   }
+  finish_info(c, b, x, bb, hist, it, conv, std::sqrt(rr / bb), vcycles, info);
+  return conv ? LDGMG_OK : LDGMG_ENOCONV;
+}
+
+// The CG iteration of solve_cg (q = A p, alpha, x and r updates, r.r, the
+// convergence test, z = V r, beta, p = z + beta p) captured once in a graph
+// and replayed `every` times between host checks.  The test runs on the
+// device: once it stops the recurrence (convergence, iteration limit,
+// breakdown, guarded stop) alpha is 0, so the replays left in the batch leave
+// x and r unchanged.  The first direction p = z comes from p = 0 and any
+// finite beta, so every iteration is the same graph.  The results (iterations,
+// x, history) are those of solve_cg; the replays after the stop cost device
+// time only.  Used for right-hand sides whose solves are launch-bound.
+int solve_cg_graph(ldgmg_hier* h, const Ctx& c, const double* b, double* x, double rtol, int maxit,
+                   ldgmg_info* info) {
+  DevHier& D = c.D;
+  const long long N = D.L[0].N;
+  double* xi = D.kx;                        // the graph's x: the caller's x changes between solves
+  fill_zero(xi, N, c.st);
+  HIPCHK(hipMemcpyAsync(D.kr, b, N * 8, hipMemcpyDeviceToDevice, c.st));
+  const double bb = dot_host(c, b, b, S_BB);
+  if (!std::isfinite(bb)) throw std::invalid_argument("right-hand side contains NaN or Inf");
+  std::vector<double> hist;
+  if (bb == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, N * 8, c.st));
+    finish_info(c, b, x, bb, hist, 0, true, 0.0, 0, info);
+    return LDGMG_OK;
+  }
+  const double tol2 = rtol * rtol * bb;
+  vcycle64(c, D.kr, D.kz);
+  dot_partial(N, D.kr, D.kz, D.partial, c.st);
+  finalize(D.partial, D.scal, 0, S_RZ, 0, c.st);
+  fill_zero(D.kp, N, c.st);                 // p = z + 0 p on the first replay
+  cg_init(D.scal, tol2, maxit, c.st);
+  if (!D.ghist) D.ghist = static_cast<double*>(D.alloc(kGraphHist * sizeof(double)));
+  if (!D.gexec || D.ggen != h->gen) {
+    if (D.gexec) HIPCHK(hipGraphExecDestroy(D.gexec));
+    if (D.graph) HIPCHK(hipGraphDestroy(D.graph));
+    D.gexec = nullptr;
+    D.graph = nullptr;
+    if (!D.capst) HIPCHK(hipStreamCreateWithFlags(&D.capst, hipStreamNonBlocking));
+    Ctx cc{c.H, D, D.capst, c.guard};
+    HIPCHK(hipStreamBeginCapture(D.capst, hipStreamCaptureModeRelaxed));
+    try {
+      // beta = rz_new / rz from the r.z partials of the previous replay (of
+      // the prologue on the first, where beta is 0)
+      finalize(D.partial, D.scal, 5, S_BETA, S_RZ, cc.st);
+      cg_dir(N, D.kp, D.kz, D.scal, S_BETA, cc.st);
+      apply_A64(cc, D.kp, D.kq);
+      dot_partial(N, D.kp, D.kq, D.partial, cc.st);
+      finalize(D.partial, D.scal, 4, S_ALPHA, S_RZ, cc.st);        // alpha = rz / (p.q), 0 once stopped
+      cg_update(N, xi, D.kr, D.kp, D.kq, D.scal, S_ALPHA, D.partial, cc.st);
+      finalize(D.partial, D.scal, 0, S_RR, 0, cc.st);
+      cg_check(D.scal, D.ghist, kGraphHist, cc.guard, S_RZ, S_ALPHA, S_RR, cc.st);
+      vcycle64(cc, D.kr, D.kz);
+      dot_partial(N, D.kr, D.kz, D.partial, cc.st);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(D.capst, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(D.capst, &D.graph));
+    HIPCHK(hipGraphInstantiate(&D.gexec, D.graph, nullptr, nullptr, 0));
+    D.ggen = h->gen;
+  }
+  const int every = std::max(1, h->graph_every);
+  int launched = 0;
+  for (;;) {
+    for (int k = 0; k < every; ++k) HIPCHK(hipGraphLaunch(D.gexec, c.st));
+    launched += every;
+    HIPCHK(hipMemcpyAsync(D.hscal, D.scal, 64 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    if (D.hscal[kScalFrozen] != 0.0) break;
+    if (launched > maxit + every) throw std::runtime_error("graph CG: the recurrence did not stop at maxit");
+  }
+  const int status = static_cast<int>(D.hscal[kScalStatus]);
+  const int it = static_cast<int>(D.hscal[kScalIt]);
+  const double rr = D.hscal[kScalRRFinal];
+  if (status == 3) throw std::runtime_error("CG breakdown (non-finite residual)");
+  hist.resize(std::min(it, kGraphHist));
+  if (!hist.empty())
+    HIPCHK(hipMemcpyAsync(hist.data(), D.ghist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipMemcpyAsync(x, xi, N * 8, hipMemcpyDeviceToDevice, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  const bool conv = status == 1;
+  // V-cycles the eager recurrence applies: one more than the iterations when
+  // it stops at the limit (the last V-cycle follows the last check)
+  const int vcycles = status == 0 ? it + 1 : it;
   finish_info(c, b, x, bb, hist, it, conv, std::sqrt(rr / bb), vcycles, info);
   return conv ? LDGMG_OK : LDGMG_ENOCONV;
 }
@@ -1323,7 +1427,7 @@ void smooth_step_multi(const Ctx& c, DevLevel& L, DevHier::BatchLevel& B, bool f
     apply_S_multi<T>(c.D, L, false, B.r, B.x, B.x, omega, 1.0, nk, c.st);
     return;
   }
-  if (zero_x) HIPCHK(hipMemsetAsync(B.x, 0, vb, c.st));
+  if (zero_x) fill_zero(B.x, static_cast<long long>(vb / sizeof(Vd)), c.st);
   const int ncol = static_cast<int>(L.colour_rows.size());
   for (int k = 0; k < ncol; ++k) {
     const int col = forward ? k : ncol - 1 - k;
@@ -1344,7 +1448,7 @@ void vcycle_level_multi(const Ctx& c, int l, int nk) {
   }
   const ldgmg_problem& P = c.H.prob;
   const bool pre_fwd = order_pre_forward(P.order), post_fwd = order_post_forward(P.order);
-  if (P.nu1 == 0) HIPCHK(hipMemsetAsync(B.x, 0, static_cast<size_t>(L.N) * nk * sizeof(Vd), c.st));
+  if (P.nu1 == 0) fill_zero(B.x, L.N * nk, c.st);
   for (int s = 0; s < P.nu1; ++s) smooth_step_multi<T, TS>(c, L, B, pre_fwd, s == 0, nk);
   residual_multi<T>(c.D, L, B.x, B.b, B.r, nk, c.st);
   DevLevel& Lc = c.D.L[l + 1];
@@ -1543,7 +1647,10 @@ int solve_one(ldgmg_hier* h, const double* b, double* x, int krylov, double rtol
     project_rhs(c, b, D.bproj);
     bb = D.bproj;
   }
-  const int rc = krylov == LDGMG_CG ? solve_cg(c, bb, x, rtol, maxit, info) : solve_gmres(c, bb, x, rtol, maxit, info);
+  int rc;
+  if (krylov != LDGMG_CG) rc = solve_gmres(c, bb, x, rtol, maxit, info);
+  else if (h->graph_every > 0 && maxit > 0 && maxit <= kGraphHist && !D.prof) rc = solve_cg_graph(h, c, bb, x, rtol, maxit, info);
+  else rc = solve_cg(c, bb, x, rtol, maxit, info);
   if (D.nker) {
     remove_kernel(c, x);
     HIPCHK(hipStreamSynchronize(st));
@@ -1913,6 +2020,16 @@ int ldgmg_cg_guard(ldgmg_handle h, int enable) {
   return guarded([&] {
     if (!h || !h->host) throw std::invalid_argument("null handle");
     h->cg_guard = enable != 0;
+    ++h->gen;                       // the guard is an argument of the captured test
+    return LDGMG_OK;
+  });
+}
+
+int ldgmg_cg_graph(ldgmg_handle h, int check_every) {
+  return guarded([&] {
+    if (!h || !h->host) throw std::invalid_argument("null handle");
+    if (check_every < 0) throw std::invalid_argument("check_every must be >= 0");
+    h->graph_every = check_every;
     return LDGMG_OK;
   });
 }
@@ -1946,6 +2063,7 @@ int ldgmg_fp32_products(ldgmg_handle h, int enable) {
     if (enable && h->host->prob.precision == LDGMG_FP64)
       throw std::invalid_argument("FP32 products need FP32 or BF16 storage");
     h->fp32_products = enable != 0;
+    ++h->gen;                       // other kernels: a captured iteration is stale
     if (h->dev)
       for (DevLevel& L : h->dev->L) L.p32 = h->fp32_products;
     return LDGMG_OK;

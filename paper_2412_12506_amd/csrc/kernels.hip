@@ -954,6 +954,11 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(int nparts, const doub
       scal[dst] = v;
     } else if (op == 1) {
       scal[dst] = scal[a] / v;
+    } else if (op == 4) {                  // op 1 that yields 0 once the recurrence is frozen
+      scal[dst] = scal[kScalFrozen] != 0.0 ? 0.0 : scal[a] / v;
+    } else if (op == 5) {                  // op 2 that yields 0 before the first iteration
+      scal[dst] = scal[kScalIt] == 0.0 ? 0.0 : v / scal[a];
+      scal[a] = v;
     } else if (op == 3) {
       scal[dst] = -v;
     } else {
@@ -1012,6 +1017,43 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize_many(int nparts, const
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += p[i];
   const double v = block_sum(s);
   if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+__global__ void k_fill_zero(long long n, double* __restrict__ p) {
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
+}
+
+// device-side CG bookkeeping of a replayed iteration (one thread)
+__global__ void k_cg_init(double* scal, double tol2, double maxit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  scal[kScalFrozen] = 0.0;
+  scal[kScalIt] = 0.0;
+  scal[kScalStatus] = -1.0;
+  scal[kScalTol2] = tol2;
+  scal[kScalMaxit] = maxit;
+  scal[kScalRRFinal] = 0.0;
+}
+
+__global__ void k_cg_check(double* scal, double* hist, int cap, int guard, int s_rz, int s_alpha, int s_rr) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (scal[kScalFrozen] != 0.0) return;
+  const double it = scal[kScalIt] + 1.0;
+  scal[kScalIt] = it;
+  const int k = static_cast<int>(it) - 1;
+  if (k < cap) hist[k] = sqrt(fabs(scal[s_rz]));
+  const double rr = scal[s_rr];
+  double status = -1.0;
+  if (!isfinite(rr)) status = 3.0;                          // breakdown
+  else if (rr <= scal[kScalTol2]) status = 1.0;             // converged
+  else if (guard && (!(scal[s_rz] > 0.0) || !(scal[s_alpha] > 0.0))) status = 2.0;   // guarded stop
+  else if (it >= scal[kScalMaxit]) status = 0.0;            // iteration limit
+  if (status >= 0.0) {
+    scal[kScalFrozen] = 1.0;
+    scal[kScalStatus] = status;
+    scal[kScalRRFinal] = rr;
+  }
 }
 
 // w += sign * sum_{j<k} h[j] Q_j
@@ -1355,6 +1397,24 @@ void dot_partial(long long n, const double* a, const double* b, double* partial,
 void finalize(const double* partial, double* scal, int op, int dst, int a, hipStream_t st) {
   k_finalize<<<1, kRedThreads, 0, st>>>(kRedBlocks, partial, scal, op, dst, a);
   check_launch("finalize");
+}
+
+void fill_zero(double* p, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  const long long want = (n + 255) / 256;
+  const int blocks = static_cast<int>(want < 4096 ? want : 4096);
+  k_fill_zero<<<blocks, 256, 0, st>>>(n, p);
+  check_launch("fill_zero");
+}
+
+void cg_init(double* scal, double tol2, int maxit, hipStream_t st) {
+  k_cg_init<<<1, 64, 0, st>>>(scal, tol2, static_cast<double>(maxit));
+  check_launch("cg_init");
+}
+
+void cg_check(double* scal, double* hist, int cap, bool guard, int s_rz, int s_alpha, int s_rr, hipStream_t st) {
+  k_cg_check<<<1, 64, 0, st>>>(scal, hist, cap, guard ? 1 : 0, s_rz, s_alpha, s_rr);
+  check_launch("cg_check");
 }
 
 void cg_update(long long n, double* x, double* r, const double* p, const double* q, const double* scal,

@@ -88,8 +88,22 @@ template <typename T> void dense_gemv(int N, const double* P, const T* in, T* ou
 
 void dot_partial(long long n, const double* a, const double* b, double* partial, hipStream_t st);
 // op 0: scal[dst] = v;  op 1: scal[dst] = scal[a] / v;  op 2: scal[dst] = v / scal[a], scal[a] = v;
-// op 3: scal[dst] = -v
+// op 3: scal[dst] = -v;  op 4: op 1, or 0 once scal[kScalFrozen] is set;  op 5: op 2, with 0 for
+// scal[dst] while scal[kScalIt] is 0
 void finalize(const double* partial, double* scal, int op, int dst, int a, hipStream_t st);
+// scalar-table slots of the CG recurrence replayed from a graph
+constexpr int kScalFrozen = 9;    // 1 once the recurrence has stopped: alpha is 0 from then on
+constexpr int kScalIt = 10;       // iterations done
+constexpr int kScalStatus = 11;   // -1 running, 0 iteration limit, 1 converged, 2 guarded stop, 3 breakdown
+constexpr int kScalTol2 = 12;     // rtol^2 b.b
+constexpr int kScalMaxit = 13;
+constexpr int kScalRRFinal = 14;  // r.r when the recurrence stopped
+void fill_zero(double* p, long long n, hipStream_t st);
+// scal: frozen 0, iterations 0, status -1, tol2 and maxit set
+void cg_init(double* scal, double tol2, int maxit, hipStream_t st);
+// after an iteration's r.r: count it, record sqrt|r.z| in hist (cap entries),
+// and freeze the recurrence on convergence, breakdown, a guarded stop or maxit
+void cg_check(double* scal, double* hist, int cap, bool guard, int s_rz, int s_alpha, int s_rr, hipStream_t st);
 void cg_update(long long n, double* x, double* r, const double* p, const double* q, const double* scal,
                int ia, double* partial, hipStream_t st);
 void cg_dir(long long n, double* p, const double* z, const double* scal, int ib, hipStream_t st);

@@ -110,7 +110,7 @@ SYMBOLS = ["ldgmg_problem_default", "ldgmg_estimate_bytes", "ldgmg_setup_host", 
            "ldgmg_solve", "ldgmg_solve_batch", "ldgmg_vcycle_batch", "ldgmg_level_op", "ldgmg_export", "ldgmg_export_colours",
            "ldgmg_setup_stats", "ldgmg_profile", "ldgmg_profile_read", "ldgmg_unload", "ldgmg_cg_guard", "ldgmg_fp32_products", "ldgmg_device_bytes", "ldgmg_upload_bytes", "ldgmg_level_storage",
            "ldgmg_rhs_check", "ldgmg_kernel", "ldgmg_solve_stream", "ldgmg_vcycle_batch_noalloc",
-           "ldgmg_setup_stats_device", "ldgmg_destroy",
+           "ldgmg_setup_stats_device", "ldgmg_cg_graph", "ldgmg_destroy",
            "ldgmg_last_error"]
 
 
@@ -152,6 +152,7 @@ def lib():
     L.ldgmg_profile_read.argtypes = [H, C.c_int, ip, dp]
     L.ldgmg_unload.argtypes = [H]
     L.ldgmg_cg_guard.argtypes = [H, C.c_int]
+    L.ldgmg_cg_graph.argtypes = [H, C.c_int]
     L.ldgmg_fp32_products.argtypes = [H, C.c_int]
     L.ldgmg_device_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.ldgmg_upload_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
@@ -484,6 +485,12 @@ def ldgmg_unload(h: int):
 
 def ldgmg_cg_guard(h: int, enable: bool = True):
     _check(lib().ldgmg_cg_guard(h, 1 if enable else 0))
+
+
+def ldgmg_cg_graph(h: int, check_every: int = 4):
+    """CG solves of the handle replay one captured iteration check_every times
+    between host checks (0: eager)."""
+    _check(lib().ldgmg_cg_graph(h, int(check_every)))
 
 
 def ldgmg_fp32_products(h: int, enable: bool = True):
