@@ -34,12 +34,20 @@ def lib_kwargs(case, precision):
     return kw
 
 
+_BUILT = {}
+
+
 def oracle_build(case):
+    """The oracle's hierarchy and V-cycle for a case, built once per process
+    (several test modules and precisions share a case; callers only read it)."""
     kw = {k: v for k, v in case.items() if k not in ("mu", "rho", "id", "krylov", "nthreads")}
-    kw["mu"] = mu_of(case)
-    if "rho" in case:
-        kw["rho"] = field_of(case, "rho")
-    return osolver.build(**kw)
+    key = repr(sorted((k, repr(v)) for k, v in case.items() if k not in ("id", "krylov", "nthreads")))
+    if key not in _BUILT:
+        kw["mu"] = mu_of(case)
+        if "rho" in case:
+            kw["rho"] = field_of(case, "rho")
+        _BUILT[key] = osolver.build(**kw)
+    return _BUILT[key]
 
 
 def smoother_matrix(vc, level):
