@@ -255,7 +255,7 @@ std::vector<int> column_offsets(const PMat& P) {
 }
 
 constexpr int kMaxTiledOffsets = 64;
-constexpr int kMinTiledRows = 16384;      // 1024 tiles: enough to fill the device
+constexpr int kMinTiledRows = 4096;       // 256 tiles; below 1024 tiles the kernel takes a wavefront per row tile
 constexpr double kMaxTiledPasses = 1.5;   // mean MFMA passes per tile and offset
 
 // pool-id table [row][offset] of a matrix and its rows ordered by table row

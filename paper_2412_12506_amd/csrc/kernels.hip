@@ -87,6 +87,7 @@ __device__ __forceinline__ T group_bcast(T v, int g, int c) {
 }
 
 constexpr int kWaves = 4;          // wavefronts per workgroup of the BSR kernels
+constexpr long long kSplitTiles = 1024;   // below this many tiles: one wavefront per row tile
 constexpr int kThreads = 64 * kWaves;
 
 // ---------------------------------------------------------------------------
@@ -503,8 +504,11 @@ __device__ __forceinline__ void load_x(const XT* xp, int kq, bool use, OP (&xb)[
 // combined with z in FP64.  XT / OT: element type of x / out; FP32 x (already
 // rounded by its producer, so the same operand values) or FP32 out only with
 // FP32 products, one right-hand side and 16 | bs.  QUAD: the matrix is laid out
-// with the 4-step k mapping (required for FP32 x).
-template <typename TM, int BS, int LKP, bool P32, typename XT = double, typename OT = double, bool QUAD = false>
+// with the 4-step k mapping (required for FP32 x).  SPLIT: one wavefront per
+// row tile of a tile (MT wavefronts per tile, one right-hand side), for
+// matrices with too few tiles to fill the device; the products are the same.
+template <typename TM, int BS, int LKP, bool P32, typename XT = double, typename OT = double, bool QUAD = false,
+          bool SPLIT = false>
 __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
                                                         const int* __restrict__ tab,
                                                         const int* __restrict__ perm,
@@ -513,8 +517,10 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
                                                         double beta, long long stride, int nk) {
   static_assert(std::is_same<XT, double>::value || (P32 && QUAD && BS % 16 == 0), "FP32 x: FP32 products, quad layout");
   static_assert(!QUAD || BS % 16 == 0, "the quad layout needs 16 | bs");
+  static_assert(!SPLIT || LKP == 0, "one wavefront per row tile: one right-hand side");
   constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
-  constexpr int MG = sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
+  constexpr int MW = SPLIT ? 1 : MT;            // row tiles of this wavefront
+  constexpr int MG = SPLIT ? 1 : sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
   using OP = typename std::conditional<P32, float, double>::type;
   using ACC = typename std::conditional<P32, v4f, v4d>::type;
   const int lane = threadIdx.x & 63;
@@ -523,7 +529,9 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   const int nb = gridDim.x, n8 = nb >> 3;
   const int b = blockIdx.x;
   const int lb = b < 8 * n8 ? (b & 7) * n8 + (b >> 3) : b;
-  const int tile = lb * kWaves + (threadIdx.x >> 6);
+  const int wv = lb * kWaves + (threadIdx.x >> 6);
+  const int tile = SPLIT ? wv / MT : wv;
+  const int mw = SPLIT ? wv - tile * MT : 0;   // first row tile of this wavefront
   const int e0 = tile * (16 >> LKP);        // 16 / kp block rows per tile
   if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
   const int col = lane & 15, kq = lane >> 4;
@@ -531,9 +539,9 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   const bool rv = e0 + (col >> LKP) < nrows && q < nk;
   const int row = perm[rv ? e0 + (col >> LKP) : e0];
   const size_t qoff = static_cast<size_t>(rv ? q : 0) * stride;
-  ACC acc[MT];
+  ACC acc[MW];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) acc[m] = ACC{0, 0, 0, 0};
+  for (int m = 0; m < MW; ++m) acc[m] = ACC{0, 0, 0, 0};
   for (int d = 0; d < noff; ++d) {
     const int o = off[d];
     const int t = tab[static_cast<size_t>(row) * noff + d];
@@ -546,20 +554,20 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const bool use = (sel >> col) & 1ull;
       OP xb[KS];
       load_x<BS, KS, QUAD>(x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0), kq, use, xb);
-      const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS);
+      const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(mw) * 64 * KS;
       // MG row tiles at a time: their operands are loaded first and their
       // independent accumulations interleaved, so no MFMA waits on the last
 #pragma unroll
-      for (int m0 = 0; m0 < MT; m0 += MG) {
+      for (int m0 = 0; m0 < MW; m0 += MG) {
         OP a[MG][KS];
 #pragma unroll
         for (int g = 0; g < MG; ++g)
-          if (m0 + g < MT) load_widen<TM, KS, OP>(bp + (m0 + g) * 64 * KS, lane, a[g]);
+          if (m0 + g < MW) load_widen<TM, KS, OP>(bp + (m0 + g) * 64 * KS, lane, a[g]);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
           for (int g = 0; g < MG; ++g)
-            if (m0 + g < MT) acc[m0 + g] = mfma_step(a[g][s], xb[s], acc[m0 + g]);
+            if (m0 + g < MW) acc[m0 + g] = mfma_step(a[g][s], xb[s], acc[m0 + g]);
       }
       rem &= ~sel;
     }
@@ -572,21 +580,21 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
     // wavefront-uniform test) every z load is issued before the first use and
     // the results leave in 16-byte stores
     if (((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(z)) & 15) == 0) {
-      double y[MT][4];
+      double y[MW][4];
 #pragma unroll
-      for (int m = 0; m < MT; ++m)
+      for (int m = 0; m < MW; ++m)
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[m][i] = alpha * static_cast<double>(acc[m][i]);
       if (beta != 0.0) {
-        double2 zv[MT][2];
+        double2 zv[MW][2];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          const double2* zp = reinterpret_cast<const double2*>(z + rb + 16 * m + 4 * kq);
+        for (int m = 0; m < MW; ++m) {
+          const double2* zp = reinterpret_cast<const double2*>(z + rb + 16 * (mw + m) + 4 * kq);
           zv[m][0] = zp[0];
           zv[m][1] = zp[1];
         }
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
+        for (int m = 0; m < MW; ++m) {
           y[m][0] = __builtin_fma(beta, zv[m][0].x, y[m][0]);
           y[m][1] = __builtin_fma(beta, zv[m][0].y, y[m][1]);
           y[m][2] = __builtin_fma(beta, zv[m][1].x, y[m][2]);
@@ -594,8 +602,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
         }
       }
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        OT* op = out + rb + 16 * m + 4 * kq;
+      for (int m = 0; m < MW; ++m) {
+        OT* op = out + rb + 16 * (mw + m) + 4 * kq;
         if constexpr (std::is_same<OT, float>::value) {
           *reinterpret_cast<float4*>(op) = float4{static_cast<float>(y[m][0]), static_cast<float>(y[m][1]),
                                                   static_cast<float>(y[m][2]), static_cast<float>(y[m][3])};
@@ -608,11 +616,11 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
     }
   }
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
+  for (int m = 0; m < MW; ++m)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       // result layout: FP64 lane l holds rows l/16 + 4i, FP32 rows 4(l/16) + i
-      const int r = 16 * m + (P32 ? 4 * kq + i : kq + 4 * i);
+      const int r = 16 * (mw + m) + (P32 ? 4 * kq + i : kq + 4 * i);
       if (r < BS) {
         const double y = alpha * static_cast<double>(acc[m][i]);
         out[rb + r] = static_cast<OT>(beta != 0.0 ? __builtin_fma(beta, z[rb + r], y) : y);
@@ -1108,23 +1116,32 @@ template <typename TM, typename T, int BS>
 void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStream_t st) {
   // FP32 products for FP32 / BF16 storage only: FP64 blocks keep FP64 products
   constexpr bool P32 = !std::is_same<TM, double>::value;
+  constexpr int MT = (BS + 15) / 16;        // row tiles per tile
   if (a.p32 && !P32) throw std::invalid_argument("bsr_tiled: FP32 products need FP32 or BF16 storage");
   if (a.x32 || a.out32) {                   // an FP32 vector in or out (smoothing residuals)
     if constexpr (P32 && BS % 16 == 0) {
       if (!a.p32 || nk != 1 || (a.x32 && a.out32) || (a.x32 && !a.tquad))
         throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products, one right-hand side and, "
                                     "for FP32 x, the quad layout");
-      const int blocks = static_cast<int>((a.nrows + 16 * kWaves - 1) / (16 * kWaves));
+      const long long tiles = (a.nrows + 15) / 16;
+      const bool split = tiles < kSplitTiles;
+      const int blocks = static_cast<int>((tiles * (split ? MT : 1) + kWaves - 1) / kWaves);
       if (blocks == 0) return;
-      if (a.x32)
-        k_bsr_tiled<TM, BS, 0, true, float, double, true><<<blocks, kThreads, 0, st>>>(
-            a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x32, a.z, a.out, a.alpha, a.beta, 0, 1);
-      else if (a.tquad)
-        k_bsr_tiled<TM, BS, 0, true, double, float, true><<<blocks, kThreads, 0, st>>>(
-            a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out32, a.alpha, a.beta, 0, 1);
-      else
-        k_bsr_tiled<TM, BS, 0, true, double, float, false><<<blocks, kThreads, 0, st>>>(
-            a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out32, a.alpha, a.beta, 0, 1);
+#define TILED32(XT_, OT_, Q_, X_, O_)                                                                          \
+  if (split)                                                                                                   \
+    k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_, true><<<blocks, kThreads, 0, st>>>(                             \
+        a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);                  \
+  else                                                                                                         \
+    k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_><<<blocks, kThreads, 0, st>>>(                                   \
+        a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);
+      if (a.x32) {
+        TILED32(float, double, true, a.x32, a.out)
+      } else if (a.tquad) {
+        TILED32(double, float, true, a.x, a.out32)
+      } else {
+        TILED32(double, float, false, a.x, a.out32)
+      }
+#undef TILED32
       check_launch("bsr_tiled");
       return;
     } else {
@@ -1139,6 +1156,29 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   const long long tiles = (a.nrows + rpt - 1) / rpt;
   const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
   if (blocks == 0) return;
+  if (lkp == 0 && tiles < kSplitTiles) {    // few tiles: one wavefront per row tile
+    const int bsplit = static_cast<int>((tiles * MT + kWaves - 1) / kWaves);
+    if constexpr (P32 && BS % 16 == 0) {
+      if (a.tquad) {
+        if (a.p32)
+          k_bsr_tiled<TM, BS, 0, true, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
+              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+        else
+          k_bsr_tiled<TM, BS, 0, false, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
+              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+        check_launch("bsr_tiled");
+        return;
+      }
+    }
+    if (P32 && a.p32)
+      k_bsr_tiled<TM, BS, 0, P32, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
+          a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+    else
+      k_bsr_tiled<TM, BS, 0, false, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
+          a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+    check_launch("bsr_tiled");
+    return;
+  }
   switch (lkp) {
 #define TILED(LK)                                                                                              \
   case LK:                                                                                                     \
