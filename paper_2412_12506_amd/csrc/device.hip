@@ -55,7 +55,8 @@ struct SingularError : std::runtime_error {
 struct Tiled {
   const void* blk = nullptr;        // pool in the operand layout of the tiled kernel
   int* tab = nullptr;               // [rows][noff] pool ids, -1 where no block
-  int* perm = nullptr;              // rows ordered by their row of tab
+  int* perm = nullptr;              // rows ordered by their row of tab, -1 where a tile is padded
+  int nperm = 0;                    // entries of perm
   int* off = nullptr;               // column offsets
   int noff = 0;
   bool quad = false;                // pool in the 4-step k mapping (read with FP32 x)
@@ -278,19 +279,44 @@ void tiled_table(const PMat& P, const std::vector<int>& off, std::vector<int>& t
   });
 }
 
-// mean number of MFMA passes (distinct blocks) per 16-row tile and offset
+// the tile order of the tiled kernel: the rows ordered by table row, each
+// group of equal table rows starting a 16-row tile (-1 pads the tile before
+// it) when that costs at most a quarter more places.  In a padded order a
+// tile holds one table row, so one MFMA pass per offset: no tile takes longer
+// than the others, which matters where there are few tiles per SIMD.
+constexpr double kMaxPadding = 1.25;
+void tiled_order(const PMat& P, const std::vector<int>& off, std::vector<int>& tab, std::vector<int>& perm) {
+  tiled_table(P, off, tab, perm);
+  const int noff = static_cast<int>(off.size());
+  std::vector<int> pad;
+  pad.reserve(perm.size() + perm.size() / 4 + 16);
+  for (size_t e = 0; e < perm.size(); ++e) {
+    const bool start = e == 0 || !std::equal(tab.begin() + static_cast<size_t>(perm[e]) * noff,
+                                             tab.begin() + static_cast<size_t>(perm[e] + 1) * noff,
+                                             tab.begin() + static_cast<size_t>(perm[e - 1]) * noff);
+    if (start)
+      while (pad.size() % 16) pad.push_back(-1);
+    pad.push_back(perm[e]);
+  }
+  if (static_cast<double>(pad.size()) <= kMaxPadding * static_cast<double>(perm.size())) perm.swap(pad);
+}
+
+// mean number of MFMA passes (distinct blocks) per 16-row tile and offset in
+// the tile order (and that order's length, both cached in P)
 double tiled_passes(const PMat& P) {
   if (P.tile_passes >= 0.0) return P.tile_passes;
   const std::vector<int> off = column_offsets(P);
   std::vector<int> tab, perm;
-  tiled_table(P, off, tab, perm);
+  tiled_order(P, off, tab, perm);
   const int noff = static_cast<int>(off.size());
+  const int np = static_cast<int>(perm.size());
   long long passes = 0, slots = 0;
   std::vector<int> ids;
-  for (int t0 = 0; t0 < P.nbr; t0 += 16)
+  for (int t0 = 0; t0 < np; t0 += 16)
     for (int d = 0; d < noff; ++d) {
       ids.clear();
-      for (int c = t0; c < std::min(P.nbr, t0 + 16); ++c) {
+      for (int c = t0; c < std::min(np, t0 + 16); ++c) {
+        if (perm[c] < 0) continue;
         const int v = tab[static_cast<size_t>(perm[c]) * noff + d];
         if (v >= 0) ids.push_back(v);
       }
@@ -299,7 +325,13 @@ double tiled_passes(const PMat& P) {
       slots += 1;
     }
   P.tile_passes = slots ? static_cast<double>(passes) / slots : 0.0;
+  P.tile_perm_len = np;
   return P.tile_passes;
+}
+
+int tiled_perm_len(const PMat& P) {
+  tiled_passes(P);
+  return P.tile_perm_len;
 }
 
 // tiled storage (on top of pooled) for a matrix: TILED; or AUTO when pooled,
@@ -323,7 +355,7 @@ size_t matrix_bytes(const PMat& P, int bs, size_t elem, int storage) {
     const size_t noff = column_offsets(P).size();
     b += static_cast<size_t>(P.pool.size()) * tiled_block_elems(bs) * elem;
     b += static_cast<size_t>(P.nbr) * noff * sizeof(int) + std::max<size_t>(16, noff * sizeof(int));
-    b += std::max<size_t>(16, static_cast<size_t>(P.nbr) * sizeof(int));            // row order
+    b += std::max<size_t>(16, static_cast<size_t>(tiled_perm_len(P)) * sizeof(int));   // tile order
   }
   return b;
 }
@@ -356,7 +388,7 @@ void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, bool quad, Ti
   // rows with equal blocks at every offset side by side (stable: interior rows
   // keep their grid order), so that a 16-row tile needs one pass per offset
   std::vector<int> tab, perm;
-  tiled_table(P, off, tab, perm);
+  tiled_order(P, off, tab, perm);
   const long long nd = P.pool.size();
   T* blk = static_cast<T*>(D.alloc(static_cast<size_t>(nd) * tiled_block_elems(bs) * sizeof(T)));
   t.perm = static_cast<int*>(D.alloc(std::max<size_t>(16, perm.size() * sizeof(int))));
@@ -371,6 +403,7 @@ void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, bool quad, Ti
   D.unstage(pool, st);
   HIPCHK(hipStreamSynchronize(st));   // the host tables above must outlive their copies
   t.blk = blk;
+  t.nperm = static_cast<int>(perm.size());
   t.noff = noff;
   t.quad = quad;
 }
@@ -770,6 +803,7 @@ void set_tiled(BsrArgs<T, Vd>& a, const Tiled& t) {
   a.tperm = t.perm;
   a.toff = t.off;
   a.noff = t.noff;
+  a.tnrows = t.nperm;
   a.tquad = t.quad;
 }
 

@@ -51,6 +51,7 @@ struct PMat {
   std::vector<int> rp, ci, id;
   Pool pool;
   mutable double tile_passes = -1.0;   // cache of the device's tiling estimate (< 0: not computed)
+  mutable int tile_perm_len = -1;      // and of the length of its tile order (rows plus padding)
   int nnzb() const { return static_cast<int>(ci.size()); }
   int slot(int i, int j) const;     // -1 if (i, j) is not stored
   const double* block(int s) const { return pool.at(id[s]); }

@@ -536,8 +536,10 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
   const int col = lane & 15, kq = lane >> 4;
   const int q = col & ((1 << LKP) - 1);     // right-hand side of this column
-  const bool rv = e0 + (col >> LKP) < nrows && q < nk;
-  const int row = perm[rv ? e0 + (col >> LKP) : e0];
+  const int e = e0 + (col >> LKP);
+  const int pr = e < nrows ? perm[e] : -1;  // -1: a padded place of the tile order
+  const bool rv = pr >= 0 && q < nk;
+  const int row = rv ? pr : 0;
   const size_t qoff = static_cast<size_t>(rv ? q : 0) * stride;
   ACC acc[MW];
 #pragma unroll
@@ -1117,23 +1119,24 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   // FP32 products for FP32 / BF16 storage only: FP64 blocks keep FP64 products
   constexpr bool P32 = !std::is_same<TM, double>::value;
   constexpr int MT = (BS + 15) / 16;        // row tiles per tile
+  const int nt = a.tnrows > 0 ? a.tnrows : a.nrows;   // places of the tile order
   if (a.p32 && !P32) throw std::invalid_argument("bsr_tiled: FP32 products need FP32 or BF16 storage");
   if (a.x32 || a.out32) {                   // an FP32 vector in or out (smoothing residuals)
     if constexpr (P32 && BS % 16 == 0) {
       if (!a.p32 || nk != 1 || (a.x32 && a.out32) || (a.x32 && !a.tquad))
         throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products, one right-hand side and, "
                                     "for FP32 x, the quad layout");
-      const long long tiles = (a.nrows + 15) / 16;
+      const long long tiles = (nt + 15) / 16;
       const bool split = tiles < kSplitTiles;
       const int blocks = static_cast<int>((tiles * (split ? MT : 1) + kWaves - 1) / kWaves);
       if (blocks == 0) return;
 #define TILED32(XT_, OT_, Q_, X_, O_)                                                                          \
   if (split)                                                                                                   \
     k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_, true><<<blocks, kThreads, 0, st>>>(                             \
-        a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);                  \
+        nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);                  \
   else                                                                                                         \
     k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_><<<blocks, kThreads, 0, st>>>(                                   \
-        a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);
+        nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);
       if (a.x32) {
         TILED32(float, double, true, a.x32, a.out)
       } else if (a.tquad) {
@@ -1153,7 +1156,7 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   int lkp = 0;                              // log2 of the power of two >= nk
   while ((1 << lkp) < nk) ++lkp;
   const int rpt = 16 >> lkp;                // block rows per tile
-  const long long tiles = (a.nrows + rpt - 1) / rpt;
+  const long long tiles = (nt + rpt - 1) / rpt;
   const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
   if (blocks == 0) return;
   if (lkp == 0 && tiles < kSplitTiles) {    // few tiles: one wavefront per row tile
@@ -1162,20 +1165,20 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
       if (a.tquad) {
         if (a.p32)
           k_bsr_tiled<TM, BS, 0, true, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
-              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
         else
           k_bsr_tiled<TM, BS, 0, false, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
-              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
         check_launch("bsr_tiled");
         return;
       }
     }
     if (P32 && a.p32)
       k_bsr_tiled<TM, BS, 0, P32, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
-          a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+          nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
     else
       k_bsr_tiled<TM, BS, 0, false, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
-          a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+          nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
     check_launch("bsr_tiled");
     return;
   }
@@ -1186,19 +1189,19 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
       if (a.tquad) {                                                                                           \
         if (a.p32)                                                                                             \
           k_bsr_tiled<TM, BS, LK, true, double, double, true><<<blocks, kThreads, 0, st>>>(                    \
-              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
         else                                                                                                   \
           k_bsr_tiled<TM, BS, LK, false, double, double, true><<<blocks, kThreads, 0, st>>>(                   \
-              a.nrows, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
         break;                                                                                                 \
       }                                                                                                        \
     }                                                                                                          \
     if (P32 && a.p32)                                                                                          \
-      k_bsr_tiled<TM, BS, LK, P32><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm,       \
+      k_bsr_tiled<TM, BS, LK, P32><<<blocks, kThreads, 0, st>>>(nt, a.noff, a.toff, a.tab, a.tperm,       \
                                                                a.tblk, a.x, a.z, a.out, a.alpha, a.beta,       \
                                                                stride, nk);                                    \
     else                                                                                                       \
-      k_bsr_tiled<TM, BS, LK, false><<<blocks, kThreads, 0, st>>>(a.nrows, a.noff, a.toff, a.tab, a.tperm,     \
+      k_bsr_tiled<TM, BS, LK, false><<<blocks, kThreads, 0, st>>>(nt, a.noff, a.toff, a.tab, a.tperm,     \
                                                                  a.tblk, a.x, a.z, a.out, a.alpha, a.beta,     \
                                                                  stride, nk);                                  \
     break;

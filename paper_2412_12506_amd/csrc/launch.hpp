@@ -48,7 +48,8 @@ struct BsrArgs {
   // column offsets and the [nrows][noff] table of pool ids (-1: no block)
   const TM* tblk = nullptr;
   const int* tab = nullptr;
-  const int* tperm = nullptr; // block rows ordered by their row of tab
+  const int* tperm = nullptr; // block rows ordered by their row of tab, -1 where a tile is padded
+  int tnrows = 0;             // entries of tperm (0: nrows)
   const int* toff = nullptr;
   int noff = 0;
   bool p32 = false;           // tiled storage: FP32 products on the matrix cores
