@@ -57,6 +57,7 @@ struct Tiled {
   int* tab = nullptr;               // [rows][noff] pool ids, -1 where no block
   int* perm = nullptr;              // rows ordered by their row of tab, -1 where a tile is padded
   int nperm = 0;                    // entries of perm
+  int* rows = nullptr;              // the same order unpadded (for tiles of fewer than 16 rows)
   int* off = nullptr;               // column offsets
   int noff = 0;
   bool quad = false;                // pool in the 4-step k mapping (read with FP32 x)
@@ -285,8 +286,10 @@ void tiled_table(const PMat& P, const std::vector<int>& off, std::vector<int>& t
 // tile holds one table row, so one MFMA pass per offset: no tile takes longer
 // than the others, which matters where there are few tiles per SIMD.
 constexpr double kMaxPadding = 1.25;
-void tiled_order(const PMat& P, const std::vector<int>& off, std::vector<int>& tab, std::vector<int>& perm) {
+void tiled_order(const PMat& P, const std::vector<int>& off, std::vector<int>& tab, std::vector<int>& perm,
+                 std::vector<int>* rows = nullptr) {
   tiled_table(P, off, tab, perm);
+  if (rows) *rows = perm;
   const int noff = static_cast<int>(off.size());
   std::vector<int> pad;
   pad.reserve(perm.size() + perm.size() / 4 + 16);
@@ -356,6 +359,7 @@ size_t matrix_bytes(const PMat& P, int bs, size_t elem, int storage) {
     b += static_cast<size_t>(P.pool.size()) * tiled_block_elems(bs) * elem;
     b += static_cast<size_t>(P.nbr) * noff * sizeof(int) + std::max<size_t>(16, noff * sizeof(int));
     b += std::max<size_t>(16, static_cast<size_t>(tiled_perm_len(P)) * sizeof(int));   // tile order
+    if (tiled_perm_len(P) != P.nbr) b += std::max<size_t>(16, static_cast<size_t>(P.nbr) * sizeof(int));   // unpadded
   }
   return b;
 }
@@ -387,12 +391,18 @@ void make_tiled(DevHier& D, const PMat& P, int bs, bool transpose, bool quad, Ti
   const int noff = static_cast<int>(off.size());
   // rows with equal blocks at every offset side by side (stable: interior rows
   // keep their grid order), so that a 16-row tile needs one pass per offset
-  std::vector<int> tab, perm;
-  tiled_order(P, off, tab, perm);
+  std::vector<int> tab, perm, rows;
+  tiled_order(P, off, tab, perm, &rows);
   const long long nd = P.pool.size();
   T* blk = static_cast<T*>(D.alloc(static_cast<size_t>(nd) * tiled_block_elems(bs) * sizeof(T)));
   t.perm = static_cast<int*>(D.alloc(std::max<size_t>(16, perm.size() * sizeof(int))));
   HIPCHK(hipMemcpyAsync(t.perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  if (perm.size() != rows.size()) {
+    t.rows = static_cast<int*>(D.alloc(std::max<size_t>(16, rows.size() * sizeof(int))));
+    HIPCHK(hipMemcpyAsync(t.rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  } else {
+    t.rows = t.perm;
+  }
   t.tab = static_cast<int*>(D.alloc(tab.size() * sizeof(int)));
   t.off = static_cast<int*>(D.alloc(std::max<size_t>(16, off.size() * sizeof(int))));
   HIPCHK(hipMemcpyAsync(t.tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, st));
@@ -804,6 +814,7 @@ void set_tiled(BsrArgs<T, Vd>& a, const Tiled& t) {
   a.toff = t.off;
   a.noff = t.noff;
   a.tnrows = t.nperm;
+  a.trows = t.rows;
   a.tquad = t.quad;
 }
 

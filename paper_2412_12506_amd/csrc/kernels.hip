@@ -1155,8 +1155,12 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
     throw std::invalid_argument("bsr_tiled: the quad layout needs FP32 or BF16 storage and 16 | bs");
   int lkp = 0;                              // log2 of the power of two >= nk
   while ((1 << lkp) < nk) ++lkp;
+  // tiles of 16 / kp rows: the unpadded order (padding to 16 rows would leave
+  // empty tiles there)
+  const int* order = lkp > 0 && a.trows ? a.trows : a.tperm;
+  const int no = lkp > 0 && a.trows ? a.nrows : nt;
   const int rpt = 16 >> lkp;                // block rows per tile
-  const long long tiles = (nt + rpt - 1) / rpt;
+  const long long tiles = (no + rpt - 1) / rpt;
   const int blocks = static_cast<int>((tiles + kWaves - 1) / kWaves);
   if (blocks == 0) return;
   if (lkp == 0 && tiles < kSplitTiles) {    // few tiles: one wavefront per row tile
@@ -1165,20 +1169,20 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
       if (a.tquad) {
         if (a.p32)
           k_bsr_tiled<TM, BS, 0, true, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
-              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
         else
           k_bsr_tiled<TM, BS, 0, false, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
-              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
         check_launch("bsr_tiled");
         return;
       }
     }
     if (P32 && a.p32)
       k_bsr_tiled<TM, BS, 0, P32, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
-          nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+          no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
     else
       k_bsr_tiled<TM, BS, 0, false, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
-          nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+          no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
     check_launch("bsr_tiled");
     return;
   }
@@ -1189,19 +1193,19 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
       if (a.tquad) {                                                                                           \
         if (a.p32)                                                                                             \
           k_bsr_tiled<TM, BS, LK, true, double, double, true><<<blocks, kThreads, 0, st>>>(                    \
-              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
         else                                                                                                   \
           k_bsr_tiled<TM, BS, LK, false, double, double, true><<<blocks, kThreads, 0, st>>>(                   \
-              nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
         break;                                                                                                 \
       }                                                                                                        \
     }                                                                                                          \
     if (P32 && a.p32)                                                                                          \
-      k_bsr_tiled<TM, BS, LK, P32><<<blocks, kThreads, 0, st>>>(nt, a.noff, a.toff, a.tab, a.tperm,       \
+      k_bsr_tiled<TM, BS, LK, P32><<<blocks, kThreads, 0, st>>>(no, a.noff, a.toff, a.tab, order,       \
                                                                a.tblk, a.x, a.z, a.out, a.alpha, a.beta,       \
                                                                stride, nk);                                    \
     else                                                                                                       \
-      k_bsr_tiled<TM, BS, LK, false><<<blocks, kThreads, 0, st>>>(nt, a.noff, a.toff, a.tab, a.tperm,     \
+      k_bsr_tiled<TM, BS, LK, false><<<blocks, kThreads, 0, st>>>(no, a.noff, a.toff, a.tab, order,     \
                                                                  a.tblk, a.x, a.z, a.out, a.alpha, a.beta,     \
                                                                  stride, nk);                                  \
     break;

@@ -50,6 +50,7 @@ struct BsrArgs {
   const int* tab = nullptr;
   const int* tperm = nullptr; // block rows ordered by their row of tab, -1 where a tile is padded
   int tnrows = 0;             // entries of tperm (0: nrows)
+  const int* trows = nullptr; // the same order unpadded, nrows entries (tiles of fewer than 16 rows)
   const int* toff = nullptr;
   int noff = 0;
   bool p32 = false;           // tiled storage: FP32 products on the matrix cores
