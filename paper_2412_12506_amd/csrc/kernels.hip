@@ -88,6 +88,7 @@ __device__ __forceinline__ T group_bcast(T v, int g, int c) {
 
 constexpr int kWaves = 4;          // wavefronts per workgroup of the BSR kernels
 constexpr long long kSplitTiles = 1024;   // below this many tiles: one wavefront per row tile
+constexpr int kColSplitRows = 1024;       // at most this many block rows: a workgroup per block row
 constexpr int kThreads = 64 * kWaves;
 
 // ---------------------------------------------------------------------------
@@ -210,6 +211,80 @@ __global__ __launch_bounds__(kThreads) void k_bsr_fwd(int nrows, const int* __re
     } else {
       if (active) out[o] = alpha * sum;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward BSR kernel for matrices with few block rows (MODE 0; 16 | bs, bs >
+// 32): the kWaves wavefronts of a workgroup share one block row, each taking a
+// quarter of every block's columns, and add their partial rows in LDS.  A
+// wavefront issues the block loads of up to CH slots before its first product,
+// so a row costs about one memory latency per CH slots where the per-row
+// kernel waits once per slot; on small levels nothing else hides those waits.
+// ---------------------------------------------------------------------------
+template <typename TM, typename T, int BS, bool POOL>
+__global__ __launch_bounds__(kThreads) void k_bsr_fwd_cs(int nrows, const int* __restrict__ rows,
+                                                         const int* __restrict__ rp,
+                                                         const int* __restrict__ ci,
+                                                         const int* __restrict__ bid,
+                                                         const TM* __restrict__ blk, const T* x, const T* z,
+                                                         T* out, T alpha, T beta) {
+  using C = BlkCfg<TM, BS>;
+  constexpr int V = C::V, NV = C::NV;
+  static_assert(C::G == 1 && NV % kWaves == 0, "one block row per workgroup, columns in kWaves groups");
+  constexpr int NQ = NV / kWaves;                // vector loads per slot and wavefront
+  constexpr int NC = NQ * V;                     // columns per wavefront
+  constexpr int CH = sizeof(TM) == 8 ? 4 : 8;    // slots whose loads are in flight together
+  constexpr int NA = 4;
+  using VT = typename VecT<TM, V>::type;
+  __shared__ T part[kWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane < BS ? lane : 0;            // lanes past bs mirror row 0 and write nothing
+  const int idx = blockIdx.x;                    // one block row per workgroup (grid = nrows)
+  const int row = rows ? rows[idx] : idx;
+  const int s0 = rp[row];
+  const int cnt = rp[row + 1] - s0;
+  const int cx = w * NC + (lane < NC ? lane : 0);   // lane l < NC holds column w NC + l of x
+  T acc[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) acc[i] = T(0);
+  for (int k0 = 0; k0 < cnt; k0 += CH) {
+    VT a[CH][NQ];
+    T xv[CH];
+    // every load from a valid slot (clamped); a slot past the row's last one
+    // gets x = 0, so no branch separates the loads from the products
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const bool in = k0 + t < cnt;
+      const int sl = in ? s0 + k0 + t : s0;
+      const size_t boff = static_cast<size_t>(POOL ? bid[sl] : sl) * (BS * BS);
+      const VT* bp = reinterpret_cast<const VT*>(blk + boff) + r;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) a[t][q] = bp[(w * NQ + q) * BS];
+      const T xl = x[static_cast<size_t>(ci[sl]) * BS + cx];
+      xv[t] = in ? xl : T(0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          acc[(q * V + v) % NA] += static_cast<T>(elem(a[t][q], v)) * readlane(xv[t], q * V + v);
+    }
+  }
+  T sum = acc[0];
+#pragma unroll
+  for (int i = 1; i < NA; ++i) sum += acc[i];
+  part[w][lane] = sum;
+  __syncthreads();
+  if (w == 0 && lane < BS) {
+    T y = part[0][lane];
+#pragma unroll
+    for (int i = 1; i < kWaves; ++i) y += part[i][lane];
+    const size_t o = static_cast<size_t>(row) * BS + lane;
+    out[o] = beta != T(0) ? alpha * y + beta * z[o] : alpha * y;
   }
 }
 
@@ -1095,6 +1170,18 @@ void launch_fwd_bs(const BsrArgs<TM, T>& a, hipStream_t st) {
   const long long waves = (a.nrows + G - 1) / G;
   const int blocks = static_cast<int>((waves + kWaves - 1) / kWaves);
   if (blocks == 0) return;
+  if constexpr (std::is_same<T, double>::value && BS % 16 == 0 && BS > 32 && BlkCfg<TM, BS>::NV % kWaves == 0) {
+    if (!a.dinv && a.nrows <= kColSplitRows) {   // few block rows: a workgroup per row
+      if (a.bid)
+        k_bsr_fwd_cs<TM, T, BS, true><<<a.nrows, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.bid, a.blk,
+                                                                     a.x, a.z, a.out, a.alpha, a.beta);
+      else
+        k_bsr_fwd_cs<TM, T, BS, false><<<a.nrows, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, nullptr,
+                                                                      a.blk, a.x, a.z, a.out, a.alpha, a.beta);
+      check_launch("bsr_fwd_cs");
+      return;
+    }
+  }
   if (a.dinv && a.bid)
     k_bsr_fwd<TM, T, BS, 1, true><<<blocks, kThreads, 0, st>>>(a.nrows, a.rows, a.rp, a.ci, a.bid, a.blk, a.x,
                                                                a.z, a.out, a.alpha, a.beta, a.dinv, a.dbid,
