@@ -82,6 +82,7 @@ struct DevLevel {
   Tiled tA, tS, tST;                // tiled storage (tab null when not tiled)
   bool p32 = false;                 // FP32 products in the tiled applies of the V-cycle
   float* r32 = nullptr;             // FP32 smoothing residual for those products (levels with tiled A and S, 16 | bs)
+  float* x32 = nullptr;             // and the FP32 copy of x that the A applies read there (kept by x's producers)
   std::vector<int*> colour_rows;    // device lists per colour
   std::vector<int> colour_count;
   double* x = nullptr;              // level vectors are FP64 in both precisions
@@ -464,7 +465,8 @@ void upload_level(DevHier& D, DevLevel& dl, const HostLevel& hl, bool bottom, bo
   dl.nnzA = hl.A.nnzb();
   dl.rpA = up_ints(hl.A.rp);
   dl.ciA = up_ints(hl.A.ci);
-  dl.valA = place(TA{}, hl.A, false, dl.bidA, dl.tA, use_tiled(hl.A, hl.bs, sizeof(TA), storage), false);
+  // where the smoothing reads FP32 vectors (quad_S) the operator reads the FP32 copy of x too: 4-step layout
+  dl.valA = place(TA{}, hl.A, false, dl.bidA, dl.tA, use_tiled(hl.A, hl.bs, sizeof(TA), storage), quad_S);
   if (!bottom) {
     dl.nnzS = hl.S.nnzb();
     dl.rpS = up_ints(hl.S.rp);
@@ -547,7 +549,7 @@ size_t estimate_from_host(const HostHierarchy& H, int prec) {
       b += N * N * 8;
     }
     b += 4 * N * 8;
-    if (fp32_residual_level(H, l, prec)) b += N * 4;
+    if (fp32_residual_level(H, l, prec)) b += N * 8;   // FP32 residual and FP32 copy of x
     b += (static_cast<size_t>(1) << L.em.dim) * L.bss * L.bss * 8 + 2 * L.em.q1 * L.em.q1 * 8;
   }
   const HostLevel& F = H.levels[0];
@@ -722,6 +724,7 @@ void upload(ldgmg_hier* h, hipStream_t st) {
     if (fp32_residual_level(H, l, D->prec)) {
       if (!D->L[l].tA.tab || !D->L[l].tS.tab) throw std::logic_error("tiled storage differs from its estimate");
       D->L[l].r32 = static_cast<float*>(D->alloc(static_cast<size_t>(D->L[l].N) * sizeof(float)));
+      D->L[l].x32 = static_cast<float*>(D->alloc(static_cast<size_t>(D->L[l].N) * sizeof(float)));
     }
   }
   const HostLevel& F = H.levels[0];
@@ -753,6 +756,7 @@ void upload(ldgmg_hier* h, hipStream_t st) {
       expand_tiled<double>(nd, F.bs, pool, tb, false, false, st);
       D->t64 = f.tA;
       D->t64.blk = tb;
+      D->t64.quad = false;                  // the 2-step k layout (FP64 x), whatever A's own
     }
     D->unstage(pool, st);
     D->unstage(ids, st);
@@ -846,11 +850,14 @@ BsrArgs<T, Vd> argsS(const DevLevel& L) {
   return a;
 }
 
-// out = b - A x (or, given out32, the same rounded to FP32 into out32 only)
+// out = b - A x (or, given out32, the same rounded to FP32 into out32 only);
+// x32 (optional): FP32 x read in place of x (FP32 products: the same operands)
 template <typename T>
-void residual(const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st, float* out32 = nullptr) {
+void residual(const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st, float* out32 = nullptr,
+              const float* x32 = nullptr) {
   BsrArgs<T, Vd> a = argsA<T>(L);
-  a.x = x;
+  a.x = x32 ? nullptr : x;
+  a.x32 = x32;
   a.z = b;
   a.out = out32 ? nullptr : out;
   a.out32 = out32;
@@ -861,20 +868,21 @@ void residual(const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t 
 
 template <typename T>
 void residual(DevHier& D, const DevLevel& L, const Vd* x, const Vd* b, Vd* out, hipStream_t st,
-              float* out32 = nullptr) {
+              float* out32 = nullptr, const float* x32 = nullptr) {
   ProfScope ps(D, L, st, K_A);
-  residual<T>(L, x, b, out, st, out32);
+  residual<T>(L, x, b, out, st, out32, x32);
 }
 
-// out = alpha S x + beta z   (transposed: S^T)
+// out = alpha S x + beta z   (transposed: S^T); out2 (optional, tiled): an FP32 copy of out
 template <typename T>
 void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* out, Vd alpha, Vd beta,
-             hipStream_t st, const float* x32 = nullptr) {
+             hipStream_t st, const float* x32 = nullptr, float* out2 = nullptr) {
   BsrArgs<T, Vd> a = argsS<T>(L);
   a.x = x32 ? nullptr : x;
   a.x32 = x32;
   a.z = z;
   a.out = out;
+  a.out2 = out2;
   a.alpha = alpha;
   a.beta = beta;
   if (transposed && L.valST) {
@@ -891,9 +899,9 @@ void apply_S(const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* o
 
 template <typename T>
 void apply_S(DevHier& D, const DevLevel& L, bool transposed, const Vd* x, const Vd* z, Vd* out, Vd alpha,
-             Vd beta, hipStream_t st, const float* x32 = nullptr) {
+             Vd beta, hipStream_t st, const float* x32 = nullptr, float* out2 = nullptr) {
   ProfScope ps(D, L, st, transposed ? K_ST : K_SF);
-  apply_S<T>(L, transposed, x, z, out, alpha, beta, st, x32);
+  apply_S<T>(L, transposed, x, z, out, alpha, beta, st, x32, out2);
 }
 
 // one smoothing step on level L with x (in/out), b.  `zero_x`: x is known to be 0.
@@ -907,15 +915,17 @@ Vd* smooth_step(const Ctx& c, DevLevel& L, Vd* x, const Vd* b, bool forward, boo
   Vd* r = L.r;
   Vd* t = L.t;
   if (sm == LDGMG_SMOOTH_SAI) {
+    // with FP32 products the applies round their vector operand to FP32
+    // anyway: the residual is written in FP32 only and read as such, and the
+    // producers of x keep its FP32 copy for the operator applies
+    float* r32 = L.p32 ? L.r32 : nullptr;
+    float* x32 = L.p32 ? L.x32 : nullptr;
     if (zero_x) {             // x = S b  (eq:B1) or S^T b (eq:BT) from x = 0
-      apply_S<TS>(c.D, L, !forward, b, nullptr, x, 1.0, 0.0, c.st);
+      apply_S<TS>(c.D, L, !forward, b, nullptr, x, 1.0, 0.0, c.st, nullptr, x32);
       return x;
     }
-    // with FP32 products the smoother apply rounds r to FP32 anyway: the
-    // residual is written in FP32 only, and read as such
-    float* r32 = L.p32 ? L.r32 : nullptr;
-    residual<T>(c.D, L, x, b, r, c.st, r32);
-    apply_S<TS>(c.D, L, !forward, r, x, x, 1.0, 1.0, c.st, r32);
+    residual<T>(c.D, L, x, b, r, c.st, r32, x32);
+    apply_S<TS>(c.D, L, !forward, r, x, x, 1.0, 1.0, c.st, r32, x32);
     return x;
   }
   if (sm == LDGMG_SMOOTH_JACOBI) {
@@ -1002,13 +1012,18 @@ void vcycle_level(const Ctx& c, int l) {
       x = L.x;
     }
   };
-  if (P.nu1 == 0) fill_zero(x, L.N, c.st);
+  // the FP32 copy of x (SAI smoothing with FP32 products) follows x through the cycle
+  float* x32 = P.smoother == LDGMG_SMOOTH_SAI && L.p32 ? L.x32 : nullptr;
+  if (P.nu1 == 0) {
+    fill_zero(x, L.N, c.st);
+    if (x32) fill_zero(x32, L.N, c.st);
+  }
   for (int s = 0; s < P.nu1; ++s) keep(smooth_step<T, TS>(c, L, x, b, pre_fwd, s == 0));
-  residual<T>(c.D, L, x, b, L.r, c.st);
+  residual<T>(c.D, L, x, b, L.r, c.st, nullptr, x32);
   DevLevel& Lc = c.D.L[l + 1];
   restrict_op<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, L.r, Lc.b, c.st);
   vcycle_level<T, TS>(c, l + 1);
-  prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, Lc.x, x, c.st);
+  prolong_add<Vd>(P.dim, Lc.n, L.ncomp, L.bss, Lc.q1, Lc.P1, Lc.Ic, Lc.x, x, c.st, x32);
   for (int s = 0; s < P.nu2; ++s) keep(smooth_step<T, TS>(c, L, x, b, post_fwd, false));
 }
 
@@ -1648,6 +1663,7 @@ void level_op_t(const Ctx& c, int l, int op, const void* in1, const void* in2, v
     case LDGMG_OP_SMOOTH_REV: {
       if (bottom) throw std::invalid_argument("no smoother on the bottom level");
       HIPCHK(hipMemcpyAsync(o, a, static_cast<size_t>(L.N) * sizeof(Vd), hipMemcpyDeviceToDevice, c.st));
+      if (c.H.prob.smoother == LDGMG_SMOOTH_SAI && L.p32 && L.x32) cast<double, float>(L.N, o, L.x32, c.st);
       Vd* res = smooth_step<T, TS>(c, L, o, b, op == LDGMG_OP_SMOOTH_FWD, false);
       if (res != o)
         HIPCHK(hipMemcpyAsync(o, res, static_cast<size_t>(L.N) * sizeof(Vd), hipMemcpyDeviceToDevice, c.st));

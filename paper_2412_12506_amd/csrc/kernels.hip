@@ -589,7 +589,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
                                                         const int* __restrict__ perm,
                                                         const TM* __restrict__ blk, const XT* x,
                                                         const double* z, OT* out, double alpha,
-                                                        double beta, long long stride, int nk) {
+                                                        double beta, long long stride, int nk,
+                                                        float* __restrict__ out2) {
   static_assert(std::is_same<XT, double>::value || (P32 && QUAD && BS % 16 == 0), "FP32 x: FP32 products, quad layout");
   static_assert(!QUAD || BS % 16 == 0, "the quad layout needs 16 | bs");
   static_assert(!SPLIT || LKP == 0, "one wavefront per row tile: one right-hand side");
@@ -687,6 +688,10 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
         } else {
           reinterpret_cast<double2*>(op)[0] = double2{y[m][0], y[m][1]};
           reinterpret_cast<double2*>(op)[1] = double2{y[m][2], y[m][3]};
+          if (out2)                          // the FP32 copy (wavefront-uniform test)
+            *reinterpret_cast<float4*>(out2 + rb + 16 * (mw + m) + 4 * kq) =
+                float4{static_cast<float>(y[m][0]), static_cast<float>(y[m][1]), static_cast<float>(y[m][2]),
+                       static_cast<float>(y[m][3])};
         }
       }
       return;
@@ -700,7 +705,9 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
       const int r = 16 * (mw + m) + (P32 ? 4 * kq + i : kq + 4 * i);
       if (r < BS) {
         const double y = alpha * static_cast<double>(acc[m][i]);
-        out[rb + r] = static_cast<OT>(beta != 0.0 ? __builtin_fma(beta, z[rb + r], y) : y);
+        const OT v = static_cast<OT>(beta != 0.0 ? __builtin_fma(beta, z[rb + r], y) : y);
+        out[rb + r] = v;
+        if (out2) out2[rb + r] = static_cast<float>(v);
       }
     }
 }
@@ -809,7 +816,7 @@ __global__ void k_restrict(int dim, int nc, int ncomp, int bss, const T* __restr
 // prolongation and correction x_f += I x_c: one thread per (fine element, component, dof)
 template <typename T>
 __global__ void k_prolong_add(int dim, int nc, int ncomp, int bss, const T* __restrict__ Ic,
-                              const T* __restrict__ xc, T* __restrict__ xf) {
+                              const T* __restrict__ xc, T* __restrict__ xf, float* __restrict__ xf32) {
   const int nf = 2 * nc;
   long long nfe = nf;
   for (int k = 1; k < dim; ++k) nfe *= nf;
@@ -828,7 +835,9 @@ __global__ void k_prolong_add(int dim, int nc, int ncomp, int bss, const T* __re
   const T* xce = xc + (K * ncomp + comp) * bss;
   T sum = T(0);
   for (int a = 0; a < bss; ++a) sum += I[a] * xce[a];
-  xf[tid] += sum;
+  const T y = xf[tid] + sum;
+  xf[tid] = y;
+  if (xf32) xf32[tid] = static_cast<float>(y);
 }
 
 // Sum-factorised transfers (bss = (p+1)^d <= 64), one lane per scalar
@@ -883,7 +892,8 @@ struct XferLane {
 // per child index c_k in {0, 1}, and one shuffle of an input value serves both.
 template <typename T, int Q1, int DIM>
 __global__ __launch_bounds__(256) void k_prolong_tree(int nc, int ncomp, const T* __restrict__ P1,
-                                                      const T* __restrict__ xc, T* __restrict__ xf, unsigned nwork) {
+                                                      const T* __restrict__ xc, T* __restrict__ xf, unsigned nwork,
+                                                      float* __restrict__ xf32) {
   using S = XferShape<Q1, DIM>;
   const XferLane<Q1, DIM> L(nc, ncomp, nwork);
   T old[S::NCH], v[S::NCH];
@@ -915,7 +925,11 @@ __global__ __launch_bounds__(256) void k_prolong_tree(int nc, int ncomp, const T
   }
 #pragma unroll
   for (int cp = 0; cp < S::NCH; ++cp)
-    if (L.valid) xf[L.fine[cp]] = old[cp] + v[cp];
+    if (L.valid) {
+      const T y = old[cp] + v[cp];
+      xf[L.fine[cp]] = y;
+      if (xf32) xf32[L.fine[cp]] = static_cast<float>(y);   // the FP32 copy, when kept
+    }
 }
 
 // r_c = I^T r_f (Section 2.2: the restriction is the adjoint of the
@@ -1104,6 +1118,12 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize_many(int nparts, const
   if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
+__global__ void k_fill_zero_f(long long n, float* __restrict__ p) {
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    p[i] = 0.0f;
+}
+
 __global__ void k_fill_zero(long long n, double* __restrict__ p) {
   for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<long long>(gridDim.x) * blockDim.x)
@@ -1210,7 +1230,7 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
   if (a.p32 && !P32) throw std::invalid_argument("bsr_tiled: FP32 products need FP32 or BF16 storage");
   if (a.x32 || a.out32) {                   // an FP32 vector in or out (smoothing residuals)
     if constexpr (P32 && BS % 16 == 0) {
-      if (!a.p32 || nk != 1 || (a.x32 && a.out32) || (a.x32 && !a.tquad))
+      if (!a.p32 || nk != 1 || (a.x32 && !a.tquad))
         throw std::invalid_argument("bsr_tiled: FP32 vectors need FP32 products, one right-hand side and, "
                                     "for FP32 x, the quad layout");
       const long long tiles = (nt + 15) / 16;
@@ -1220,11 +1240,13 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
 #define TILED32(XT_, OT_, Q_, X_, O_)                                                                          \
   if (split)                                                                                                   \
     k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_, true><<<blocks, kThreads, 0, st>>>(                             \
-        nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);                  \
+        nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1, a.out2);                  \
   else                                                                                                         \
     k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_><<<blocks, kThreads, 0, st>>>(                                   \
-        nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1);
-      if (a.x32) {
+        nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1, a.out2);
+      if (a.x32 && a.out32) {
+        TILED32(float, float, true, a.x32, a.out32)
+      } else if (a.x32) {
         TILED32(float, double, true, a.x32, a.out)
       } else if (a.tquad) {
         TILED32(double, float, true, a.x, a.out32)
@@ -1256,20 +1278,20 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
       if (a.tquad) {
         if (a.p32)
           k_bsr_tiled<TM, BS, 0, true, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
-              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk, a.out2);
         else
           k_bsr_tiled<TM, BS, 0, false, double, double, true, true><<<bsplit, kThreads, 0, st>>>(
-              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk, a.out2);
         check_launch("bsr_tiled");
         return;
       }
     }
     if (P32 && a.p32)
       k_bsr_tiled<TM, BS, 0, P32, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
-          no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+          no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk, a.out2);
     else
       k_bsr_tiled<TM, BS, 0, false, double, double, false, true><<<bsplit, kThreads, 0, st>>>(
-          no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);
+          no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk, a.out2);
     check_launch("bsr_tiled");
     return;
   }
@@ -1280,21 +1302,21 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
       if (a.tquad) {                                                                                           \
         if (a.p32)                                                                                             \
           k_bsr_tiled<TM, BS, LK, true, double, double, true><<<blocks, kThreads, 0, st>>>(                    \
-              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk, a.out2);  \
         else                                                                                                   \
           k_bsr_tiled<TM, BS, LK, false, double, double, true><<<blocks, kThreads, 0, st>>>(                   \
-              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk);  \
+              no, a.noff, a.toff, a.tab, order, a.tblk, a.x, a.z, a.out, a.alpha, a.beta, stride, nk, a.out2);  \
         break;                                                                                                 \
       }                                                                                                        \
     }                                                                                                          \
     if (P32 && a.p32)                                                                                          \
       k_bsr_tiled<TM, BS, LK, P32><<<blocks, kThreads, 0, st>>>(no, a.noff, a.toff, a.tab, order,       \
                                                                a.tblk, a.x, a.z, a.out, a.alpha, a.beta,       \
-                                                               stride, nk);                                    \
+                                                               stride, nk, a.out2);                                    \
     else                                                                                                       \
       k_bsr_tiled<TM, BS, LK, false><<<blocks, kThreads, 0, st>>>(no, a.noff, a.toff, a.tab, order,     \
                                                                  a.tblk, a.x, a.z, a.out, a.alpha, a.beta,     \
-                                                                 stride, nk);                                  \
+                                                                 stride, nk, a.out2);                                  \
     break;
     TILED(0) TILED(1) TILED(2) TILED(3) TILED(4)
 #undef TILED
@@ -1458,12 +1480,12 @@ void expand_tiled(long long nblk, int bs, const double* pool, T* out, bool trans
 
 template <typename T, int Q1, int DIM>
 void launch_xfer_tree(bool prolong, int nc, int ncomp, long long nwork, const T* P1, const T* in, T* out,
-                      hipStream_t st) {
+                      hipStream_t st, float* out32) {
   constexpr int G = XferShape<Q1, DIM>::G;
   const long long waves = (nwork + G - 1) / G;
   const int blocks = static_cast<int>((waves + 3) / 4);
   if (prolong)
-    k_prolong_tree<T, Q1, DIM><<<blocks, 256, 0, st>>>(nc, ncomp, P1, in, out, static_cast<unsigned>(nwork));
+    k_prolong_tree<T, Q1, DIM><<<blocks, 256, 0, st>>>(nc, ncomp, P1, in, out, static_cast<unsigned>(nwork), out32);
   else
     k_restrict_tree<T, Q1, DIM><<<blocks, 256, 0, st>>>(nc, ncomp, P1, in, out, static_cast<unsigned>(nwork));
   check_launch(prolong ? "prolong_tree" : "restrict_tree");
@@ -1473,22 +1495,22 @@ void launch_xfer_tree(bool prolong, int nc, int ncomp, long long nwork, const T*
 // tree over the children; returns false for the others.
 template <typename T>
 bool xfer_tree(bool prolong, int dim, int q1, int nc, int ncomp, long long nwork, const T* P1, const T* in,
-               T* out, hipStream_t st) {
+               T* out, hipStream_t st, float* out32 = nullptr) {
   if (nwork >= (1LL << 31)) throw std::invalid_argument("transfer: more than 2^31 coarse element components");
   if (dim == 3) {
     switch (q1) {
-      case 2: launch_xfer_tree<T, 2, 3>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
-      case 3: launch_xfer_tree<T, 3, 3>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
-      case 4: launch_xfer_tree<T, 4, 3>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+      case 2: launch_xfer_tree<T, 2, 3>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
+      case 3: launch_xfer_tree<T, 3, 3>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
+      case 4: launch_xfer_tree<T, 4, 3>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
       default: return false;
     }
   }
   switch (q1) {
-    case 2: launch_xfer_tree<T, 2, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
-    case 3: launch_xfer_tree<T, 3, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
-    case 4: launch_xfer_tree<T, 4, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
-    case 5: launch_xfer_tree<T, 5, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
-    case 6: launch_xfer_tree<T, 6, 2>(prolong, nc, ncomp, nwork, P1, in, out, st); return true;
+    case 2: launch_xfer_tree<T, 2, 2>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
+    case 3: launch_xfer_tree<T, 3, 2>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
+    case 4: launch_xfer_tree<T, 4, 2>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
+    case 5: launch_xfer_tree<T, 5, 2>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
+    case 6: launch_xfer_tree<T, 6, 2>(prolong, nc, ncomp, nwork, P1, in, out, st, out32); return true;
     default: return false;
   }
 }
@@ -1506,14 +1528,14 @@ void restrict_op(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const
 
 template <typename T>
 void prolong_add(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* xc, T* xf,
-                 hipStream_t st) {
+                 hipStream_t st, float* xf32) {
   long long nfe = 2 * nc;
   for (int k = 1; k < dim; ++k) nfe *= 2 * nc;
   long long nce = nc;
   for (int k = 1; k < dim; ++k) nce *= nc;
-  if (xfer_tree<T>(true, dim, q1, nc, ncomp, nce * ncomp, P1, xc, xf, st)) return;
+  if (xfer_tree<T>(true, dim, q1, nc, ncomp, nce * ncomp, P1, xc, xf, st, xf32)) return;
   const long long total = nfe * ncomp * bss;
-  k_prolong_add<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, xc, xf);
+  k_prolong_add<T><<<static_cast<int>((total + 255) / 256), 256, 0, st>>>(dim, nc, ncomp, bss, Ic, xc, xf, xf32);
   check_launch("prolong");
 }
 
@@ -1531,6 +1553,13 @@ void dot_partial(long long n, const double* a, const double* b, double* partial,
 void finalize(const double* partial, double* scal, int op, int dst, int a, hipStream_t st) {
   k_finalize<<<1, kRedThreads, 0, st>>>(kRedBlocks, partial, scal, op, dst, a);
   check_launch("finalize");
+}
+
+void fill_zero(float* p, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  const long long want = (n + 255) / 256;
+  k_fill_zero_f<<<static_cast<int>(want < 4096 ? want : 4096), 256, 0, st>>>(n, p);
+  check_launch("fill_zero");
 }
 
 void fill_zero(double* p, long long n, hipStream_t st) {
@@ -1610,7 +1639,7 @@ template void expand_blocks<double>(long long, int, const int*, const double*, d
 template void restrict_op<double>(int, int, int, int, int, const double*, const double*, const double*, double*,
                                   hipStream_t);
 template void prolong_add<double>(int, int, int, int, int, const double*, const double*, const double*, double*,
-                                  hipStream_t);
+                                  hipStream_t, float*);
 template void dense_gemv<float>(int, const double*, const float*, float*, hipStream_t);
 template void dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);
 template void cast<double, float>(long long, const double*, float*, hipStream_t);

@@ -56,6 +56,7 @@ struct BsrArgs {
   bool p32 = false;           // tiled storage: FP32 products on the matrix cores
   bool tquad = false;         // the tiled pool uses the 4-step k mapping (16 | bs; required for x32)
   const float* x32 = nullptr; // with p32, one right-hand side and 16 | bs: FP32 input in place of x
+  float* out2 = nullptr;      // tiled: an FP32 copy of out (rounded to nearest), or null
   float* out32 = nullptr;     // ... or FP32 output in place of out
   T omega = T(1);
 };
@@ -83,9 +84,10 @@ void expand_blocks(long long nslots, int bs, const int* ids, const double* pool,
 template <typename T>
 void restrict_op(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* rf, T* rc,
                  hipStream_t st);
+// xf32 (optional): an FP32 copy of x_f, written with the result (rounded to nearest)
 template <typename T>
 void prolong_add(int dim, int nc, int ncomp, int bss, int q1, const T* P1, const T* Ic, const T* xc, T* xf,
-                 hipStream_t st);
+                 hipStream_t st, float* xf32 = nullptr);
 template <typename T> void dense_gemv(int N, const double* P, const T* in, T* out, hipStream_t st);
 
 void dot_partial(long long n, const double* a, const double* b, double* partial, hipStream_t st);
@@ -101,6 +103,7 @@ constexpr int kScalTol2 = 12;     // rtol^2 b.b
 constexpr int kScalMaxit = 13;
 constexpr int kScalRRFinal = 14;  // r.r when the recurrence stopped
 void fill_zero(double* p, long long n, hipStream_t st);
+void fill_zero(float* p, long long n, hipStream_t st);
 // scal: frozen 0, iterations 0, status -1, tol2 and maxit set
 void cg_init(double* scal, double tol2, int maxit, hipStream_t st);
 // after an iteration's r.r: count it, record sqrt|r.z| in hist (cap entries),
