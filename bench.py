@@ -144,11 +144,13 @@ def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_pr
             # with FP32 products)
             vec = 3 * N * 8 if kind != "A64" else 2 * N * 8
             if fp32_products and tiled and bs % 16 == 0 and storage["tiled_A"] and storage["tiled_S"]:
-                # the smoothing residuals are FP32: B and B^T read r in FP32;
+                # the smoothing vectors are FP32 where they are only operands:
+                # B and B^T read r in FP32, read and write x in FP64 and write
+                # its FP32 copy; the A launches read that copy and b (FP64), and
                 # of the 6 fine A launches of a V-cycle (nu1 = nu2 = 3, x = 0 at
                 # entry) 5 write r in FP32 and the one before restriction in FP64
-                vec = (4 + 8 + 8) * N if kind in ("S", "ST") else \
-                    ((5 * (8 + 8 + 4) + (8 + 8 + 8)) * N) // 6 if kind == "A" else vec
+                vec = (4 + 8 + 8 + 4) * N if kind in ("S", "ST") else \
+                    ((5 * (4 + 8 + 4) + (4 + 8 + 8)) * N) // 6 if kind == "A" else vec
             idx = (ne + 1) * 4 + nnzb * 4
             blocks = pool * bs * bs * ebk + nnzb * 4 if pool else nnzb * bs * bs * ebk
             byts = blocks + idx + vec
