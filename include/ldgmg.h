@@ -233,11 +233,13 @@ int ldgmg_cg_graph(ldgmg_handle h, int check_every);
  * need more iterations at high coefficient contrast.  With an SAI smoother,
  * on levels whose A and B are both tiled and whose block size is a multiple of
  * 16, the smoothing residual (consumed only by the B or B^T apply, which rounds
- * it to FP32 anyway) is written in FP32 to a per-level buffer that ldgmg_upload
- * allocates for such levels whether or not this mode is on (N * 4 bytes,
- * counted by ldgmg_upload_bytes).  Off by default; needs FP32 or BF16S
- * precision (LDGMG_EINVAL otherwise).  Kept across ldgmg_unload /
- * ldgmg_upload. */
+ * it to FP32 anyway) is written in FP32, and the smoother applies and the
+ * prolongation keep an FP32 copy of the iterate beside it, which the operator
+ * applies read (the same operand values as rounding the FP64 iterate): two
+ * per-level buffers that ldgmg_upload allocates for such levels whether or not
+ * this mode is on (N * 8 bytes, counted by ldgmg_upload_bytes).  Off by
+ * default; needs FP32 or BF16S precision (LDGMG_EINVAL otherwise).  Kept
+ * across ldgmg_unload / ldgmg_upload. */
 int ldgmg_fp32_products(ldgmg_handle h, int enable);
 
 /* Device bytes the handle holds now (0 when it holds no device data): what
