@@ -833,6 +833,7 @@ BsrArgs<T, Vd> argsA(const DevLevel& L) {
   a.blk = static_cast<const T*>(L.valA);
   set_tiled(a, L.tA);
   a.p32 = L.p32;
+  a.tpair = true;
   return a;
 }
 template <typename T>

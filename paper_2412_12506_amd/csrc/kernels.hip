@@ -88,6 +88,7 @@ __device__ __forceinline__ T group_bcast(T v, int g, int c) {
 
 constexpr int kWaves = 4;          // wavefronts per workgroup of the BSR kernels
 constexpr long long kSplitTiles = 1024;   // below this many tiles: one wavefront per row tile
+constexpr long long kPairTiles = 8192;    // from this many: two tiles per wavefront (FP32 blocks)
 constexpr int kColSplitRows = 1024;       // at most this many block rows: a workgroup per block row
 constexpr int kThreads = 64 * kWaves;
 
@@ -574,84 +575,13 @@ __device__ __forceinline__ void load_x(const XT* xp, int kq, bool use, OP (&xb)[
   }
 }
 
-// P32: FP32 products (operands rounded to FP32: the stored FP32 / BF16 entries
-// exactly, the vector entries to nearest) accumulated in FP32; the result is
-// combined with z in FP64.  XT / OT: element type of x / out; FP32 x (already
-// rounded by its producer, so the same operand values) or FP32 out only with
-// FP32 products, one right-hand side and 16 | bs.  QUAD: the matrix is laid out
-// with the 4-step k mapping (required for FP32 x).  SPLIT: one wavefront per
-// row tile of a tile (MT wavefronts per tile, one right-hand side), for
-// matrices with too few tiles to fill the device; the products are the same.
-template <typename TM, int BS, int LKP, bool P32, typename XT = double, typename OT = double, bool QUAD = false,
-          bool SPLIT = false>
-__global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
-                                                        const int* __restrict__ tab,
-                                                        const int* __restrict__ perm,
-                                                        const TM* __restrict__ blk, const XT* x,
-                                                        const double* z, OT* out, double alpha,
-                                                        double beta, long long stride, int nk,
-                                                        float* __restrict__ out2) {
-  static_assert(std::is_same<XT, double>::value || (P32 && QUAD && BS % 16 == 0), "FP32 x: FP32 products, quad layout");
-  static_assert(!QUAD || BS % 16 == 0, "the quad layout needs 16 | bs");
-  static_assert(!SPLIT || LKP == 0, "one wavefront per row tile: one right-hand side");
-  constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
-  constexpr int MW = SPLIT ? 1 : MT;            // row tiles of this wavefront
-  constexpr int MG = SPLIT ? 1 : sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
-  using OP = typename std::conditional<P32, float, double>::type;
-  using ACC = typename std::conditional<P32, v4f, v4d>::type;
-  const int lane = threadIdx.x & 63;
-  // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous
-  // range of tiles so that neighbouring rows share its L2
-  const int nb = gridDim.x, n8 = nb >> 3;
-  const int b = blockIdx.x;
-  const int lb = b < 8 * n8 ? (b & 7) * n8 + (b >> 3) : b;
-  const int wv = lb * kWaves + (threadIdx.x >> 6);
-  const int tile = SPLIT ? wv / MT : wv;
-  const int mw = SPLIT ? wv - tile * MT : 0;   // first row tile of this wavefront
-  const int e0 = tile * (16 >> LKP);        // 16 / kp block rows per tile
-  if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
-  const int col = lane & 15, kq = lane >> 4;
-  const int q = col & ((1 << LKP) - 1);     // right-hand side of this column
-  const int e = e0 + (col >> LKP);
-  const int pr = e < nrows ? perm[e] : -1;  // -1: a padded place of the tile order
-  const bool rv = pr >= 0 && q < nk;
-  const int row = rv ? pr : 0;
-  const size_t qoff = static_cast<size_t>(rv ? q : 0) * stride;
-  ACC acc[MW];
-#pragma unroll
-  for (int m = 0; m < MW; ++m) acc[m] = ACC{0, 0, 0, 0};
-  for (int d = 0; d < noff; ++d) {
-    const int o = off[d];
-    const int t = tab[static_cast<size_t>(row) * noff + d];
-    const int myid = rv ? t : -1;
-    unsigned long long rem = __ballot(myid >= 0) & 0xFFFFull;
-    while (rem) {                           // one MFMA pass per distinct block of this offset
-      const int c0 = __ffsll(static_cast<long long>(rem)) - 1;
-      const int id = __shfl(myid, c0);
-      const unsigned long long sel = __ballot(myid == id) & 0xFFFFull;
-      const bool use = (sel >> col) & 1ull;
-      OP xb[KS];
-      load_x<BS, KS, QUAD>(x + (use ? qoff + static_cast<size_t>(row + o) * BS : 0), kq, use, xb);
-      const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(mw) * 64 * KS;
-      // MG row tiles at a time: their operands are loaded first and their
-      // independent accumulations interleaved, so no MFMA waits on the last
-#pragma unroll
-      for (int m0 = 0; m0 < MW; m0 += MG) {
-        OP a[MG][KS];
-#pragma unroll
-        for (int g = 0; g < MG; ++g)
-          if (m0 + g < MW) load_widen<TM, KS, OP>(bp + (m0 + g) * 64 * KS, lane, a[g]);
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-          for (int g = 0; g < MG; ++g)
-            if (m0 + g < MW) acc[m0 + g] = mfma_step(a[g][s], xb[s], acc[m0 + g]);
-      }
-      rem &= ~sel;
-    }
-  }
-  if (!rv) return;
-  const size_t rb = qoff + static_cast<size_t>(row) * BS;
+// the epilogue of k_bsr_tiled for one tile: out = alpha Y + beta z (and the
+// FP32 copy out2 when given) for the rows of block row rb / BS held by this
+// lane
+template <int BS, bool P32, int MW, typename OT, typename ACC>
+__device__ __forceinline__ void tiled_store(const ACC (&acc)[MW], size_t rb, int mw, int kq, OT* out,
+                                            const double* z, double alpha, double beta,
+                                            float* __restrict__ out2) {
   if constexpr (P32 && BS % 16 == 0) {
     // FP32 result layout: lane l holds rows 16 m + 4 (l/16) + i, four
     // consecutive entries per row tile: with 16-byte aligned out and z (a
@@ -710,6 +640,116 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
         if (out2) out2[rb + r] = static_cast<float>(v);
       }
     }
+}
+
+// P32: FP32 products (operands rounded to FP32: the stored FP32 / BF16 entries
+// exactly, the vector entries to nearest) accumulated in FP32; the result is
+// combined with z in FP64.  XT / OT: element type of x / out; FP32 x (already
+// rounded by its producer, so the same operand values) or FP32 out only with
+// FP32 products, one right-hand side and 16 | bs.  QUAD: the matrix is laid out
+// with the 4-step k mapping (required for FP32 x).  SPLIT: one wavefront per
+// row tile of a tile (MT wavefronts per tile, one right-hand side), for
+// matrices with too few tiles to fill the device; the products are the same.
+// NG: consecutive tiles per wavefront (1 or 2; 2 with FP32 products and one
+// right-hand side): a pass loads the block operands once and multiplies them
+// with the x columns of every tile (zero columns where a tile's rows do not
+// hold that block), halving the block loads per MFMA.
+template <typename TM, int BS, int LKP, bool P32, typename XT = double, typename OT = double, bool QUAD = false,
+          bool SPLIT = false, int NG = 1>
+__global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, const int* __restrict__ off,
+                                                        const int* __restrict__ tab,
+                                                        const int* __restrict__ perm,
+                                                        const TM* __restrict__ blk, const XT* x,
+                                                        const double* z, OT* out, double alpha,
+                                                        double beta, long long stride, int nk,
+                                                        float* __restrict__ out2) {
+  static_assert(std::is_same<XT, double>::value || (P32 && QUAD && BS % 16 == 0), "FP32 x: FP32 products, quad layout");
+  static_assert(!QUAD || BS % 16 == 0, "the quad layout needs 16 | bs");
+  static_assert(!SPLIT || LKP == 0, "one wavefront per row tile: one right-hand side");
+  static_assert(NG == 1 || (NG == 2 && P32 && !SPLIT && LKP == 0), "two tiles per wavefront: FP32 products, one vector");
+  constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
+  constexpr int MW = SPLIT ? 1 : MT;            // row tiles of this wavefront
+  constexpr int MG = SPLIT ? 1 : sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
+  using OP = typename std::conditional<P32, float, double>::type;
+  using ACC = typename std::conditional<P32, v4f, v4d>::type;
+  const int lane = threadIdx.x & 63;
+  // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous
+  // range of tiles so that neighbouring rows share its L2
+  const int nb = gridDim.x, n8 = nb >> 3;
+  const int b = blockIdx.x;
+  const int lb = b < 8 * n8 ? (b & 7) * n8 + (b >> 3) : b;
+  const int wv = lb * kWaves + (threadIdx.x >> 6);
+  const int tile = SPLIT ? wv / MT : wv * NG;
+  const int mw = SPLIT ? wv - tile * MT : 0;   // first row tile of this wavefront
+  const int e0 = tile * (16 >> LKP);        // 16 / kp block rows per tile
+  if (e0 >= nrows) return;                  // the whole wavefront; no barrier follows
+  const int col = lane & 15, kq = lane >> 4;
+  const int q = col & ((1 << LKP) - 1);     // right-hand side of this column
+  int rowg[NG];
+  bool rvg[NG];
+#pragma unroll
+  for (int h = 0; h < NG; ++h) {            // tile h of this wavefront
+    const int e = e0 + 16 * h + (col >> LKP);
+    const int pr = e < nrows ? perm[e] : -1;  // -1: a padded place of the tile order
+    rvg[h] = pr >= 0 && q < nk;
+    rowg[h] = rvg[h] ? pr : 0;
+  }
+  const size_t qoff = static_cast<size_t>(rvg[0] ? q : 0) * stride;
+  ACC acc[NG][MW];
+#pragma unroll
+  for (int h = 0; h < NG; ++h)
+#pragma unroll
+    for (int m = 0; m < MW; ++m) acc[h][m] = ACC{0, 0, 0, 0};
+  for (int d = 0; d < noff; ++d) {
+    const int o = off[d];
+    int myid[NG];
+    unsigned long long rem[NG], left = 0;
+#pragma unroll
+    for (int h = 0; h < NG; ++h) {
+      const int t = tab[static_cast<size_t>(rowg[h]) * noff + d];
+      myid[h] = rvg[h] ? t : -1;
+      rem[h] = __ballot(myid[h] >= 0) & 0xFFFFull;
+      left |= rem[h];
+    }
+    while (left) {                          // one MFMA pass per distinct block of this offset
+      int id = -1;
+#pragma unroll
+      for (int h = NG - 1; h >= 0; --h)      // a block not yet served, first tile first
+        if (rem[h]) id = __shfl(myid[h], __ffsll(static_cast<long long>(rem[h])) - 1);
+      OP xb[NG][KS];
+      left = 0;
+#pragma unroll
+      for (int h = 0; h < NG; ++h) {
+        const unsigned long long sel = __ballot(myid[h] == id) & 0xFFFFull;
+        const bool use = (sel >> col) & 1ull;
+        load_x<BS, KS, QUAD>(x + (use ? qoff + static_cast<size_t>(rowg[h] + o) * BS : 0), kq, use, xb[h]);
+        rem[h] &= ~sel;
+        left |= rem[h];
+      }
+      const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(mw) * 64 * KS;
+      // MG row tiles at a time: their operands are loaded first and their
+      // independent accumulations interleaved, so no MFMA waits on the last
+#pragma unroll
+      for (int m0 = 0; m0 < MW; m0 += MG) {
+        OP a[MG][KS];
+#pragma unroll
+        for (int g = 0; g < MG; ++g)
+          if (m0 + g < MW) load_widen<TM, KS, OP>(bp + (m0 + g) * 64 * KS, lane, a[g]);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+          for (int h = 0; h < NG; ++h)
+#pragma unroll
+            for (int g = 0; g < MG; ++g)
+              if (m0 + g < MW) acc[h][m0 + g] = mfma_step(a[g][s], xb[h][s], acc[h][m0 + g]);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < NG; ++h) {
+    if (rvg[h]) tiled_store<BS, P32, MW, OT>(acc[h], qoff + static_cast<size_t>(rowg[h]) * BS, mw, kq, out, z,
+                                             alpha, beta, out2);
+  }
 }
 
 // pooled blocks (row-major FP64) -> the operand layout of k_bsr_tiled
@@ -1235,13 +1275,22 @@ void launch_tiled_bs(const BsrArgs<TM, T>& a, long long stride, int nk, hipStrea
                                     "for FP32 x, the quad layout");
       const long long tiles = (nt + 15) / 16;
       const bool split = tiles < kSplitTiles;
-      const int blocks = static_cast<int>((tiles * (split ? MT : 1) + kWaves - 1) / kWaves);
+      // FP32 blocks of a matrix that asks for it: two tiles per wavefront (one
+      // load of a pass's blocks for both) where that still leaves two
+      // wavefronts per SIMD; BF16 blocks are half the load and keep one
+      constexpr bool kPair = std::is_same<TM, float>::value;
+      const int per = kPair && a.tpair && tiles >= kPairTiles ? 2 : 1;   // tiles per wavefront
+      const int blocks = static_cast<int>(((split ? tiles * MT : (tiles + per - 1) / per) + kWaves - 1) / kWaves);
       if (blocks == 0) return;
 #define TILED32(XT_, OT_, Q_, X_, O_)                                                                          \
   if (split)                                                                                                   \
     k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_, true><<<blocks, kThreads, 0, st>>>(                             \
         nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1, a.out2);                  \
-  else                                                                                                         \
+  else if (per == 2) {                                                                                         \
+    if constexpr (kPair)                                                                                       \
+      k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_, false, 2><<<blocks, kThreads, 0, st>>>(                       \
+          nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1, a.out2);                \
+  } else                                                                                                       \
     k_bsr_tiled<TM, BS, 0, true, XT_, OT_, Q_><<<blocks, kThreads, 0, st>>>(                                   \
         nt, a.noff, a.toff, a.tab, a.tperm, a.tblk, X_, a.z, O_, a.alpha, a.beta, 0, 1, a.out2);
       if (a.x32 && a.out32) {

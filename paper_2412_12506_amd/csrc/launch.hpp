@@ -55,6 +55,8 @@ struct BsrArgs {
   int noff = 0;
   bool p32 = false;           // tiled storage: FP32 products on the matrix cores
   bool tquad = false;         // the tiled pool uses the 4-step k mapping (16 | bs; required for x32)
+  bool tpair = false;         // FP32 blocks, FP32 vectors: two tiles per wavefront on large levels (set for the
+                              // operator, whose FP32 block loads it halves; the smoother is faster with one)
   const float* x32 = nullptr; // with p32, one right-hand side and 16 | bs: FP32 input in place of x
   float* out2 = nullptr;      // tiled: an FP32 copy of out (rounded to nearest), or null
   float* out32 = nullptr;     // ... or FP32 output in place of out

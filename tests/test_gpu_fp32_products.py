@@ -276,3 +276,112 @@ def test_headline_path_fine_level_n12():
             assert worst <= 1.0, (op, worst)
     finally:
         s.close()
+
+
+def _dense_round(B, how):
+    return (round_bf16 if how == "bf16" else round_fp32)(B).toarray()
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_headline_path_fine_level_sampled(n):
+    """The benchmark's launch configurations at sizes the oracle cannot
+    assemble whole, 3D Q_3 with BF16 SAI, tiled storage and FP32 products:
+    32^3 (32,768 block rows, over 2,048 tiles: the unsplit tiled launches, one
+    tile per wavefront) and 64^3 (262,144 block rows: two tiles per wavefront
+    for the FP32 A, the benchmark's own grid), both in the XCD tile order with
+    padded tiles.  Sampled rows
+    (corners, edges, faces, random) of the residual, apply_s, apply_st and
+    both smoothing steps (whose residual is the FP32-x, FP32-out launch)
+    against the oracle's local rows and local least-squares SAI columns,
+    rounded as stored, within the bounds of test_level_operations; then a CG
+    solve with FP32 products takes the iterations of FP64 products (+-1) to a
+    true FP64 residual <= 2e-10."""
+    from paper_2412_12506_amd import ldgmg as L
+    from oracle.local import LocalOperator
+    dim, p = 3, 3
+    bs = (p + 1) ** dim
+    lo = LocalOperator(dim, n, p)
+    s = L.Solver(dim=dim, n=n, p=p, smoother="sai", precision="bf16s", storage="tiled", fp32_products=True)
+    try:
+        st = L.ldgmg_level_storage(s.handle, 0)
+        assert st["tiled_A"] and st["tiled_S"], st
+        ne = lo.grid.ne
+        rng = np.random.default_rng(2000 + n)
+        rows = sorted({0, n - 1, n * n - 1, ne - 1, n // 2, n * n // 2 + 3, ne // 2 + n // 2 + 1,
+                       *rng.choice(ne, 6, replace=False).tolist()})
+        N = ne * bs
+        x, b = rng.standard_normal(N), rng.standard_normal(N)
+        xv, bv = x.reshape(-1, bs), b.reshape(-1, bs)
+        xt, bt = torch.from_numpy(x).cuda(), torch.from_numpy(b).cuda()
+        outs = {}
+        for op in ("residual", "apply_s", "apply_st", "smooth_fwd", "smooth_rev"):
+            out = torch.empty_like(xt)
+            L.ldgmg_level_op(s.handle, 0, op, xt, bt if op in ("residual", "smooth_fwd", "smooth_rev") else None, out)
+            torch.cuda.synchronize()
+            outs[op] = out.cpu().numpy().reshape(-1, bs)
+        arows, acache, scols = {}, {}, {}
+
+        def arow(K):                        # {J: A_KJ}, FP32 as stored
+            if K not in arows:
+                arows[K] = {J: _dense_round(B, "fp32") for J, B in lo.row(K).items()}
+            return arows[K]
+
+        def ax(K):                          # (A x)_K, (|A||x|)_K, terms per row
+            if K not in acache:
+                blocks = arow(K)
+                acache[K] = (sum(B @ xv[J] for J, B in blocks.items()),
+                             sum(np.abs(B) @ np.abs(xv[J]) for J, B in blocks.items()), bs * len(blocks))
+            return acache[K]
+
+        def scol(J):                        # {I: S_IJ}, BF16 as stored
+            if J not in scols:
+                scols[J] = {I: _dense_round(B, "bf16") for I, B in lo.sai_column(J, 1).items()}
+            return scols[J]
+
+        worst = {}
+        for K in rows:
+            AxK, absK, nA = ax(K)
+            err = np.abs((bv[K] - outs["residual"][K]) - AxK)
+            w = float(np.max(err / np.maximum((nA + 3) * U32 * absK, 1e-300)))
+            worst["residual"] = max(worst.get("residual", 0.0), w)
+            assert w <= 1.0, ("residual", K, w)
+            srow = {J: scol(J)[K] for J in arow(K)}          # row K of S (the pattern of A is symmetric)
+            ref_s = sum(B @ xv[J] for J, B in srow.items())
+            mag_s = sum(np.abs(B) @ np.abs(xv[J]) for J, B in srow.items())
+            nS = bs * len(srow)
+            w = float(np.max(np.abs(outs["apply_s"][K] - ref_s) / np.maximum((nS + 3) * U32 * mag_s, 1e-300)))
+            worst["apply_s"] = max(worst.get("apply_s", 0.0), w)
+            assert w <= 1.0, ("apply_s", K, w)
+            stcol = scol(K)                                   # row K of S^T = column K of S
+            ref_t = sum(B.T @ xv[I] for I, B in stcol.items())
+            mag_t = sum(np.abs(B.T) @ np.abs(xv[I]) for I, B in stcol.items())
+            nT = bs * len(stcol)
+            w = float(np.max(np.abs(outs["apply_st"][K] - ref_t) / np.maximum((nT + 3) * U32 * mag_t, 1e-300)))
+            worst["apply_st"] = max(worst.get("apply_st", 0.0), w)
+            assert w <= 1.0, ("apply_st", K, w)
+            for op, Mrow in (("smooth_fwd", srow), ("smooth_rev", {I: B.T for I, B in stcol.items()})):
+                ref = xv[K].copy()
+                bound = np.zeros(bs)
+                nM = bs * len(Mrow)
+                for J, B in Mrow.items():
+                    AxJ, absJ, nAJ = ax(J)
+                    ref += B @ (bv[J] - AxJ)
+                    bound += (nM + 3) * U32 * (np.abs(B) @ (np.abs(bv[J]) + absJ))
+                    bound += np.abs(B) @ ((nAJ + 3) * U32 * absJ)
+                w = float(np.max(np.abs(outs[op][K] - ref) / np.maximum(bound, 1e-300)))
+                worst[op] = max(worst.get(op, 0.0), w)
+                assert w <= 1.0, (op, K, w)
+        print(f"  {n}^3 sampled rows " + ", ".join(f"{k} {v:.3f}" for k, v in worst.items()), flush=True)
+        b = torch.from_numpy(rhs_normal(N, 7)).cuda()
+        its = {}
+        for fp32p in (False, True):
+            L.ldgmg_fp32_products(s.handle, fp32p)
+            xs = torch.empty_like(b)
+            info = L.ldgmg_solve(s.handle, b, xs, "cg", 1e-10, 100)
+            torch.cuda.synchronize()
+            assert info["converged"] and info["rel_res_true"] <= 2e-10, (fp32p, info)
+            its[fp32p] = info["iters"]
+        assert abs(its[True] - its[False]) <= 1, its
+        print(f"  {n}^3 CG iterations: FP64 products {its[False]}, FP32 products {its[True]}", flush=True)
+    finally:
+        s.close()
