@@ -237,9 +237,15 @@ int ldgmg_cg_graph(ldgmg_handle h, int check_every);
  * prolongation keep an FP32 copy of the iterate beside it, which the operator
  * applies read (the same operand values as rounding the FP64 iterate): two
  * per-level buffers that ldgmg_upload allocates for such levels whether or not
- * this mode is on (N * 8 bytes, counted by ldgmg_upload_bytes).  Off by
- * default; needs FP32 or BF16S precision (LDGMG_EINVAL otherwise).  Kept
- * across ldgmg_unload / ldgmg_upload. */
+ * this mode is on (N * 8 bytes, counted by ldgmg_upload_bytes).  Where a BF16
+ * smoother matrix (BF16S precision, 32 | bs) reads that FP32 residual, its
+ * products run on the BF16 matrix cores instead: each FP32 entry is split
+ * exactly into three BF16 parts (hi + mid + lo, by truncation), so every
+ * product of a stored BF16 entry and a part is exact and the sums are FP32, as
+ * on the FP32 matrix cores (a different summation order, the same error
+ * bound up to the count of summed terms).  Off by default; needs FP32 or BF16S
+ * precision (LDGMG_EINVAL otherwise).  Kept across ldgmg_unload /
+ * ldgmg_upload. */
 int ldgmg_fp32_products(ldgmg_handle h, int enable);
 
 /* Device bytes the handle holds now (0 when it holds no device data): what

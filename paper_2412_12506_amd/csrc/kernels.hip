@@ -493,6 +493,10 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
 // entries per 16-byte group of the pool layout
 template <typename TM>
 __host__ __device__ constexpr int tile_vec(int KS) {
@@ -531,6 +535,35 @@ __device__ __forceinline__ v4d mfma_step(double a, double b, v4d c) {
 }
 __device__ __forceinline__ v4f mfma_step(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// FP32 x split exactly into three BF16 parts, x = hi + mid + lo: hi keeps the
+// top 8 significand bits (truncated), mid the next 8 of the remainder, lo the
+// last 8 (the remainders are exact in FP32 and lo fits a BF16 exactly).  Each
+// group of 8 steps 8c .. 8c+7 becomes one 8-element operand per part.
+template <int KS>
+__device__ __forceinline__ void split_bf16x3(const float (&f)[KS], v8bf (&xs)[3][KS / 8]) {
+#pragma unroll
+  for (int c = 0; c < KS / 8; ++c) {
+    unsigned w[3][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float v = f[8 * c + e];
+      const unsigned uh = __float_as_uint(v) & 0xFFFF0000u;
+      const float r1 = v - __uint_as_float(uh);
+      const unsigned um = __float_as_uint(r1) & 0xFFFF0000u;
+      const float r2 = r1 - __uint_as_float(um);
+      w[0][e] = uh;
+      w[1][e] = um;
+      w[2][e] = __float_as_uint(r2);
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const v4u p{(w[t][0] >> 16) | (w[t][1] & 0xFFFF0000u), (w[t][2] >> 16) | (w[t][3] & 0xFFFF0000u),
+                  (w[t][4] >> 16) | (w[t][5] & 0xFFFF0000u), (w[t][6] >> 16) | (w[t][7] & 0xFFFF0000u)};
+      xs[t][c] = __builtin_bit_cast(v8bf, p);
+    }
+  }
 }
 
 // the KS operands of the x block at xp for k lane kq (zero when !use), in the
@@ -672,6 +705,8 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
   constexpr int MG = SPLIT ? 1 : sizeof(TM) == 8 ? 1 : 4;   // row tiles whose operands are held at once
   using OP = typename std::conditional<P32, float, double>::type;
   using ACC = typename std::conditional<P32, v4f, v4d>::type;
+  // BF16 blocks times FP32 x on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16)
+  constexpr bool BFX = std::is_same<TM, bf16s>::value && std::is_same<XT, float>::value && QUAD && KS % 8 == 0;
   const int lane = threadIdx.x & 63;
   // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous
   // range of tiles so that neighbouring rows share its L2
@@ -727,6 +762,30 @@ __global__ __launch_bounds__(kThreads) void k_bsr_tiled(int nrows, int noff, con
         left |= rem[h];
       }
       const TM* bp = blk + static_cast<size_t>(id) * (MT * 64 * KS) + static_cast<size_t>(mw) * 64 * KS;
+      if constexpr (BFX) {
+        // BF16 blocks and FP32 x: a 16-byte pool group holds a lane's steps
+        // 8c .. 8c+7 and is the block operand as stored; x enters as its three
+        // exact BF16 parts, so every product is exact and the sums are FP32
+        v8bf ab[MW][KS / 8];
+        const v4u* g4 = reinterpret_cast<const v4u*>(bp) + lane;
+#pragma unroll
+        for (int m = 0; m < MW; ++m)
+#pragma unroll
+          for (int c = 0; c < KS / 8; ++c) ab[m][c] = __builtin_bit_cast(v8bf, g4[(m * (KS / 8) + c) * 64]);
+#pragma unroll
+        for (int h = 0; h < NG; ++h) {
+          v8bf xs[3][KS / 8];
+          split_bf16x3<KS>(xb[h], xs);
+#pragma unroll
+          for (int c = 0; c < KS / 8; ++c)
+#pragma unroll
+            for (int t = 2; t >= 0; --t)
+#pragma unroll
+              for (int m = 0; m < MW; ++m)
+                acc[h][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[m][c], xs[t][c], acc[h][m], 0, 0, 0);
+        }
+        continue;
+      }
       // MG row tiles at a time: their operands are loaded first and their
       // independent accumulations interleaved, so no MFMA waits on the last
 #pragma unroll

@@ -9,7 +9,9 @@ the FP64 vectors in FP64.  Tolerances, from that arithmetic:
     from an FP32-rounded input is within (n + 3) u32 (|M||x|)_i of the FP64
     product of the stored matrix (u32 = 2^-24: n - 1 sums, the products, the
     input rounding, and one unit for a stored entry that the two independent
-    setups round to neighbouring FP32 values);
+    setups round to neighbouring FP32 values); in a smoothing step whose BF16
+    B reads the FP32 residual (32 | bs) the residual is split exactly into
+    three BF16 parts, each product exact, so n becomes 3n for that apply;
   * V-cycle: against the oracle's V-cycle with FP32 products
     (tests/gpu_common.fp32_products_vcycle; the same roundings, another
     summation order) within 1e-4 relative: each apply agrees to n u32 <= 3e-5
@@ -62,6 +64,13 @@ def built(request):
     s.close()
 
 
+def _split_terms(prec, bs):
+    """Summed terms per stored entry in a smoothing step's B apply: 3 where a
+    BF16 B meets the FP32 residual on the BF16 matrix cores (the residual split
+    exactly into three BF16 parts; 32 | bs), else 1."""
+    return 3 if prec == "bf16s" and bs % 32 == 0 else 1
+
+
 def _check_rows(y, ref, M, x, what):
     """Entry-wise FP32-product bound; M is the stored matrix (FP64 values)."""
     M = M.tocsr()
@@ -101,7 +110,8 @@ def test_level_operations(built):
         # FP32 products; entry-wise first-order bound from both products
         nA, nS = np.diff(A.tocsr().indptr), np.diff(S.tocsr().indptr)
         absAx = abs(A) @ np.abs(x)
-        for op, M, n in (("smooth_fwd", S, nS), ("smooth_rev", S.T.tocsr(), np.diff(S.T.tocsr().indptr))):
+        ks = _split_terms(prec, s.bs)
+        for op, M, n in (("smooth_fwd", S, ks * nS), ("smooth_rev", S.T.tocsr(), ks * np.diff(S.T.tocsr().indptr))):
             L.ldgmg_level_op(s.handle, l, op, xt, bt, out)
             torch.cuda.synchronize()
             ref = x + M @ (b - A @ x)
@@ -268,7 +278,7 @@ def test_headline_path_fine_level_n12():
         for op, M in (("smooth_fwd", S.tocsr()), ("smooth_rev", S.T.tocsr())):
             L.ldgmg_level_op(s.handle, 0, op, xt, bt, out)
             torch.cuda.synchronize()
-            nM = np.diff(M.indptr)
+            nM = _split_terms("bf16s", bs) * np.diff(M.indptr)
             ref = x + M @ (b - A @ x)
             bound = (nM + 3) * U32 * (abs(M) @ (np.abs(b) + absAx)) + abs(M) @ ((nA + 3) * U32 * absAx)
             worst = float(np.max(np.abs(out.cpu().numpy() - ref) / np.maximum(bound, 1e-300)))
@@ -362,7 +372,7 @@ def test_headline_path_fine_level_sampled(n):
             for op, Mrow in (("smooth_fwd", srow), ("smooth_rev", {I: B.T for I, B in stcol.items()})):
                 ref = xv[K].copy()
                 bound = np.zeros(bs)
-                nM = bs * len(Mrow)
+                nM = _split_terms("bf16s", bs) * bs * len(Mrow)
                 for J, B in Mrow.items():
                     AxJ, absJ, nAJ = ax(J)
                     ref += B @ (bv[J] - AxJ)
