@@ -167,9 +167,11 @@ def time_solves(L, torch, args, s, precision, label, rhs, prof, setup_s, fp32_pr
 
 
 def kernel_source(kernel):
-    """Source text of a kernel family in kernels.hip (what the counter
-    summaries are keyed on): the forward kernels (k_bsr_fwd and its
-    multi-right-hand-side form) or the tiled kernel with its layout helpers."""
+    """Code of a kernel family in kernels.hip (what the counter summaries are
+    keyed on): the forward kernels (k_bsr_fwd and its multi-right-hand-side
+    form) or the tiled kernel with its layout helpers, with // comments,
+    trailing blanks and empty lines removed (edits of comments alone keep the
+    key)."""
     src = open(os.path.join(ROOT, "paper_2412_12506_amd", "csrc", "kernels.hip")).read()
     sep = "// ---------------------------------------------------------------------------\n"
     if kernel == "tiled":
@@ -178,7 +180,8 @@ def kernel_source(kernel):
     else:
         a = src.rindex("template <", 0, src.index("void k_bsr_fwd("))
         b = src.index(sep + "// transposed BSR kernel")
-    return src[a:b]
+    lines = (line.split("//", 1)[0].rstrip() for line in src[a:b].splitlines())
+    return "\n".join(line for line in lines if line) + "\n"
 
 
 def counter_traffic(storage="expanded"):

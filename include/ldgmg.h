@@ -240,10 +240,11 @@ int ldgmg_cg_graph(ldgmg_handle h, int check_every);
  * this mode is on (N * 8 bytes, counted by ldgmg_upload_bytes).  Where a BF16
  * smoother matrix (BF16S precision, 32 | bs) reads that FP32 residual, its
  * products run on the BF16 matrix cores instead: each FP32 entry is split
- * exactly into three BF16 parts (hi + mid + lo, by truncation), so every
- * product of a stored BF16 entry and a part is exact and the sums are FP32, as
- * on the FP32 matrix cores (a different summation order, the same error
- * bound up to the count of summed terms).  Off by default; needs FP32 or BF16S
+ * into three BF16 parts (hi + mid + lo, by truncation; exact for entries of
+ * magnitude at least 2^-103, below that the last part loses less than 2^-133),
+ * so every product of a stored BF16 entry and a part is exact and the sums are
+ * FP32, as on the FP32 matrix cores (a different summation order; the error
+ * bound counts 3n summed terms in place of n).  Off by default; needs FP32 or BF16S
  * precision (LDGMG_EINVAL otherwise).  Kept across ldgmg_unload /
  * ldgmg_upload. */
 int ldgmg_fp32_products(ldgmg_handle h, int enable);

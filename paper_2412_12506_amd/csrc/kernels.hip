@@ -537,9 +537,10 @@ __device__ __forceinline__ v4f mfma_step(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// FP32 x split exactly into three BF16 parts, x = hi + mid + lo: hi keeps the
-// top 8 significand bits (truncated), mid the next 8 of the remainder, lo the
-// last 8 (the remainders are exact in FP32 and lo fits a BF16 exactly).  Each
+// FP32 x split into three BF16 parts, x = hi + mid + lo: hi keeps the top 8
+// significand bits (truncated), mid the next 8 of the remainder, lo the last 8
+// (the remainders are exact in FP32 and lo fits a BF16 exactly when
+// |x| >= 2^-103; below that lo may be subnormal and loses under 2^-133).  Each
 // group of 8 steps 8c .. 8c+7 becomes one 8-element operand per part.
 template <int KS>
 __device__ __forceinline__ void split_bf16x3(const float (&f)[KS], v8bf (&xs)[3][KS / 8]) {

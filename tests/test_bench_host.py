@@ -25,10 +25,28 @@ def test_counter_traffic_follows_the_kernel_source(storage, monkeypatch):
     import bench
     t = bench.counter_traffic(storage)
     assert t is None or t > 0
-    # any change of the kernel source makes the summary stale
+    # any change of the kernel code makes the summary stale
     real = bench.kernel_source
-    monkeypatch.setattr(bench, "kernel_source", lambda k: real(k) + "// changed\n")
+    monkeypatch.setattr(bench, "kernel_source", lambda k: real(k) + "int changed;\n")
     assert bench.counter_traffic(storage) is None
+
+
+def test_kernel_source_ignores_comments(tmp_path, monkeypatch):
+    """The key is the code: comments, trailing blanks and empty lines do not
+    change it; a changed statement does."""
+    import bench
+    src = open(os.path.join(ROOT, "paper_2412_12506_amd", "csrc", "kernels.hip")).read()
+    root = tmp_path / "repo"
+    (root / "paper_2412_12506_amd" / "csrc").mkdir(parents=True)
+    f = root / "paper_2412_12506_amd" / "csrc" / "kernels.hip"
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    f.write_text(src)
+    base = {k: bench.kernel_source(k) for k in ("tiled", "fwd")}
+    at = src.index("__global__", src.index("// tiled forward BSR kernel"))
+    f.write_text(src[:at] + "// a new comment line\n\n" + src[at:].replace("{\n", "{   // trailing note\n", 1))
+    assert {k: bench.kernel_source(k) for k in ("tiled", "fwd")} == base
+    f.write_text(src[:at] + "static int changed;\n" + src[at:])
+    assert bench.kernel_source("tiled") != base["tiled"]
 
 
 def test_committed_counter_summaries_are_consistent():
