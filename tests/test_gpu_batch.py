@@ -1,7 +1,7 @@
 """Batched serving step: k right-hand sides of one hierarchy solved together
 (every matrix block streamed once per batch).  Each right-hand side must match
 the oracle exactly as a single solve does (iterations +-1, solution within
-1e-8), and the batched V-cycle must equal k single V-cycles to rounding
+1e-9 relative in FP64 mode and 1e-8 with FP32 / BF16 storage), and the batched V-cycle must equal k single V-cycles to rounding
 (same arithmetic, summation order aside: 1e-12 relative)."""
 import numpy as np
 import pytest
@@ -71,7 +71,10 @@ def test_solve_batch_matches_oracle(built):
         assert infos[q]["converged"] and ref.converged
         assert abs(infos[q]["iters"] - ref.iters) <= 1, (q, infos[q]["iters"], ref.iters)
         x = xs[q].cpu().numpy()
-        assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+        # the solution tolerance of the single solves (tests/test_gpu_parity.py):
+        # 1e-9 relative in FP64 mode, 1e-8 with FP32 / BF16 storage
+        rel = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+        assert rel <= (1e-9 if prec == "fp64" else 1e-8), (q, prec, rel)
         assert infos[q]["rel_res_true"] <= 2e-10
         # the same right-hand side alone gives the same iterations
         xa = torch.empty_like(bs[q])
