@@ -395,3 +395,51 @@ def test_headline_path_fine_level_sampled(n):
         print(f"  {n}^3 CG iterations: FP64 products {its[False]}, FP32 products {its[True]}", flush=True)
     finally:
         s.close()
+
+
+def test_stokes3d_q1_bs32_bf16_core_smoothing():
+    """Block size 32 (3D stress-form Stokes, Q_1: 4 x 8 unknowns per element),
+    the other block size with 32 | bs: BF16 SAI, tiled storage, FP32 products.
+    Its smoothing steps read the FP32 residual into the BF16-core apply with a
+    single 32-wide k group; both steps entry by entry against the oracle's
+    matrices (rounded as stored) within the bounds of test_level_operations,
+    and the V-cycle within 1e-4 of the FP32-product emulation."""
+    from paper_2412_12506_amd import ldgmg as L
+    case = dict(id="s3d-p1-stress-sai1", dim=3, n=4, p=1, system="stokes", gamma=1, smoother="sai")
+    lv, vc = oracle_build(case)
+    s = L.Solver(storage="tiled", fp32_products=True, **lib_kwargs(case, "bf16s"))
+    try:
+        assert s.bs == 32, s.bs
+        st = L.ldgmg_level_storage(s.handle, 0)
+        assert st["tiled_A"] and st["tiled_S"], st
+        A = round_fp32(vc.levels[0].A)
+        S = round_bf16(smoother_matrix(vc, 0))
+        rng = np.random.default_rng(32)
+        N = A.shape[0]
+        x, b = rng.standard_normal(N), rng.standard_normal(N)
+        xt, bt = torch.from_numpy(x).cuda(), torch.from_numpy(b).cuda()
+        out = torch.empty_like(xt)
+        nA = np.diff(A.tocsr().indptr)
+        absAx = abs(A) @ np.abs(x)
+        ks = _split_terms("bf16s", s.bs)
+        assert ks == 3
+        for op, M in (("smooth_fwd", S.tocsr()), ("smooth_rev", S.T.tocsr())):
+            L.ldgmg_level_op(s.handle, 0, op, xt, bt, out)
+            torch.cuda.synchronize()
+            n = ks * np.diff(M.indptr)
+            ref = x + M @ (b - A @ x)
+            bound = (n + 3) * U32 * (abs(M) @ (np.abs(b) + absAx)) + abs(M) @ ((nA + 3) * U32 * absAx)
+            worst = float(np.max(np.abs(out.cpu().numpy() - ref) / np.maximum(bound, 1e-300)))
+            print(f"  bs=32 {op}: worst error / bound {worst:.3f}", flush=True)
+            assert worst <= 1.0, (op, worst)
+        bv = rhs_normal(N, 9)
+        bvt = torch.from_numpy(bv).cuda()
+        xv = torch.empty_like(bvt)
+        L.ldgmg_vcycle(s.handle, bvt, xv)
+        torch.cuda.synchronize()
+        ref = fp32_products_vcycle(vc, "bf16s").apply(bv)
+        err = np.linalg.norm(xv.cpu().numpy() - ref) / np.linalg.norm(ref)
+        print(f"  bs=32 V-cycle relative difference {err:.2e}", flush=True)
+        assert err <= 1e-4
+    finally:
+        s.close()
